@@ -1,0 +1,23 @@
+"""FP64 CPU oracle for guided-filter non-blind deconvolution (Yang, Zhu, Zhang, Huang).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The GPU library never
+calls it and shares no code with it.
+
+Everything here is plain NumPy in float64 / complex128, written step by step from
+the paper; each function names the passage it follows.  The 2-D DFT is the one
+library primitive used (``numpy.fft``); everything around it is spelled out.
+
+Readings of passages that are silent or ambiguous (periodic boundaries, the
+discretised gradient, Parseval normalisation, the lambda bracket, the tie at the
+infinite-lambda branch, ...) are stated next to the code that takes them.
+
+Parity status: every function here is pinned by CPU tests against closed forms,
+brute force or invariants, except the multi-iteration trajectory, which has no
+closed form; its parity is pinned only through its components and invariants.
+"""
+from .gfd import (  # noqa: F401
+    dft2, idft2, embed_psf, grad_symbol, rho_eq12, Setup, setup, residual_energy,
+    discrepancy_lambda, spectral_solve, box_mean, guided_filter, StepResult, step,
+    deconvolve, isnr, FLAG_INF_BRANCH, FLAG_NO_ROOT,
+)
