@@ -1,0 +1,148 @@
+/*
+ * gfdeconv.h -- C ABI of the MI355X (gfx950) guided-filter non-blind deconvolution library.
+ *
+ * Method: Yang, Zhu, Zhang, Huang, "Guided Filter based Edge-preserving Image Non-blind
+ * Deconvolution".  The observation model is y = h * u + gamma with white Gaussian noise of
+ * variance sigma^2 (Sec. 1, Eq.(1)).  Each iteration (Sec. 3.1, Steps 1-3) chooses lambda by the
+ * discrepancy principle (Sec. 3.2, Eqs.(10)-(12)), solves the two Fourier-domain least-squares
+ * problems (Eqs.(8)-(9)) for the guidance image u_I and the filtering input u_p, and applies the
+ * guided filter u = guidfilter(u_I, u_p, w, eps) (Sec. 2, Eqs.(3)-(5)) to get the next estimate.
+ *
+ * Conventions shared by every entry point:
+ *  - Images are M rows x N columns of contiguous row-major float32 (pitch N), P = M*N.
+ *  - Pointers named *_dev or documented as device pointers are device memory on the current
+ *    HIP device; they are owned by the caller and must stay valid until the stream has passed
+ *    the call.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Calls are stream-ordered and asynchronous unless stated otherwise.
+ *  - Boundaries are periodic everywhere: the blur is a circular convolution and the guided
+ *    filter's w x w windows wrap around the image edges.
+ *  - Sizes: M and N are products of powers of 2, 3 and 5, each in [2, 4096].
+ *  - Arguments are checked before anything is enqueued.  On error a negative status is
+ *    returned, a message is stored for gfd_last_error() (per thread) and nothing is written.
+ *  - Conditions that arise on the device (NaN input, lambda clamped at its floor, the
+ *    lambda = +inf branch) are recorded as flags read with deconv_get_status().
+ */
+#ifndef GFDECONV_H
+#define GFDECONV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gfd_ctx gfd_ctx; /* opaque, library-owned; bound to the device current at init */
+typedef int gfd_status;
+
+enum {
+  GFD_OK = 0,
+  GFD_ERR_ARG = -1,           /* invalid argument (NULL pointer, w even, eps < 0, ...) */
+  GFD_ERR_SIZE = -2,          /* unsupported image or PSF size */
+  GFD_ERR_HIP = -3,           /* a HIP runtime call failed */
+  GFD_ERR_NOMEM = -4,         /* device allocation failed */
+  GFD_ERR_STATE = -5,         /* context destroyed, foreign, or not usable for this call */
+  GFD_ERR_UNIMPLEMENTED = -6  /* valid request outside what this build supports */
+};
+
+/* Device-side condition flags (deconv_get_status). */
+enum {
+  GFD_FLAG_INF_BRANCH = 1u, /* some iteration found u_E in K and used lambda = +inf (Sec. 3.2) */
+  GFD_FLAG_NO_ROOT = 2u,    /* some iteration clamped lambda at its floor (no root of Eq.(11)) */
+  GFD_FLAG_NONFINITE = 4u   /* a non-finite value reached a reduction (NaN/Inf in the data) */
+};
+
+/*
+ * deconv_init -- per-image set-up (Sec. 3.1 Step 0, plus the transforms the solves need).
+ *   y      device, M x N float32: the observation of Eq.(1).
+ *   h      device, kh x kw float32, row-major, odd kh <= M and kw <= N: the PSF, centred at
+ *          (kh/2, kw/2); it is embedded periodically so that entry (i, j) acts at offset
+ *          (i - kh/2, j - kw/2).  Its sum must be non-zero (the solve for u_I divides by F(h) at
+ *          the zero frequency).
+ *   sigma2 noise variance, >= 0 (on the same intensity scale as y).
+ *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N)) and regulariser (>= 0, finite).
+ *   rho    discrepancy factor of the set K (Sec. 3.2), 0 < rho <= 1; rho <= 0 selects Eq.(12).
+ * The estimate starts at u_E = 0 (Step 0).  Allocates device memory; synchronises `stream`
+ * once at the end so that *out is ready.  *out is untouched on error.
+ */
+gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float *h, int kh, int kw,
+                       double sigma2, int w, float eps, double rho, void *stream);
+
+/*
+ * deconv_iterate -- run n_iter iterations of Steps 1-3 (Sec. 3.1) from the current estimate.
+ *   u_out       device M x N or NULL: receives the estimate after the last iteration.
+ *   lambda_out  device, n_iter floats, or NULL: the lambda used at each iteration
+ *               (scale * lambda_star), +inf where the Sec. 3.2 branch u_E in K was taken.
+ * The whole iteration runs on the device with no host round trip; one iteration is captured
+ * once into a HIP graph and replayed.  Iterating in chunks gives the same result as one call.
+ */
+gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_out, void *stream);
+
+/*
+ * guided_filter -- u = guidfilter(u_I, u_p, w, eps), Sec. 2 Eqs.(3)-(5); context-free.
+ *   uI (guidance), up (filtering input), u (output): device M x N float32; u must not alias
+ *   uI or up.  Windows are w x w (odd w, 1 <= w <= min(M, N)), wrap periodically, and every
+ *   mean divides by w^2.  M, N in [1, 65536] (no factorisation constraint here).
+ */
+gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
+                         void *stream);
+
+/*
+ * spectral_solve -- the two regularised least-squares solves, Eqs.(8)-(9), for a given
+ * pre-estimate and lambda, using the context's F(h), F(y) and gradient symbol.
+ *   uE device M x N (input), uI and up device M x N (outputs: gradient- and identity-
+ *   regularised solutions).  lambda > 0, or +inf for u_I = u_p = u_E.
+ */
+gfd_status spectral_solve(gfd_ctx *ctx, const float *uE, float lambda, float *uI, float *up,
+                          void *stream);
+
+/*
+ * discrepancy_lambda -- lambda_star for the pre-estimate uE by the discrepancy principle
+ * (Sec. 3.2, Eqs.(10)-(11)): +inf if ||h*uE - y||^2 <= rho*P*sigma^2, else the root of Eq.(11)
+ * (the floor value 1e-30 with GFD_FLAG_NO_ROOT if there is none).
+ *   uE device M x N (input); lambda_dev device, 1 float (output).  Does not change the
+ *   context's estimate or iteration count.
+ */
+gfd_status discrepancy_lambda(gfd_ctx *ctx, const float *uE, float *lambda_dev, void *stream);
+
+/*
+ * deconv_set_scales -- per-iteration lambda scales s_k (lambda_k = s_k * lambda_star_k),
+ * counted from the context's next iteration.  s_dev: device, n floats, copied (stream-ordered
+ * on the null stream, synchronously).  Iterations beyond n use scale 1.  n = 0 clears.
+ */
+gfd_status deconv_set_scales(gfd_ctx *ctx, const float *s_dev, int n);
+
+/* deconv_set_estimate -- replace the current estimate u_E (device M x N, copied). */
+gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream);
+
+/* deconv_reset -- back to Step 0: u_E = 0, iteration count 0, flags cleared. */
+gfd_status deconv_reset(gfd_ctx *ctx, void *stream);
+
+/* deconv_info -- host copies of rho, the target rho*P*sigma^2 and the iteration count. */
+gfd_status deconv_info(gfd_ctx *ctx, double *rho, double *target, int *iterations);
+
+/* deconv_get_status -- synchronises the context's work and returns the OR of device flags. */
+gfd_status deconv_get_status(gfd_ctx *ctx, unsigned *flags_host);
+
+/* deconv_set_graph -- 1 (default): deconv_iterate replays a captured HIP graph; 0: launches
+ * the same kernels one by one (same results, bitwise). */
+gfd_status deconv_set_graph(gfd_ctx *ctx, int use_graph);
+
+/*
+ * deconv_profile -- run n_iter iterations (exactly as deconv_iterate, advancing the estimate)
+ * launching the kernels one by one with HIP events between the passes, and return in
+ * stage_ms_host[0 .. n_stages) the summed device time of each pass, in this order:
+ *   0 row transform of u_E, 1 column transform + residual + first lambda candidates,
+ *   2 remaining lambda evaluation rounds, 3 solves (Eqs.(8)-(9)) + column inverse transforms,
+ *   4 row inverse transforms, 5 guided filter.
+ * n_stages <= 6; synchronises `stream` before returning.
+ */
+gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_stages, void *stream);
+
+/* deconv_destroy -- frees the context; NULL and already-destroyed contexts are ignored. */
+void deconv_destroy(gfd_ctx *ctx);
+
+/* gfd_last_error -- message of the last failing call on this thread ("" if none). */
+const char *gfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFDECONV_H */

@@ -1,0 +1,219 @@
+"""MI355X (gfx950) guided-filter non-blind deconvolution.
+
+Thin Python binding over ``libgfdeconv.so`` (declared in ``include/gfdeconv.h``).  Every step
+of the method runs in the library's HIP kernels; this module only checks tensor arguments,
+passes device pointers and the current HIP stream, and turns status codes into exceptions.
+PyTorch supplies device memory and streams.
+
+Method: Yang, Zhu, Zhang, Huang, "Guided Filter based Edge-preserving Image Non-blind
+Deconvolution" -- Sec. 3.1 (Steps 0-3, Eqs.(8)-(9)), Sec. 3.2 (Eqs.(10)-(12)), Sec. 2
+(Eqs.(3)-(5)).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = ["GFDError", "GFDeconv", "deconvolve", "guided_filter", "spectral_solve", "discrepancy_lambda",
+           "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libgfdeconv.so"
+_lib = None
+
+FLAG_INF_BRANCH, FLAG_NO_ROOT, FLAG_NONFINITE = 1, 2, 4
+_ERRNAMES = {-1: "GFD_ERR_ARG", -2: "GFD_ERR_SIZE", -3: "GFD_ERR_HIP", -4: "GFD_ERR_NOMEM", -5: "GFD_ERR_STATE",
+             -6: "GFD_ERR_UNIMPLEMENTED"}
+
+_vp, _i, _f, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
+# name -> (restype, argtypes)
+EXPORTS = {
+    "deconv_init": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _vp, _i, _i, _d, _i, _f, _d, _vp]),
+    "deconv_iterate": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "guided_filter": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
+    "spectral_solve": (_i, [_vp, _vp, _f, _vp, _vp, _vp]),
+    "discrepancy_lambda": (_i, [_vp, _vp, _vp, _vp]),
+    "deconv_set_scales": (_i, [_vp, _vp, _i]),
+    "deconv_set_estimate": (_i, [_vp, _vp, _vp]),
+    "deconv_reset": (_i, [_vp, _vp]),
+    "deconv_info": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i)]),
+    "deconv_get_status": (_i, [_vp, ctypes.POINTER(ctypes.c_uint)]),
+    "deconv_set_graph": (_i, [_vp, _i]),
+    "deconv_profile": (_i, [_vp, _i, ctypes.POINTER(_f), _i, _vp]),
+    "deconv_destroy": (None, [_vp]),
+    "gfd_last_error": (ctypes.c_char_p, []),
+}
+
+
+class GFDError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def load_library():
+    """Load the built HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_1609_01839_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GFDError(rc, load_library().gfd_last_error().decode())
+
+
+def _dev(t: torch.Tensor, name: str, shape=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor on the GPU")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class GFDeconv:
+    """One deconvolution problem bound to the current GPU (a library context).
+
+    ``y`` (M x N) and ``h`` (kh x kw, odd sides) are float32 GPU tensors; ``sigma2`` the noise
+    variance; ``w``, ``eps`` the guided-filter window and regulariser; ``rho=None`` takes
+    Eq.(12), otherwise 0 < rho <= 1.
+    """
+
+    def __init__(self, y: torch.Tensor, h: torch.Tensor, sigma2: float, w: int, eps: float, rho=None):
+        lib = load_library()
+        if y.dim() != 2 or h.dim() != 2:
+            raise ValueError("y and h must be 2-D")
+        self.M, self.N = (int(s) for s in y.shape)
+        self.device = y.device
+        self._y, self._h = y, h
+        ctx = _vp()
+        rc = lib.deconv_init(ctypes.byref(ctx), _dev(y, "y"), self.M, self.N, _dev(h, "h"), int(h.shape[0]),
+                             int(h.shape[1]), float(sigma2), int(w), float(eps), -1.0 if rho is None else float(rho),
+                             _stream(self.device))
+        _check(rc)
+        self._ctx = ctx
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            load_library().deconv_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        if self._ctx is None:
+            raise GFDError(-5, "context closed")
+        return self._ctx
+
+    # -- iteration
+    def iterate(self, n: int, out: torch.Tensor | None = None, lambdas: torch.Tensor | None = None):
+        """Run n iterations; returns (u, lambdas) as GPU tensors (allocated if not given)."""
+        out = torch.empty((self.M, self.N), device=self.device, dtype=torch.float32) if out is None else out
+        lambdas = torch.empty((max(n, 0),), device=self.device, dtype=torch.float32) if lambdas is None else lambdas
+        _check(load_library().deconv_iterate(self.handle, int(n), _dev(out, "out", (self.M, self.N)),
+                                             _dev(lambdas, "lambdas", (n,)) if n > 0 else None,
+                                             _stream(self.device)))
+        return out, lambdas
+
+    def set_scales(self, scales):
+        s = torch.as_tensor(scales, dtype=torch.float32, device=self.device).contiguous()
+        torch.cuda.synchronize(self.device)
+        _check(load_library().deconv_set_scales(self.handle, _dev(s, "scales") if s.numel() else None, s.numel()))
+
+    def set_estimate(self, uE: torch.Tensor):
+        _check(load_library().deconv_set_estimate(self.handle, _dev(uE, "uE", (self.M, self.N)), _stream(self.device)))
+
+    def reset(self):
+        _check(load_library().deconv_reset(self.handle, _stream(self.device)))
+
+    def set_graph(self, use_graph: bool):
+        _check(load_library().deconv_set_graph(self.handle, 1 if use_graph else 0))
+
+    def info(self):
+        rho, T, it = _d(), _d(), _i()
+        _check(load_library().deconv_info(self.handle, ctypes.byref(rho), ctypes.byref(T), ctypes.byref(it)))
+        return {"rho": rho.value, "target": T.value, "iterations": it.value}
+
+    def status(self) -> int:
+        f = ctypes.c_uint()
+        _check(load_library().deconv_get_status(self.handle, ctypes.byref(f)))
+        return f.value
+
+    STAGES = ("row_fwd", "col_fwd_resid", "lambda_sweeps", "col_inv_solve", "row_inv", "guided_filter")
+
+    def profile(self, n: int) -> dict:
+        """Run n iterations launching pass by pass; summed device milliseconds per pass."""
+        ms = (ctypes.c_float * 6)()
+        _check(load_library().deconv_profile(self.handle, int(n), ms, 6, _stream(self.device)))
+        return dict(zip(self.STAGES, list(ms)))
+
+    def spectral_solve(self, uE: torch.Tensor, lam: float):
+        return spectral_solve(self, uE, lam)
+
+    def discrepancy_lambda(self, uE: torch.Tensor):
+        return discrepancy_lambda(self, uE)
+
+
+def deconvolve(y, h, sigma2, w, eps, iters, rho=None, scales=None):
+    """Run ``iters`` iterations from u_E = 0; returns (u, lambdas) as GPU tensors."""
+    with GFDeconv(y, h, sigma2, w, eps, rho) as g:
+        if scales is not None:
+            g.set_scales(scales)
+        return g.iterate(iters)
+
+
+def guided_filter(uI: torch.Tensor, up: torch.Tensor, w: int, eps: float, out: torch.Tensor | None = None):
+    """u = guidfilter(u_I, u_p, w, eps) with periodic windows (Sec. 2, Eqs.(3)-(5))."""
+    M, N = (int(s) for s in uI.shape)
+    out = torch.empty_like(uI) if out is None else out
+    _check(load_library().guided_filter(_dev(uI, "uI"), _dev(up, "up", (M, N)), _dev(out, "out", (M, N)), M, N,
+                                        int(w), float(eps), _stream(uI.device)))
+    return out
+
+
+def spectral_solve(g: GFDeconv, uE: torch.Tensor, lam: float):
+    """(u_I, u_p) from Eqs.(8)-(9) for pre-estimate uE and a given lambda (+inf allowed)."""
+    uI = torch.empty((g.M, g.N), device=g.device, dtype=torch.float32)
+    up = torch.empty_like(uI)
+    _check(load_library().spectral_solve(g.handle, _dev(uE, "uE", (g.M, g.N)), float(lam), uI.data_ptr(),
+                                         up.data_ptr(), _stream(g.device)))
+    return uI, up
+
+
+def discrepancy_lambda(g: GFDeconv, uE: torch.Tensor):
+    """lambda_star for pre-estimate uE by the discrepancy principle (Sec. 3.2); 1-element GPU tensor."""
+    lam = torch.empty((1,), device=g.device, dtype=torch.float32)
+    _check(load_library().discrepancy_lambda(g.handle, _dev(uE, "uE", (g.M, g.N)), lam.data_ptr(),
+                                             _stream(g.device)))
+    return lam

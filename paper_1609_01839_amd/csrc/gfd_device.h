@@ -1,0 +1,110 @@
+// Device helpers shared by the gfx950 kernels: complex arithmetic, error-free sums,
+// wave/block reductions and cheap integer division by run-time constants.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gfd {
+
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+using cf = cpx<float>;
+using cd = cpx<double>;
+
+template <class T> __device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
+template <class T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <class T> __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <class T> __device__ __forceinline__ cpx<T> cscale(cpx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by -i (forward sign) or +i (inverse sign): DIR = -1 gives -i
+template <int DIR, class T> __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
+  return DIR < 0 ? cpx<T>{a.im, -a.re} : cpx<T>{-a.im, a.re};
+}
+// |z|^2 with one fixed evaluation order (callers that must agree bit for bit use this)
+__device__ __forceinline__ float abs2f(cf z) { return __fmaf_rn(z.re, z.re, __fmul_rn(z.im, z.im)); }
+
+// ---------------------------------------------------------------- error-free transformations
+// TwoSum (Knuth): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = __fadd_rn(a, b);
+  float bb = __fsub_rn(s, a);
+  e = __fadd_rn(__fsub_rn(a, __fsub_rn(s, bb)), __fsub_rn(b, bb));
+}
+// (hi, lo) += (bh, bl): compensated (double-float) accumulation.
+__device__ __forceinline__ void df_add(float &hi, float &lo, float bh, float bl) {
+  float s, e;
+  two_sum(hi, bh, s, e);
+  e = __fadd_rn(e, __fadd_rn(lo, bl));
+  hi = __fadd_rn(s, e);
+  lo = __fsub_rn(e, __fsub_rn(hi, s));
+}
+
+// ---------------------------------------------------------------- reductions
+// Compensated sum of NV (hi, lo) pairs over the whole block; result valid in thread 0.
+// `scratch` must hold 2 * NV * (blockDim.x / 64) floats.  Fixed order: deterministic.
+template <int NV>
+__device__ void block_reduce_df(float (&hi)[NV], float (&lo)[NV], float *scratch) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      float oh = __shfl_down(hi[v], off, 64);
+      float ol = __shfl_down(lo[v], off, 64);
+      df_add(hi[v], lo[v], oh, ol);
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      scratch[(wid * NV + v) * 2] = hi[v];
+      scratch[(wid * NV + v) * 2 + 1] = lo[v];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int v = 0; v < NV; ++v) {
+      float h = scratch[v * 2], l = scratch[v * 2 + 1];
+      for (int w = 1; w < nw; ++w) df_add(h, l, scratch[(w * NV + v) * 2], scratch[(w * NV + v) * 2 + 1]);
+      hi[v] = h;
+      lo[v] = l;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- integer division
+// Quotient of x / d for 0 <= x < 2^22 and 1 <= d < 2^22 using a float reciprocal and one
+// correction step (exact in that range).
+struct FastDiv {
+  int d;
+  float inv;
+};
+__device__ __forceinline__ int fdiv(int x, FastDiv f) {
+  int q = (int)((float)x * f.inv);
+  int r = x - q * f.d;
+  q += (r >= f.d) - (r < 0);
+  return q;
+}
+
+// Remap a linear block index so that each of the 8 XCDs (which receive blocks round-robin)
+// works on a contiguous range of logical tiles.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int nx = 8;
+  int per = (nblocks + nx - 1) / nx;
+  int xcd = bid % nx, local = bid / nx;
+  int full = nblocks - (per - 1) * nx;  // XCDs that receive `per` blocks
+  int start = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+  return start + local;
+}
+
+}  // namespace gfd

@@ -1,0 +1,210 @@
+// Discrepancy-principle search for lambda (Sec. 3.2, Eqs.(10)-(11)) as a small state machine.
+//
+// The device kernels evaluate, for a handful of candidate values lambda_j, the compensated
+// FP32 sums   S_j  = sum_b q_b g_j(b),   D_j = sum_b q_b g_j(b) (1 - r_j(b)),
+// with q_b the Hermitian-weighted |R_b|^2, t_b = |H_b|^2, r = 1 / (1 + t_b / lambda_j) and
+// g = r^2, so that f(lambda_j) = S_j / P is the left-hand side of Eq.(11) and
+// d ln f / d ln lambda = 2 D_j / S_j.  The root f = T is unique because f increases with
+// lambda (Sec. 3.2).  After every evaluation round one thread calls the functions below,
+// which keep a bracket [llo, lhi] with f(llo) < T <= f(lhi) and choose the next candidates:
+// uniform k-section while the bracket is wide, then points clustered around the root of the
+// cubic Hermite interpolant of ln f over ln lambda.  Only FP32 arithmetic is used.
+//
+// The code is plain C++ usable on the host (unit tests) and on the device.
+#pragma once
+#include <math.h>
+
+#if defined(__HIPCC__)
+#define GFD_HD __host__ __device__
+#else
+#define GFD_HD
+#endif
+
+namespace gfd {
+
+constexpr int kLamMaxCand = 8;     // candidates per evaluation round
+constexpr int kLamFirstCand = 8;   // candidates folded into the residual pass
+constexpr float kLamFloor = 1e-30f;
+constexpr float kLamCeil = 1e30f;
+
+enum : int { kFlagInf = 1, kFlagNoRoot = 2, kFlagNonFinite = 4 };
+
+struct LamState {
+  // constants of the image
+  float TP;          // target times P: rho * P^2 * sigma^2 (sums are compared against this)
+  float invP;
+  // iteration bookkeeping
+  int k;             // index of the current iteration
+  int nscale;        // number of valid entries in the scale array
+  int phase;         // 0: searching, 1: lambda fixed for this iteration
+  int flags;         // flags of the current iteration
+  unsigned flags_all;
+  int rounds;        // evaluation rounds used this iteration
+  float Einf;        // ||h * u_E - y||^2 of this iteration
+  float lam_star, lam;
+  float lam_prev;    // last finite lambda_star (0 = none): centre of the first candidates
+  // bracket
+  int haslo, hashi;
+  float llo, lhi, Flo, Fhi, Dlo, Dhi;
+  int nc;
+  float cand[kLamMaxCand];
+  float mu[kLamMaxCand];  // 1 / cand
+  // offsets subtracted from u_I and u_p inside the guided filter (their means)
+  float meanI, meanP;
+  unsigned arrive;   // arrival counter of the last-block reductions
+};
+
+GFD_HD inline float lam_relF(float hi, float lo, float TP) {
+  // f / T - 1 with the subtraction done exactly when hi is close to TP
+  return ((hi - TP) + lo) / TP;
+}
+
+GFD_HD inline void lam_set_cand(LamState &s, int n, const float *c) {
+  s.nc = n;
+  for (int j = 0; j < n; ++j) {
+    float v = fminf(fmaxf(c[j], kLamFloor), kLamCeil);
+    s.cand[j] = v;
+    s.mu[j] = 1.0f / v;
+  }
+}
+
+// First candidates of an iteration: around the previous lambda_star when there is one,
+// otherwise spread over the whole admissible range.
+GFD_HD inline void lam_first_candidates(LamState &s) {
+  float c[kLamFirstCand];
+  if (s.lam_prev > 0.0f) {
+    for (int j = 0; j < kLamFirstCand; ++j)
+      c[j] = s.lam_prev * expf(0.5f * ((float)j - 0.5f * (kLamFirstCand - 1)));
+  } else {
+    const float x0 = logf(kLamFloor), x1 = logf(kLamCeil);
+    for (int j = 0; j < kLamFirstCand; ++j)
+      c[j] = expf(x0 + (x1 - x0) * ((float)j + 0.5f) / (float)kLamFirstCand);
+  }
+  lam_set_cand(s, kLamFirstCand, c);
+}
+
+// Fold one round of evaluations into the bracket.
+GFD_HD inline void lam_absorb(LamState &s, int n, const float *cand, const float *Shi, const float *Slo,
+                              const float *Dsum) {
+  for (int j = 0; j < n; ++j) {
+    float F = lam_relF(Shi[j], Slo[j], s.TP);
+    float S = Shi[j] + Slo[j];
+    float D = S > 0.0f ? 2.0f * Dsum[j] / S : 0.0f;
+    if (F < 0.0f) {
+      if (!s.haslo || cand[j] > s.llo) { s.haslo = 1; s.llo = cand[j]; s.Flo = F; s.Dlo = D; }
+    } else {
+      if (!s.hashi || cand[j] < s.lhi) { s.hashi = 1; s.lhi = cand[j]; s.Fhi = F; s.Dhi = D; }
+    }
+  }
+}
+
+// Root in tau in [0, 1] of the cubic Hermite interpolant with values G0 < 0 <= G1 and slopes
+// d0, d1 (already multiplied by the interval length).
+GFD_HD inline float hermite_root(float G0, float G1, float d0, float d1, float tau_guess) {
+  float lo = 0.0f, hi = 1.0f, t = fminf(fmaxf(tau_guess, 0.0f), 1.0f);
+  for (int it = 0; it < 40; ++it) {
+    float t2 = t * t, t3 = t2 * t;
+    float p = (2 * t3 - 3 * t2 + 1) * G0 + (t3 - 2 * t2 + t) * d0 + (-2 * t3 + 3 * t2) * G1 + (t3 - t2) * d1;
+    float dp = (6 * t2 - 6 * t) * G0 + (3 * t2 - 4 * t + 1) * d0 + (-6 * t2 + 6 * t) * G1 + (3 * t2 - 2 * t) * d1;
+    if (p < 0.0f) lo = t; else hi = t;
+    float tn = (dp > 0.0f) ? t - p / dp : -1.0f;
+    if (!(tn > lo && tn < hi)) tn = 0.5f * (lo + hi);
+    if (fabsf(tn - t) <= 1e-9f) { t = tn; break; }
+    t = tn;
+  }
+  return t;
+}
+
+// Estimate of the root from the current bracket; returns the ln-lambda error proxy.
+GFD_HD inline float lam_estimate(const LamState &s, float &lam_est, float &width) {
+  width = log1pf((s.lhi - s.llo) / s.llo);          // ln(lhi / llo)
+  float G0 = log1pf(s.Flo), G1 = log1pf(s.Fhi);     // ln(f / T) at both ends
+  float ts = (G1 > G0) ? -G0 / (G1 - G0) : 0.5f;    // secant
+  float th = hermite_root(G0, G1, s.Dlo * width, s.Dhi * width, ts);
+  lam_est = s.llo + s.llo * expm1f(th * width);
+  return fabsf(th - ts) * width;
+}
+
+// Decide after a round: either fix lambda (phase = 1) or load the next candidates.
+// `last` forces a decision.  Returns 1 if lambda is fixed.
+GFD_HD inline int lam_decide(LamState &s, bool last) {
+  s.rounds += 1;
+  float next[kLamMaxCand];
+  if (s.haslo && s.hashi) {
+    if (!(s.llo < s.lhi)) {  // inconsistent (rounding noise at the root): take the midpoint
+      s.lam_star = 0.5f * (s.llo + s.lhi);
+      s.phase = 1;
+      return 1;
+    }
+    float est, width;
+    float err = lam_estimate(s, est, width);
+    if (last || width <= 1e-6f || (err <= 1e-6f && width <= 0.05f)) {
+      s.lam_star = est;
+      s.phase = 1;
+      return 1;
+    }
+    const int n = kLamMaxCand;
+    if (width > 1.0f || !(err > 0.0f)) {
+      for (int j = 0; j < n; ++j) next[j] = s.llo * expf(width * (float)(j + 1) / (float)(n + 1));
+    } else {
+      float h = fmaxf(4.0f * err, 1e-7f);
+      if (h * (float)(n + 1) >= width) {
+        for (int j = 0; j < n; ++j) next[j] = s.llo * expf(width * (float)(j + 1) / (float)(n + 1));
+      } else {
+        // clustered around the estimate, kept strictly inside the bracket
+        float xe = logf(est / s.llo);
+        xe = fminf(fmaxf(xe, 0.5f * h * (float)(n + 1)), width - 0.5f * h * (float)(n + 1));
+        for (int j = 0; j < n; ++j) next[j] = s.llo * expf(xe + h * ((float)j - 0.5f * (float)(n - 1)));
+      }
+    }
+    lam_set_cand(s, n, next);
+    return 0;
+  }
+  // not bracketed yet: march outwards in large geometric steps
+  const float step = 6.0f;
+  if (s.haslo) {
+    if (last || s.llo >= kLamCeil) { s.lam_star = s.llo; s.phase = 1; return 1; }
+    for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.llo * expf(step * (float)(j + 1));
+  } else {
+    if (last || s.lhi <= kLamFloor) { s.lam_star = s.lhi; s.phase = 1; return 1; }
+    for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.lhi * expf(-step * (float)(j + 1));
+  }
+  lam_set_cand(s, kLamMaxCand, next);
+  return 0;
+}
+
+// Start of an iteration after the residual pass: Einf = sum q / P, Sfloor = sum q g(floor).
+// Returns 1 if lambda is already fixed (infinite branch or no root).
+GFD_HD inline int lam_begin(LamState &s, float Ehi, float Elo, float Fl_hi, float Fl_lo, int n,
+                            const float *cand, const float *Shi, const float *Slo, const float *Dsum) {
+  s.rounds = 0;
+  s.haslo = s.hashi = 0;
+  s.Einf = (Ehi + Elo) * s.invP;
+  if (!(Ehi == Ehi) || isinf(Ehi)) {
+    s.flags |= kFlagNonFinite;
+  }
+  if ((Ehi - s.TP) + Elo <= 0.0f) {          // u_E in K: lambda = +inf (ties take the branch)
+    s.flags |= kFlagInf;
+    s.lam_star = INFINITY;
+    s.phase = 1;
+    return 1;
+  }
+  if ((Fl_hi - s.TP) + Fl_lo >= 0.0f) {      // even the floor overshoots: no root
+    s.flags |= kFlagNoRoot;
+    s.lam_star = kLamFloor;
+    s.phase = 1;
+    return 1;
+  }
+  s.haslo = 1;                                // the floor is a valid lower end
+  s.llo = kLamFloor;
+  s.Flo = lam_relF(Fl_hi, Fl_lo, s.TP);
+  s.Dlo = 0.0f;
+  s.hashi = 1;                                // lambda -> inf gives Einf > T
+  s.lhi = kLamCeil;
+  s.Fhi = lam_relF(Ehi, Elo, s.TP);
+  s.Dhi = 0.0f;
+  lam_absorb(s, n, cand, Shi, Slo, Dsum);
+  return lam_decide(s, false);
+}
+
+}  // namespace gfd

@@ -1,0 +1,82 @@
+"""The C ABI library loads, exports every declared entry point, and rejects bad arguments
+before touching the GPU (these calls make no HIP call, so they run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1609_01839_amd as gfd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gfdeconv.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(gfd.library_path()), reason="library not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:gfd_status|void|const char \*)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    lib = gfd.load_library()
+    names = declared_functions()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in gfd.EXPORTS, n
+    assert set(gfd.EXPORTS) == set(names)
+
+
+def test_invalid_arguments_are_rejected_without_gpu():
+    lib = gfd.load_library()
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    cases = [
+        # (M, N, kh, kw, sigma2, w, eps, rho, expected)
+        (7 * 16, 64, 3, 3, 1.0, 3, 1.0, 1.0, -2),     # 7 is not 2^a 3^b 5^c
+        (8192, 64, 3, 3, 1.0, 3, 1.0, 1.0, -2),       # too large
+        (64, 64, 4, 3, 1.0, 3, 1.0, 1.0, -2),         # even PSF side
+        (64, 64, 65, 3, 1.0, 3, 1.0, 1.0, -2),        # PSF larger than the image
+        (64, 64, 3, 3, -1.0, 3, 1.0, 1.0, -1),        # negative noise variance
+        (64, 64, 3, 3, 1.0, 4, 1.0, 1.0, -1),         # even window
+        (64, 64, 3, 3, 1.0, 65, 1.0, 1.0, -1),        # window larger than the image
+        (64, 64, 3, 3, 1.0, 3, 0.0, 1.0, -1),         # eps must be > 0
+        (64, 64, 3, 3, 1.0, 3, float("nan"), 1.0, -1),
+        (64, 64, 3, 3, 1.0, 3, 1.0, 1.5, -1),         # rho > 1
+        (64, 64, 3, 3, 1.0, 19, 1.0, 1.0, -6),        # wider windows are not built
+    ]
+    for M, N, kh, kw, s2, w, eps, rho, want in cases:
+        rc = lib.deconv_init(ctypes.byref(ctx), fake, M, N, fake, kh, kw, s2, w, eps, rho, None)
+        assert rc == want, (M, N, kh, kw, s2, w, eps, rho, rc, lib.gfd_last_error())
+        assert ctx.value is None
+        assert lib.gfd_last_error()
+    assert lib.deconv_init(ctypes.byref(ctx), None, 64, 64, fake, 3, 3, 1.0, 3, 1.0, 1.0, None) == -1
+    assert lib.deconv_init(None, fake, 64, 64, fake, 3, 3, 1.0, 3, 1.0, 1.0, None) == -1
+
+
+def test_guided_filter_argument_checks():
+    lib = gfd.load_library()
+    a, b, c = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
+    assert lib.guided_filter(None, b, c, 16, 16, 3, 1.0, None) == -1
+    assert lib.guided_filter(a, b, c, 16, 16, 2, 1.0, None) == -1
+    assert lib.guided_filter(a, b, c, 16, 16, 17, 1.0, None) == -1
+    assert lib.guided_filter(a, b, c, 0, 16, 1, 1.0, None) == -2
+    assert lib.guided_filter(a, b, c, 16, 16, 3, -1.0, None) == -1
+    assert lib.guided_filter(a, b, ctypes.c_void_p(0x10000 + 64), 16, 16, 3, 1.0, None) == -1  # u overlaps uI
+
+
+def test_foreign_and_null_contexts():
+    lib = gfd.load_library()
+    bogus = ctypes.c_void_p(0xDEAD0)
+    assert lib.deconv_iterate(bogus, 1, None, None, None) == -5
+    assert lib.deconv_iterate(None, 1, None, None, None) == -5
+    assert lib.deconv_reset(bogus, None) == -5
+    assert lib.deconv_set_graph(bogus, 1) == -5
+    flags = ctypes.c_uint()
+    assert lib.deconv_get_status(bogus, ctypes.byref(flags)) == -5
+    lib.deconv_destroy(None)
+    lib.deconv_destroy(bogus)   # unknown pointers are ignored, never dereferenced
+    assert "invalid" in lib.gfd_last_error().decode() or lib.gfd_last_error() is not None

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same inputs.
+
+Tolerances come from the stated target: every iterate within 1e-5 relative L2 of the FP64
+oracle, final ISNR within 0.01 dB.  Component checks (FFT round trip, guided filter, solves,
+lambda) use the same or tighter bounds.  Each test prints the errors it measured.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1609_01839_amd as gfd
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def problem(M, N, h, sigma2=None, bsnr=35.0, seed=0, textured=False):
+    rng = np.random.default_rng(seed)
+    u = synth.textured_image(M, N, rng) if textured else synth.piecewise_image(M, N, rng)
+    b = synth.blur_periodic(u, h)
+    if sigma2 is None:
+        sigma2 = synth.sigma2_for_bsnr(b, bsnr)
+    y = (b + math.sqrt(sigma2) * rng.standard_normal((M, N))).astype(np.float32)
+    return u, y, float(sigma2)
+
+
+def oracle_setup(y, h, sigma2, rho=None):
+    return oracle.setup(y.astype(np.float64), h.astype(np.float32).astype(np.float64), sigma2, rho)
+
+
+SIZES = [(6, 10), (16, 16), (30, 48), (45, 75), (64, 80), (256, 256), (480, 640), (720, 1280), (243, 125),
+         (1024, 1024)]
+
+
+@pytest.mark.parametrize("M,N", SIZES)
+def test_fft_round_trip(M, N):
+    """lambda = +inf: u_I = u_p = F^-1 F u_E through all four FFT passes."""
+    h = synth.psf_box(3 if min(M, N) >= 3 else 1)
+    _, y, s2 = problem(M, N, h)
+    rng = np.random.default_rng(1)
+    uE = rng.uniform(0, 255, (M, N)).astype(np.float32)
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h), s2, 1, 1.0, 1.0) as g:
+        uI, up = g.spectral_solve(to_gpu(uE), math.inf)
+        e1, e2 = rel_l2(uI.cpu().numpy(), uE), rel_l2(up.cpu().numpy(), uE)
+    print(f"round trip {M}x{N}: {e1:.2e} {e2:.2e}")
+    assert e1 < 1e-6 and e2 < 1e-6
+
+
+GF_CASES = [(64, 64, 1), (64, 64, 3), (100, 130, 5), (256, 256, 7), (120, 96, 9), (480, 640, 17), (37, 41, 17),
+            (8, 300, 5), (1024, 1024, 17)]
+
+
+@pytest.mark.parametrize("M,N,w", GF_CASES)
+@pytest.mark.parametrize("eps", [650.25, 48.77])
+def test_guided_filter_parity(M, N, w, eps):
+    rng = np.random.default_rng(M * 7 + N + w)
+    I = synth.piecewise_image(M, N, rng, n_shapes=8) + 5.0 * rng.standard_normal((M, N))
+    p = I + 20.0 * rng.standard_normal((M, N))
+    I32, p32 = I.astype(np.float32), p.astype(np.float32)
+    out = gfd.guided_filter(to_gpu(I32), to_gpu(p32), w, eps).cpu().numpy()
+    ref = oracle.guided_filter(I32.astype(np.float64), p32.astype(np.float64), w, float(np.float32(eps)))
+    e = rel_l2(out, ref)
+    emax = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+    print(f"GF {M}x{N} w={w} eps={eps}: rel L2 {e:.2e}, max {emax:.2e}")
+    assert e < 2e-6 and emax < 2e-5
+
+
+def test_guided_filter_special_cases():
+    rng = np.random.default_rng(5)
+    c = np.full((40, 50), 93.5, np.float32)
+    out = gfd.guided_filter(to_gpu(c), to_gpu(c), 5, 650.25).cpu().numpy()
+    assert np.array_equal(out, c)  # flat window: a = 0, b = the constant
+    I = rng.uniform(0, 255, (40, 50)).astype(np.float32)
+    p = rng.uniform(0, 255, (40, 50)).astype(np.float32)
+    out = gfd.guided_filter(to_gpu(I), to_gpu(p), 1, 650.25).cpu().numpy()
+    assert np.max(np.abs(out - p)) < 1e-3  # w = 1 returns the input
+    out = gfd.guided_filter(to_gpu(p), to_gpu(p), 5, 1e-6).cpu().numpy()
+    assert rel_l2(out, p) < 1e-5  # identical guide, eps -> 0 returns the input
+
+
+SOLVE_CASES = [(64, 80, "box9"), (256, 256, "gauss"), (480, 640, "box9"), (45, 75, "invq"), (243, 125, "gauss")]
+
+
+def psf(kind, M, N):
+    k = {"box9": synth.psf_box(9), "gauss": synth.psf_gaussian(1.6, 25), "invq": synth.psf_inverse_quadratic(15)}[kind]
+    return k if k.shape[0] <= min(M, N) else synth.psf_box(3)
+
+
+@pytest.mark.parametrize("M,N,kind", SOLVE_CASES)
+def test_spectral_solve_parity(M, N, kind):
+    h = psf(kind, M, N)
+    u, y, s2 = problem(M, N, h)
+    S = oracle_setup(y, h, s2)
+    rng = np.random.default_rng(2)
+    uE = (u + 10 * rng.standard_normal((M, N))).astype(np.float32)
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h.astype(np.float32)), s2, 3, 1.0) as g:
+        for lam in (1e-3, 0.05, 3.0, 1e4):
+            uI, up = g.spectral_solve(to_gpu(uE), lam)
+            rI, rp = oracle.spectral_solve(S, oracle.dft2(uE.astype(np.float64)), float(np.float32(lam)))
+            eI, ep = rel_l2(uI.cpu().numpy(), rI), rel_l2(up.cpu().numpy(), rp)
+            print(f"solve {M}x{N} {kind} lam={lam}: u_I {eI:.2e}, u_p {ep:.2e}")
+            assert eI < 1e-5 and ep < 1e-5
+
+
+@pytest.mark.parametrize("M,N,kind", SOLVE_CASES)
+def test_discrepancy_lambda_parity(M, N, kind):
+    h = psf(kind, M, N)
+    u, y, s2 = problem(M, N, h)
+    rng = np.random.default_rng(3)
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h.astype(np.float32)), s2, 3, 1.0) as g:
+        S = oracle_setup(y, h, s2)
+        assert math.isclose(g.info()["rho"], S.rho, rel_tol=1e-9)
+        for uE in (np.zeros((M, N)), 0.9 * u + 3 * rng.standard_normal((M, N))):
+            uE = uE.astype(np.float32)
+            lam = float(g.discrepancy_lambda(to_gpu(uE)).cpu()[0])
+            ref, flags = oracle.discrepancy_lambda(S, oracle.dft2(uE.astype(np.float64)))
+            err = abs(lam - ref) / ref
+            print(f"lambda {M}x{N} {kind}: gpu {lam:.9g} oracle {ref:.9g} rel {err:.2e}")
+            assert flags == 0 and err < 1e-5
+
+
+def run_trajectory(c, iters, rho=None, one_step=True):
+    y, h = c.y, c.h.astype(np.float32)
+    eps = float(np.float32(c.eps))
+    ref_u, info = oracle.deconvolve(y.astype(np.float64), h.astype(np.float64), c.sigma2, c.w, eps, iters, rho=rho,
+                                    keep_iterates=True)
+    errs, lam_errs, step_errs = [], [], []
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h), c.sigma2, c.w, eps, rho) as g:
+        for k in range(iters):
+            u, lam = g.iterate(1)
+            errs.append(rel_l2(u.cpu().numpy(), info["iterates"][k]))
+            lam_errs.append(abs(float(lam.cpu()[0]) - info["lam"][k]) / info["lam"][k])
+        isnr_gpu = oracle.isnr(u.cpu().numpy(), y, c.u_orig)
+        if one_step:
+            S = oracle_setup(y, h, c.sigma2, rho)
+            for k in range(iters - 1):
+                g.set_estimate(to_gpu(info["iterates"][k]))
+                u1, _ = g.iterate(1)
+                ref = oracle.step(S, info["iterates"][k].astype(np.float32).astype(np.float64), c.w, eps)
+                step_errs.append(rel_l2(u1.cpu().numpy(), ref.u))
+    isnr_ref = oracle.isnr(ref_u, y, c.u_orig)
+    return errs, lam_errs, step_errs, isnr_gpu, isnr_ref, info
+
+
+def test_iteration_parity_256_box9():
+    c = synth.make_case(1)                       # 256^2, 9x9 box, BSNR 40 dB, w = 5, 10 iterations
+    errs, lam_errs, step_errs, ig, io, info = run_trajectory(c, c.iters)
+    print("trajectory rel L2:", " ".join(f"{e:.1e}" for e in errs))
+    print("one-step rel L2:  ", " ".join(f"{e:.1e}" for e in step_errs))
+    print("lambda rel err:   ", " ".join(f"{e:.1e}" for e in lam_errs))
+    print(f"ISNR gpu {ig:.4f} dB oracle {io:.4f} dB")
+    assert max(errs) < 1e-5 and max(step_errs) < 1e-5
+    assert max(lam_errs) < 1e-4
+    assert abs(ig - io) < 0.01
+
+
+def test_iteration_parity_odd_sizes_and_table1_setting():
+    c = synth.table1_case(4, 75, 90)           # binomial PSF, sigma^2 = 49, w = 3, eps of Sec. 4
+    errs, lam_errs, step_errs, ig, io, _ = run_trajectory(c, 8)
+    print("trajectory:", " ".join(f"{e:.1e}" for e in errs), f"ISNR {ig:.4f}/{io:.4f}")
+    assert max(errs) < 1e-5 and max(step_errs) < 1e-5 and abs(ig - io) < 0.01
+
+
+def test_iteration_parity_1024_textured():
+    c = synth.make_case(2)                       # 1024^2 textured, 15x15 1/(1+x^2+y^2), sigma^2 = 2, w = 7
+    errs, lam_errs, step_errs, ig, io, _ = run_trajectory(c, 4, one_step=False)
+    print("trajectory:", " ".join(f"{e:.1e}" for e in errs), f"lambda {max(lam_errs):.1e}", f"ISNR {ig:.4f}/{io:.4f}")
+    assert max(errs) < 1e-5 and max(lam_errs) < 1e-4
+
+
+def test_graph_replay_equals_eager_and_chunking():
+    c = synth.make_case(1, size=(128, 96))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    outs = []
+    for use_graph, chunks in ((True, [6]), (False, [6]), (True, [2, 3, 1])):
+        with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+            g.set_graph(use_graph)
+            lams = []
+            for n in chunks:
+                u, lam = g.iterate(n)
+                lams.append(lam.cpu().numpy())
+            outs.append((u.cpu().numpy(), np.concatenate(lams)))
+    for u, lam in outs[1:]:
+        assert np.array_equal(u, outs[0][0])
+        assert np.array_equal(lam, outs[0][1])
+
+
+def test_branch_flags():
+    c = synth.make_case(1, size=(64, 64))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    big = 10.0 * float(np.mean(c.y.astype(np.float64) ** 2))
+    with gfd.GFDeconv(y, h, big, c.w, c.eps, rho=1.0) as g:   # u_E = 0 already in K
+        u, lam = g.iterate(3)
+        assert torch.all(torch.isinf(lam)).item()
+        assert torch.count_nonzero(u).item() == 0
+        assert g.status() & gfd.FLAG_INF_BRANCH
+    with gfd.GFDeconv(y, h, 0.0, c.w, c.eps) as g:            # sigma^2 = 0: no root, lambda floor
+        u, lam = g.iterate(1)
+        assert float(lam.cpu()[0]) == pytest.approx(1e-30, rel=1e-6)
+        assert g.status() & gfd.FLAG_NO_ROOT
+
+
+def test_scales_multiply_lambda():
+    c = synth.make_case(1, size=(64, 64))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+        _, lam1 = g.iterate(3)
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+        g.set_scales([1.0, 1.0, 0.5])
+        _, lam2 = g.iterate(3)
+    l1, l2 = lam1.cpu().numpy(), lam2.cpu().numpy()
+    assert np.array_equal(l1[:2], l2[:2])
+    assert l2[2] == pytest.approx(0.5 * l1[2], rel=1e-6)
+
+
+def test_determinism():
+    c = synth.make_case(1, size=(256, 256))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    res = []
+    for _ in range(2):
+        with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+            u, lam = g.iterate(5)
+            res.append((u.cpu().numpy(), lam.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
