@@ -22,7 +22,8 @@ hipError_t launch_copy_lam_star(const LamState *st, float *out, hipStream_t s);
 using namespace gfd;
 
 static const uint64_t kMagic = 0x6766646563763031ull;  // "gfdecv01"
-static const int kSweeps = 6;                           // lambda evaluation rounds per iteration
+static const int kSweeps = 3;      // lambda evaluation rounds per iteration after the first (graph)
+static const int kSweepsFull = 10; // rounds of a stand-alone search (cold start allowed)
 
 struct gfd_ctx {
   uint64_t magic;
@@ -135,7 +136,7 @@ static hipError_t enqueue_iteration(gfd_ctx *c, hipStream_t s) {
     return e;
   if ((e = launch_row_inv(c->SI, c->SP, L, c->pn, c->twN, c->uI, c->uP, s)) != hipSuccess) return e;
   return launch_guided_filter(c->uI, c->uP, c->uE, c->M, c->N, c->w, c->eps, &c->st->meanI, &c->st->meanP,
-                              &c->st->k, s);
+                              c->st, s);
 }
 
 // The same launches as enqueue_iteration with an event recorded after each pass.
@@ -157,9 +158,22 @@ static hipError_t enqueue_iteration_timed(gfd_ctx *c, hipStream_t s, hipEvent_t 
   if ((e = launch_row_inv(c->SI, c->SP, L, c->pn, c->twN, c->uI, c->uP, s)) != hipSuccess) return e;
   if ((e = hipEventRecord(ev[5], s)) != hipSuccess) return e;
   if ((e = launch_guided_filter(c->uI, c->uP, c->uE, c->M, c->N, c->w, c->eps, &c->st->meanI, &c->st->meanP,
-                                &c->st->k, s)) != hipSuccess)
+                                c->st, s)) != hipSuccess)
     return e;
   return hipEventRecord(ev[6], s);
+}
+
+// Lambda search for the current estimate outside the graph, with enough rounds for a cold start;
+// leaves lambda_star as the warm start of the next iteration (the iteration count is unchanged).
+static hipError_t enqueue_warm_start(gfd_ctx *c, hipStream_t s) {
+  const Layout &L = c->lay;
+  LamBuffers lb = lam_buffers(c, false);
+  hipError_t e;
+  if ((e = launch_row_fwd(c->uE, L, c->pn, c->twN, c->S1, s)) != hipSuccess) return e;
+  if ((e = launch_col_fwd_resid(c->S1, c->q, c->H, c->Y, L, c->pm, c->twM, lb, s)) != hipSuccess) return e;
+  for (int k = 0; k < kSweepsFull; ++k)
+    if ((e = launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweepsFull - 1, s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 static gfd_status capture_graph(gfd_ctx *c) {
@@ -298,6 +312,7 @@ gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float 
   if (e == hipSuccess) e = launch_state_reset(c->st_aux, s);
   if (e == hipSuccess) e = launch_fill_f(c->uE, P, 0.0f, s);
   if (e == hipSuccess) e = launch_fill_f(c->scales, c->hist_cap, 1.0f, s);
+  if (e == hipSuccess) e = enqueue_warm_start(c, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   double ro[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpy(ro, c->rho_out, sizeof(ro), hipMemcpyDeviceToHost);
@@ -441,7 +456,8 @@ gfd_status discrepancy_lambda(gfd_ctx *ctx, const float *uE, float *lambda_dev, 
   HIPCHK(launch_state_reset(c->st_aux, s));
   HIPCHK(launch_row_fwd(uE, L, c->pn, c->twN, c->S1, s));
   HIPCHK(launch_col_fwd_resid(c->S1, c->q, c->H, c->Y, L, c->pm, c->twM, lb, s));
-  for (int k = 0; k < kSweeps; ++k) HIPCHK(launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweeps - 1, s));
+  for (int k = 0; k < kSweepsFull; ++k)
+    HIPCHK(launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweepsFull - 1, s));
   HIPCHK(launch_copy_lam_star(c->st_aux, lambda_dev, s));
   return GFD_OK;
 }
@@ -468,6 +484,7 @@ gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream) {
   if (!uE) return fail(GFD_ERR_ARG, "uE must be a device pointer");
   HIPCHK(hipMemcpyAsync(ctx->uE, uE, (size_t)ctx->M * ctx->N * sizeof(float), hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));
+  HIPCHK(enqueue_warm_start(ctx, (hipStream_t)stream));
   return GFD_OK;
 }
 
@@ -477,6 +494,7 @@ gfd_status deconv_reset(gfd_ctx *ctx, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(launch_fill_f(ctx->uE, (size_t)ctx->M * ctx->N, 0.0f, s));
   HIPCHK(launch_state_reset(ctx->st, s));
+  HIPCHK(enqueue_warm_start(ctx, s));
   ctx->iters = 0;
   return GFD_OK;
 }

@@ -1,0 +1,134 @@
+// Register-resident Stockham FFT for power-of-two lengths L = 256 .. 4096.
+//
+// T = L / 16 threads cooperate on one sequence; thread t keeps the 16 elements
+// x[t + T m], m = 0..15, in registers.  A pass of radix R (16, 8, 4 or 2) gives each thread
+// 16 / R butterflies j = t + T v whose inputs x[j + i L/R] are exactly its registers
+// v + i 16/R; the twiddled R-point DFT outputs go to the Stockham positions
+// (j - k) R + k + i s (s = product of the earlier radices, k = j mod s) through LDS, and the
+// thread reads back its next inputs.  After the last pass (s R = L) the outputs land on the
+// thread's own positions t + T m, so no exchange follows it.  LDS positions are padded by one
+// slot every 16 to keep the stride-16 writes of the first pass off a single bank.
+#pragma once
+#include "fft_lds.h"
+
+namespace gfd {
+
+struct RegPlan {
+  int L, T, npass;
+  int radix[3];  // radix of each pass (16, 8, 4 or 2)
+};
+
+__device__ __forceinline__ int lds_pad(int p) { return p + (p >> 4); }
+
+// 16-point DFT as 4 x 4 with the W16 twiddles in between.
+template <int DIR>
+__device__ __forceinline__ void dft16(cf *x) {
+  const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+  cf a[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cf y[4] = {x[n2], x[n2 + 4], x[n2 + 8], x[n2 + 12]};
+    dft4<DIR>(y);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = y[k1];
+  }
+  // a[n2][k1] *= W16^(n2 k1), W16 = exp(DIR i 2 pi / 16)
+  const float D = (float)DIR;
+  a[1][1] = cmul(a[1][1], cf{c1, D * s1});
+  a[1][2] = cmul(a[1][2], cf{h, D * h});
+  a[1][3] = cmul(a[1][3], cf{s1, D * c1});
+  a[2][1] = cmul(a[2][1], cf{h, D * h});
+  a[2][2] = mul_i<DIR>(a[2][2]);
+  a[2][3] = cmul(a[2][3], cf{-h, D * h});
+  a[3][1] = cmul(a[3][1], cf{s1, D * c1});
+  a[3][2] = cmul(a[3][2], cf{-h, D * h});
+  a[3][3] = cmul(a[3][3], cf{-c1, -D * s1});
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cf z[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4<DIR>(z);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = z[k2];
+  }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dftR(cf *x) {
+  if constexpr (R == 16) dft16<DIR>(x);
+  else if constexpr (R == 8) dft8<DIR>(x);
+  else if constexpr (R == 4) dft4<DIR>(x);
+  else dft2<DIR>(x);
+}
+
+// One pass.  `lds` addresses the sequence's region: slot(p) = lds[lds_pad(p) * ls].
+template <int R, int DIR>
+__device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L, bool last, cf *lds, int ls,
+                                         const cf *__restrict__ tw) {
+  constexpr int NBF = 16 / R;
+  const int tstride = L / (s * R);
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int j = t + T * b;
+    const int k = j & (s - 1);
+    cf x[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = v[b + i * NBF];
+    if (s > 1) {
+#pragma unroll
+      for (int i = 1; i < R; ++i) {
+        cf w = tw[i * k * tstride];
+        if (DIR > 0) w.im = -w.im;
+        x[i] = cmul(x[i], w);
+      }
+    }
+    dftR<R, DIR>(x);
+    if (last) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[b + i * NBF] = x[i];
+    } else {
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int i = 0; i < R; ++i) lds[lds_pad(base + i * s) * ls] = x[i];
+    }
+  }
+  if (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = lds[lds_pad(t + T * m) * ls];
+    __syncthreads();
+  }
+}
+
+// Whole transform.  On entry v[m] = x[t + T m]; on exit v[m] = X[t + T m] (unnormalised).
+// Every thread of the block must call this (it contains barriers).
+template <int DIR>
+__device__ __forceinline__ void reg_fft(cf (&v)[16], int t, const RegPlan &p, cf *lds, int ls,
+                                        const cf *__restrict__ tw) {
+  int s = 1;
+  for (int q = 0; q < p.npass; ++q) {
+    const bool last = q == p.npass - 1;
+    switch (p.radix[q]) {
+      case 16: reg_pass<16, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
+      case 8: reg_pass<8, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
+      case 4: reg_pass<4, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
+      default: reg_pass<2, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
+    }
+    s *= p.radix[q];
+  }
+}
+
+inline bool reg_plan_ok(int L) { return L >= 256 && L <= 4096 && (L & (L - 1)) == 0; }
+
+inline RegPlan make_reg_plan(int L) {
+  RegPlan p;
+  p.L = L;
+  p.T = L / 16;
+  int rest = L / 256;  // 1, 2, 4, 8, 16
+  p.npass = rest == 1 ? 2 : 3;
+  p.radix[0] = 16;
+  p.radix[1] = 16;
+  p.radix[2] = rest == 1 ? 1 : rest;
+  return p;
+}
+
+}  // namespace gfd

@@ -17,9 +17,11 @@ struct Layout {
   int Wh;        // N / 2 + 1
   int C, logC;   // tile width (power of two)
   int NT;        // number of tiles = ceil(Wh / C)
-  int R;         // image rows per block in the row passes (even)
+  int R;         // image rows per block in the LDS-resident row passes (even)
+  int Rf, Ri;    // rows per block of the register-resident row passes (forward even, inverse)
   FastDiv Ndiv;  // division by N
   FastDiv RCdiv; // division by R * C
+  FastDiv RfCdiv;// division by Rf * C
   size_t bins() const { return (size_t)NT * M * C; }
 };
 
@@ -64,9 +66,10 @@ hipError_t launch_col_inv(const cf *UE, const cf *HY, const float *H2, const flo
 // Row pass, inverse: two half spectra -> two real images.
 hipError_t launch_row_inv(const cf *SI, const cf *SP, const Layout &L, const FftPlan &pn, const cf *twN,
                           float *uI, float *uP, hipStream_t st);
-// Guided filter; cI / cP point at the offsets subtracted before forming products.
+// Guided filter; cI / cP point at the offsets subtracted before forming products.  With a
+// state, the kernel also closes the iteration (counter, first lambda candidates of the next).
 hipError_t launch_guided_filter(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
-                                const float *cI, const float *cP, int *iter_counter, hipStream_t st);
+                                const float *cI, const float *cP, LamState *st, hipStream_t s);
 bool guided_filter_supported(int w);
 
 // Init helpers

@@ -1,16 +1,19 @@
 // Guided filter u = guidfilter(u_I, u_p, w, eps) on gfx950 (Sec. 2, Eqs.(3)-(5)).
 //
-// One block owns a strip of TX output columns and TY output rows and streams down its rows.
-// Every thread owns one column of the strip extended by 2r on each side (r = (w-1)/2):
-//   stage 1: vertical running sums over the last w rows of I, p, I*I, I*p (compensated FP32),
-//            then horizontal sums of those across the block's columns -> w x w window sums,
-//            giving a_k and b_k (Eqs.(3)-(4)) one row of windows at a time;
-//   stage 2: the same two-direction running sums over a and b -> abar, bbar (Eq.(5)), and
+// One block owns a strip of TX output columns and TY output rows and streams down its rows,
+// RB rows per round of barriers.  Every thread owns one column of the strip extended by 2r on
+// each side (r = (w-1)/2):
+//   stage 1: vertical running sums over the last w rows of I, p, I*I, I*p (Kahan-compensated
+//            FP32), then horizontal sliding sums across the block's columns (LDS) -> w x w window
+//            sums -> a_k, b_k (Eqs.(3)-(4)) for one row of windows;
+//   stage 2: the same two-direction sums over a and b -> abar, bbar (Eq.(5)), then
 //            u = abar * I + bbar.
-// The last w rows of (I, p) and of (a, b) sit in LDS rings so that the rows leaving the
-// vertical windows can be subtracted.  Windows wrap periodically in both directions.
-// The inputs are shifted by constants (the image means when known) before the products
-// are formed; the filter commutes with such shifts (u shifts by the input's constant).
+// The rows leaving the stage-1 windows and the guide row of the output are re-read from global
+// memory (they were read w rows earlier and are still cached); the last w rows of (a, b) sit in
+// an LDS ring.  Windows wrap periodically in both directions.  Inputs are shifted by constants
+// (the image means when known) before products are formed; the filter commutes with such
+// shifts (u shifts by the input's constant).  The radius is a template parameter so that the
+// horizontal sums unroll into back-to-back LDS reads.
 #include "gfd_internal.h"
 
 namespace gfd {
@@ -18,6 +21,7 @@ namespace gfd {
 constexpr int kGfThreads = 256;
 constexpr int kGfRmax = 8;
 constexpr int kGfRun = 4;  // columns per thread in the horizontal sums
+constexpr int kGfRB = 2;   // rows per round of barriers
 
 struct Kahan {
   float s, c;
@@ -37,119 +41,194 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-// Horizontal window sums of NQ rows of values held in LDS (row q at src + q * kGfThreads):
-// thread (q, run) produces columns [run*kGfRun, run*kGfRun + kGfRun).
-template <int NQ>
-__device__ __forceinline__ void hsum_rows(const float *src, float *dst, int r) {
-  const int t = threadIdx.x;
+// Horizontal window sums (half-width R) of `ntask` rows of kGfThreads values: task `t` covers
+// row t / runs and columns [run * kGfRun, run * kGfRun + kGfRun).  Columns outside [R, used - R)
+// produce don't-care values.
+template <int R>
+__device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *__restrict__ dst, int task) {
   constexpr int runs = kGfThreads / kGfRun;
-  if (t >= NQ * runs) return;
-  const int q = t / runs, run = t - q * runs;
-  const float *v = src + q * kGfThreads;
+  const int row = task / runs, run = task - row * runs;
+  const float *v = src + row * kGfThreads;
   const int j0 = run * kGfRun;
+  float x[kGfRun + 2 * R];
+#pragma unroll
+  for (int i = 0; i < kGfRun + 2 * R; ++i) x[i] = v[min(max(j0 - R + i, 0), kGfThreads - 1)];
   float s = 0.0f;
-  for (int d = -r; d <= r; ++d) s += v[min(max(j0 + d, 0), kGfThreads - 1)];
-  float *o = dst + q * kGfThreads + j0;
+#pragma unroll
+  for (int i = 0; i <= 2 * R; ++i) s += x[i];
+  float *o = dst + row * kGfThreads + j0;
   o[0] = s;
 #pragma unroll
   for (int i = 1; i < kGfRun; ++i) {
-    s += v[min(j0 + i + r, kGfThreads - 1)] - v[max(j0 + i - 1 - r, 0)];
+    s += x[i + 2 * R] - x[i - 1];
     o[i] = s;
   }
 }
 
+template <int R>
 __global__ void __launch_bounds__(kGfThreads) k_guided_filter(const float *__restrict__ uI, const float *__restrict__ uP,
-                                                              float *__restrict__ u, int M, int N, int r, float eps,
-                                                              int TX, int TY, int nby, const float *__restrict__ cIp,
-                                                              const float *__restrict__ cPp, int *iter_counter) {
-  __shared__ float2 ringIP[(2 * kGfRmax + 1) * kGfThreads];
-  __shared__ float2 ringAB[(2 * kGfRmax + 1) * kGfThreads];
-  __shared__ float vbuf[4 * kGfThreads];
-  __shared__ float hbuf[4 * kGfThreads];
+                                                              float *__restrict__ u, int M, int N, float eps, int TX,
+                                                              int TY, int nby, const float *__restrict__ cIp,
+                                                              const float *__restrict__ cPp, LamState *st) {
+  constexpr int W = 2 * R + 1;
+  constexpr int RB = kGfRB;
+  __shared__ float2 ringAB[W * kGfThreads];
+  __shared__ float vbuf[RB * 4 * kGfThreads];
+  __shared__ float hbuf[RB * 4 * kGfThreads];
 
-  if (iter_counter != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *iter_counter += 1;
-
-  const int w = 2 * r + 1;
-  const float inv_w2 = 1.0f / (float)(w * w);
+  if (st != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the lambda phase of this iteration is over: advance the counter and seed the next search
+    st->k += 1;
+    st->phase = 0;
+    lam_first_candidates(*st);
+  }
+  const float inv_w2 = 1.0f / (float)(W * W);
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = lb / nby, by = lb - bx * nby;
   const int x0 = bx * TX, y0 = by * TY;
   const int j = threadIdx.x;
-  const int used = TX + 4 * r;
-  const int gx = wrap(x0 - 2 * r + j, N);
+  const int used = TX + 4 * R;
+  const bool active = j < used;
+  const int gx = wrap(x0 - 2 * R + j, N);
   const float cI = *cIp, cP = *cPp;
+  const int nrows = TY + 4 * R;  // stream rows it = 0 .. nrows-1 are image rows y0 - 2R + it
+  const int ybase = y0 - 2 * R;
+
+  // per stream row: (I, p) entering, (I, p) leaving the stage-1 window, guide I of the output row
+  struct RowIn {
+    float I, p, Io, po, Ig;
+  };
+  auto fetch = [&](int it) -> RowIn {
+    RowIn v = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (!active || it >= nrows) return v;
+    const size_t g = (size_t)wrap(ybase + it, M) * N + gx;
+    v.I = uI[g];
+    v.p = uP[g];
+    if (it >= W) {
+      const size_t go = (size_t)wrap(ybase + it - W, M) * N + gx;
+      v.Io = uI[go];
+      v.po = uP[go];
+    }
+    if (it >= 4 * R) v.Ig = uI[(size_t)wrap(ybase + it - 2 * R, M) * N + gx];  // guide of the output row
+    return v;
+  };
 
   Kahan sI = {0, 0}, sP = {0, 0}, sII = {0, 0}, sIP = {0, 0}, sA = {0, 0}, sB = {0, 0};
-  const int nrows = TY + 4 * r;
-  for (int it = 0; it < nrows; ++it) {
-    // ---- stage 1, vertical: add row `it`, drop row `it - w`
-    const int gy = wrap(y0 - 2 * r + it, M);
-    const int slot = it % w;
-    if (j < used) {
-      const size_t g = (size_t)gy * N + gx;
-      const float I = __fsub_rn(uI[g], cI), p = __fsub_rn(uP[g], cP);
-      float2 old = make_float2(0.0f, 0.0f);
-      if (it >= w) old = ringIP[slot * kGfThreads + j];
-      ringIP[slot * kGfThreads + j] = make_float2(I, p);
-      kahan_slide(sI, I, old.x);
-      kahan_slide(sP, p, old.y);
-      kahan_slide(sII, I * I, old.x * old.x);
-      kahan_slide(sIP, I * p, old.x * old.y);
-      vbuf[0 * kGfThreads + j] = sI.s;
-      vbuf[1 * kGfThreads + j] = sP.s;
-      vbuf[2 * kGfThreads + j] = sII.s;
-      vbuf[3 * kGfThreads + j] = sIP.s;
+  RowIn cur[RB], nxt[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) nxt[q] = fetch(q);
+  for (int base = 0; base < nrows; base += RB) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) cur[q] = nxt[q];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) nxt[q] = fetch(base + RB + q);
+    // ---- stage 1, vertical
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      if (active && base + q < nrows) {
+        const float I = __fsub_rn(cur[q].I, cI), p = __fsub_rn(cur[q].p, cP);
+        const bool out = base + q >= W;
+        const float Io = out ? __fsub_rn(cur[q].Io, cI) : 0.0f, po = out ? __fsub_rn(cur[q].po, cP) : 0.0f;
+        kahan_slide(sI, I, Io);
+        kahan_slide(sP, p, po);
+        kahan_slide(sII, I * I, Io * Io);
+        kahan_slide(sIP, I * p, Io * po);
+        float *vb = vbuf + q * 4 * kGfThreads;
+        vb[j] = sI.s;
+        vb[kGfThreads + j] = sP.s;
+        vb[2 * kGfThreads + j] = sII.s;
+        vb[3 * kGfThreads + j] = sIP.s;
+      } else {
+        float *vb = vbuf + q * 4 * kGfThreads;
+        vb[j] = vb[kGfThreads + j] = vb[2 * kGfThreads + j] = vb[3 * kGfThreads + j] = 0.0f;
+      }
     }
     __syncthreads();
-    if (it < w - 1) continue;  // no complete window yet (uniform across the block)
-    // ---- stage 1, horizontal: window sums centred at row it - r
-    hsum_rows<4>(vbuf, hbuf, r);
+    if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
+    // ---- stage 1, horizontal: RB rows x 4 quantities
+#pragma unroll
+    for (int t = j; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
     __syncthreads();
-    // ---- coefficients a, b (Eqs. 3-4) and stage 2, vertical
-    const int it2 = it - (w - 1);  // index of this row of (a, b) in the stage-2 stream
-    const int slot2 = it2 % w;
-    if (j >= r && j < used - r) {
-      const float mu = hbuf[j] * inv_w2;
-      const float pb = hbuf[kGfThreads + j] * inv_w2;
-      const float var = fmaxf(__fmaf_rn(-mu, mu, hbuf[2 * kGfThreads + j] * inv_w2), 0.0f);
-      const float cov = __fmaf_rn(-mu, pb, hbuf[3 * kGfThreads + j] * inv_w2);
-      const float a = cov / (var + eps);
-      const float b = __fmaf_rn(-a, mu, pb);
-      float2 old = make_float2(0.0f, 0.0f);
-      if (it2 >= w) old = ringAB[slot2 * kGfThreads + j];
-      ringAB[slot2 * kGfThreads + j] = make_float2(a, b);
-      kahan_slide(sA, a, old.x);
-      kahan_slide(sB, b, old.y);
-      vbuf[j] = sA.s;
-      vbuf[kGfThreads + j] = sB.s;
+    // ---- a, b (Eqs. 3-4) and stage 2, vertical
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int it = base + q;
+      const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
+      float *vb = vbuf + q * 2 * kGfThreads;
+      if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
+        const float *hb = hbuf + q * 4 * kGfThreads;
+        const float mu = hb[j] * inv_w2;
+        const float pb = hb[kGfThreads + j] * inv_w2;
+        const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * inv_w2), 0.0f);
+        const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * inv_w2);
+        const float a = cov / (var + eps);
+        const float b = __fmaf_rn(-a, mu, pb);
+        const int slot = it2 % W;
+        float2 old = make_float2(0.0f, 0.0f);
+        if (it2 >= W) old = ringAB[slot * kGfThreads + j];
+        ringAB[slot * kGfThreads + j] = make_float2(a, b);
+        kahan_slide(sA, a, old.x);
+        kahan_slide(sB, b, old.y);
+        vb[j] = sA.s;
+        vb[kGfThreads + j] = sB.s;
+      } else {
+        // Columns without coefficients still enter the first window of a sliding run before
+        // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
+        vb[j] = 0.0f;
+        vb[kGfThreads + j] = 0.0f;
+      }
     }
     __syncthreads();
-    if (it2 < w - 1) continue;
-    // ---- stage 2, horizontal: window sums of a, b centred at row it - 2r
-    hsum_rows<2>(vbuf, hbuf, r);
+    if (base + RB - 1 < 4 * R) continue;  // no complete stage-2 window yet (uniform)
+    // ---- stage 2, horizontal: RB rows x 2 quantities
+#pragma unroll
+    for (int t = j; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
     __syncthreads();
-    const int yo = y0 - 2 * r + it - 2 * r;  // output row
-    const int xo = x0 - 2 * r + j;           // output column
-    if (j >= 2 * r && j < TX + 2 * r && xo < N && yo < M && yo < y0 + TY) {
-      const float abar = hbuf[j] * inv_w2, bbar = hbuf[kGfThreads + j] * inv_w2;
-      const float I = ringIP[((it - 2 * r) % w) * kGfThreads + j].x;
-      u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, I, bbar), cP);
+    // ---- output rows
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int it = base + q;
+      const int yo = ybase + it - 2 * R;  // output row
+      const int xo = x0 - 2 * R + j;      // output column
+      if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
+        const float *hb = hbuf + q * 2 * kGfThreads;
+        const float abar = hb[j] * inv_w2, bbar = hb[kGfThreads + j] * inv_w2;
+        const float I = __fsub_rn(cur[q].Ig, cI);
+        u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, I, bbar), cP);
+      }
     }
+    // the next round's first barrier orders these hbuf reads before hbuf is rewritten
   }
 }
 
 bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
 
-hipError_t launch_guided_filter(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
-                                const float *cI, const float *cP, int *iter_counter, hipStream_t st) {
-  const int r = (w - 1) / 2;
-  int TX = kGfThreads - 4 * r;
+template <int R>
+static void launch_r(const float *uI, const float *uP, float *u, int M, int N, float eps, const float *cI,
+                     const float *cP, LamState *st, hipStream_t s) {
+  int TX = kGfThreads - 4 * R;
   if (TX > N) TX = N;
   int TY = 64;
   if (TY > M) TY = M;
   const int nbx = (N + TX - 1) / TX, nby = (M + TY - 1) / TY;
-  hipLaunchKernelGGL(k_guided_filter, dim3(nbx * nby), dim3(kGfThreads), 0, st, uI, uP, u, M, N, r, eps, TX, TY, nby,
-                     cI, cP, iter_counter);
+  hipLaunchKernelGGL(k_guided_filter<R>, dim3(nbx * nby), dim3(kGfThreads), 0, s, uI, uP, u, M, N, eps, TX, TY, nby,
+                     cI, cP, st);
+}
+
+hipError_t launch_guided_filter(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
+                                const float *cI, const float *cP, LamState *st, hipStream_t s) {
+  switch ((w - 1) / 2) {
+    case 0: launch_r<0>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 1: launch_r<1>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 2: launch_r<2>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 3: launch_r<3>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 4: launch_r<4>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 5: launch_r<5>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 6: launch_r<6>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 7: launch_r<7>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    case 8: launch_r<8>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

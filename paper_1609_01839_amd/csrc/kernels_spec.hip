@@ -2,8 +2,10 @@
 // spectrum, the residual and lambda reductions (Sec. 3.2, Eqs.(10)-(11)), the two Fourier
 // solves (Sec. 3.1, Eqs.(8)-(9)) and the per-image set-up.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include "fft_reg.h"
 #include "gfd_internal.h"
 
 namespace gfd {
@@ -12,21 +14,6 @@ namespace gfd {
 
 template <class T>
 __device__ __forceinline__ T zero_of() { return (T)0; }
-
-// Last-block detection: every block publishes its partials, then bumps the counter; the
-// block that sees nblocks - 1 finishes the reduction (and resets the counter).
-__device__ __forceinline__ bool arrive_last(unsigned *counter, int nblocks) {
-  __shared__ int is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
 
 // Sum NV (hi, lo) accumulators of `nparts` block partials with every thread of the block;
 // deterministic order.  Result in thread 0.
@@ -78,7 +65,10 @@ __device__ void lam_commit(LamState *st, const LamBuffers &lb) {
   if (!isinf(ls)) {
     float sc = (lb.scales != nullptr && st->k < st->nscale) ? lb.scales[st->k] : 1.0f;
     lam = sc * ls;
-    if (!(st->flags & kFlagNoRoot)) st->lam_prev = ls;
+    if (!(st->flags & kFlagNoRoot)) {
+      st->lam_prev2 = st->lam_prev;
+      st->lam_prev = ls;
+    }
   }
   st->lam = lam;
   st->flags_all |= (unsigned)st->flags;
@@ -99,7 +89,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd(const TI *__restrict__ x, Layo
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem_raw);
   const int M = lay.M, N = lay.N, R = lay.R, LP = N + 1;
   const int npair = R >> 1;
-  const int r0 = blockIdx.x * R;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;  // neighbouring row blocks share an XCD's L2
   for (int e = threadIdx.x; e < npair * N; e += blockDim.x) {
     const int b = fdiv(e, lay.Ndiv), n = e - b * N;
     const int ra = r0 + 2 * b, rb = ra + 1;
@@ -144,7 +134,8 @@ __global__ void __launch_bounds__(1024) k_col_fwd(cpx<T> *__restrict__ S, Layout
 
 // Column pass fused with the residual R = H U_E - Y of Eq.(10), the Hermitian-weighted
 // q = w |R|^2 (w = 1 on columns 0 and N/2, else 2), Einf = sum q / P, and the first lambda
-// candidates of the search.  The last block starts the search.
+// candidates of the search.  Each block writes its compensated partial sums; k_lam_begin
+// finishes them.
 template <int E>
 __global__ void __launch_bounds__(1024) k_col_fwd_resid(cf *__restrict__ S, float *__restrict__ q,
                                                         const cf *__restrict__ H, const cf *__restrict__ Y,
@@ -206,25 +197,14 @@ __global__ void __launch_bounds__(1024) k_col_fwd_resid(cf *__restrict__ S, floa
       dst[2 * v + 1] = lo[v];
     }
   }
-  if (!arrive_last(&st->arrive, gridDim.x)) return;
-  reduce_partials<2 + 2 * NC>(lb.partials, gridDim.x, hi, lo, scratch);
-  if (threadIdx.x == 0) {
-    st->arrive = 0;
-    st->phase = 0;
-    st->flags = 0;
-    float cand[NC];
-    for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
-    int done = lam_begin(*st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC);
-    if (done) lam_commit(st, lb);
-  }
 }
 
 // ============================================================================ lambda sweep
-// One evaluation round: sums over all bins of q g_j and q g_j (1 - r_j) for the current
-// candidates; the last block updates the bracket and picks the next candidates.
+// One evaluation round: per-block sums over the bins of q g_j and q g_j (1 - r_j) for the
+// current candidates (k_lam_round finishes them).
 template <int NC>
 __global__ void __launch_bounds__(256) k_lam_sweep(const float *__restrict__ q, const float *__restrict__ H2,
-                                                   size_t nbins, LamBuffers lb, int last) {
+                                                   size_t nbins, LamBuffers lb) {
   __shared__ float scratch[2 * kLamAcc * 4];
   LamState *st = lb.st;
   if (st->phase != 0) return;  // lambda already fixed for this iteration
@@ -271,10 +251,34 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const float *__restrict__ q, 
       dst[2 * v + 1] = lo[v];
     }
   }
-  if (!arrive_last(&st->arrive, gridDim.x)) return;
-  reduce_partials<2 * NC>(lb.partials, gridDim.x, hi, lo, scratch);
+}
+
+// ============================================================================ lambda decisions
+// One block finishes the partial sums of the residual pass (round 0) or of a sweep and runs the
+// search state machine; deterministic order.
+__global__ void __launch_bounds__(256) k_lam_begin(LamBuffers lb, int nparts) {
+  __shared__ float scratch[2 * kLamAcc * 4];
+  constexpr int NC = kLamFirstCand;
+  float hi[2 + 2 * NC], lo[2 + 2 * NC];
+  reduce_partials<2 + 2 * NC>(lb.partials, nparts, hi, lo, scratch);
   if (threadIdx.x == 0) {
-    st->arrive = 0;
+    LamState *st = lb.st;
+    st->phase = 0;
+    st->flags = 0;
+    float cand[NC];
+    for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
+    if (lam_begin(*st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(st, lb);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_lam_round(LamBuffers lb, int nparts, int last) {
+  __shared__ float scratch[2 * kLamAcc * 4];
+  constexpr int NC = kLamMaxCand;
+  if (lb.st->phase != 0) return;
+  float hi[2 * NC], lo[2 * NC];
+  reduce_partials<2 * NC>(lb.partials, nparts, hi, lo, scratch);
+  if (threadIdx.x == 0) {
+    LamState *st = lb.st;
     float cand[NC];
     for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
     lam_absorb(*st, NC, cand, hi, lo, hi + NC);
@@ -367,7 +371,7 @@ __global__ void __launch_bounds__(1024) k_row_inv(const cf *__restrict__ SI, con
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *buf = reinterpret_cast<cf *>(smem_raw);
   const int M = lay.M, N = lay.N, R = lay.R, C = lay.C, Wh = lay.Wh, LP = N + 1;
-  const int r0 = blockIdx.x * R;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;  // neighbouring row blocks share an XCD's L2
   const int per_t = R * C, total = lay.NT * per_t;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int t = fdiv(e, lay.RCdiv), rem = e - t * per_t;
@@ -393,6 +397,222 @@ __global__ void __launch_bounds__(1024) k_row_inv(const cf *__restrict__ SI, con
     const cf z = buf[rho * LP + nn];
     uI[(size_t)m * N + nn] = z.re;
     uP[(size_t)m * N + nn] = z.im;
+  }
+}
+
+
+// ============================================================================ power-of-two lengths
+// The same passes with the register-resident radix-16 transform of fft_reg.h: two LDS
+// exchanges per transform instead of one per radix pass, and the first / last passes read and
+// write global memory directly.
+
+// Row pass, forward: block = npair sequences x T threads.
+__global__ void __launch_bounds__(512) k_row_fwd_r16(const float *__restrict__ x, Layout lay, RegPlan rp,
+                                                      const cf *__restrict__ tw, cf *__restrict__ S) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cf *lds = reinterpret_cast<cf *>(smem_raw);
+  const int M = lay.M, N = lay.N, R = lay.Rf, T = rp.T;
+  const int LP = N + (N >> 4);
+  const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;
+  const int ra = r0 + 2 * seq, rb = ra + 1;
+  cf v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int n = t + T * m;
+    v[m] = cf{ra < M ? x[(size_t)ra * N + n] : 0.0f, rb < M ? x[(size_t)rb * N + n] : 0.0f};
+  }
+  cf *my = lds + seq * LP;
+  reg_fft<-1>(v, t, rp, my, 1, tw);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) my[lds_pad(t + T * m)] = v[m];
+  __syncthreads();
+  const int C = lay.C, per_t = R * C, Wh = lay.Wh;
+  const int total = lay.NT * per_t;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int tt = fdiv(e, lay.RfCdiv), rem = e - tt * per_t;
+    const int rho = rem >> lay.logC, c = rem & (C - 1);
+    const int m = r0 + rho;
+    if (m >= M) continue;
+    const int k = tt * C + c;
+    cf X = {0.0f, 0.0f};
+    if (k < Wh) {
+      const cf *z = lds + (rho >> 1) * LP;
+      const cf Zk = z[lds_pad(k)], Zn = z[lds_pad(k == 0 ? 0 : N - k)];
+      if ((rho & 1) == 0) X = cf{(Zk.re + Zn.re) * 0.5f, (Zk.im - Zn.im) * 0.5f};
+      else X = cf{(Zk.im + Zn.im) * 0.5f, (Zn.re - Zk.re) * 0.5f};
+    }
+    S[((size_t)tt * M + m) * C + c] = X;
+  }
+}
+
+// Column pass, forward (optionally fused with the residual and the first lambda candidates,
+// as k_col_fwd_resid): block = C columns x T threads, column c = tid % C.
+template <bool RESID>
+__global__ void __launch_bounds__(512) k_col_fwd_r16(cf *__restrict__ S, float *__restrict__ q,
+                                                      const cf *__restrict__ H, const cf *__restrict__ Y, Layout lay,
+                                                      RegPlan rp, const cf *__restrict__ tw, LamBuffers lb) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cf *lds = reinterpret_cast<cf *>(smem_raw);
+  __shared__ float scratch[kLamAcc * 16];
+  const int C = lay.C, T = rp.T;
+  const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
+  const size_t off = (size_t)blockIdx.x * lay.M * C;
+  cf *tile = S + off;
+  cf v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = tile[(t + T * m) * C + c];
+  reg_fft<-1>(v, t, rp, lds + c, C, tw);
+  if (!RESID) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) tile[(t + T * m) * C + c] = v[m];
+    return;
+  }
+  LamState *st = lb.st;
+  constexpr int NC = kLamFirstCand;
+  float mu[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) mu[j] = st->mu[j];
+  const float mu_floor = 1.0f / kLamFloor;
+  float acc[2 + 2 * NC];
+#pragma unroll
+  for (int a = 0; a < 2 + 2 * NC; ++a) acc[a] = 0.0f;
+  const int k = blockIdx.x * C + c;
+  const bool valid = k < lay.Wh;
+  const float wgt = (k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int e = (t + T * m) * C + c;
+    tile[e] = v[m];
+    float qq = 0.0f, t2 = 0.0f;
+    if (valid) {
+      const cf h = H[off + e], y = Y[off + e];
+      const cf r = cmul(h, v[m]) - y;
+      qq = wgt * abs2f(r);
+      t2 = abs2f(h);
+    }
+    q[off + e] = qq;
+    acc[0] += qq;
+    {
+      const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu_floor, 1.0f));
+      acc[1] = __fmaf_rn(qq, r * r, acc[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu[j], 1.0f));
+      const float qg = qq * (r * r);
+      acc[2 + j] += qg;
+      acc[2 + NC + j] = __fmaf_rn(qg, 1.0f - r, acc[2 + NC + j]);
+    }
+  }
+  float hi[2 + 2 * NC], lo[2 + 2 * NC];
+  block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
+  if (threadIdx.x == 0) {
+    float *dst = lb.partials + (size_t)blockIdx.x * kLamAcc * 2;
+    for (int a = 0; a < 2 + 2 * NC; ++a) {
+      dst[2 * a] = hi[a];
+      dst[2 * a + 1] = lo[a];
+    }
+  }
+}
+
+// Solves (Eqs. 8-9) and column inverse of both spectra; U_I waits in registers.
+__global__ void __launch_bounds__(512) k_col_inv_r16(const cf *__restrict__ UE, const cf *__restrict__ HY,
+                                                      const float *__restrict__ H2, const float *__restrict__ dM,
+                                                      const float *__restrict__ dN, Layout lay, RegPlan rp,
+                                                      const cf *__restrict__ tw, LamState *st, cf *__restrict__ SI,
+                                                      cf *__restrict__ SP) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cf *lds = reinterpret_cast<cf *>(smem_raw);
+  const int C = lay.C, T = rp.T;
+  const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
+  const size_t off = (size_t)blockIdx.x * lay.M * C;
+  const float lam = st->lam, invP = st->invP;
+  const bool inf_branch = isinf(lam);
+  const bool big = lam >= 1.0f;
+  const float mu = big ? 1.0f / lam : 0.0f;
+  const int k = blockIdx.x * C + c;
+  const bool valid = k < lay.Wh;
+  const float dk = valid ? dN[k] : 0.0f;
+  cf vp[16], vi[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int row = t + T * m;
+    const int e = row * C + c;
+    cf Up = {0.0f, 0.0f}, Ui = {0.0f, 0.0f};
+    if (valid) {
+      const cf U = UE[off + e];
+      if (inf_branch) {
+        Up = cscale(U, invP);
+        Ui = Up;
+      } else {
+        const cf hy = HY[off + e];
+        const float t2 = H2[off + e];
+        const float d2 = dM[row] + dk;
+        if (big) {
+          const float ip = invP * __builtin_amdgcn_rcpf(__fmaf_rn(mu, t2, 1.0f));
+          const float ii = invP * __builtin_amdgcn_rcpf(__fmaf_rn(mu, t2, d2));
+          Up = cf{(__fmaf_rn(mu, hy.re, U.re)) * ip, (__fmaf_rn(mu, hy.im, U.im)) * ip};
+          Ui = cf{(__fmaf_rn(mu, hy.re, d2 * U.re)) * ii, (__fmaf_rn(mu, hy.im, d2 * U.im)) * ii};
+        } else {
+          const float ip = invP * __builtin_amdgcn_rcpf(t2 + lam);
+          const float ld = lam * d2;
+          const float ii = invP * __builtin_amdgcn_rcpf(t2 + ld);
+          Up = cf{__fmaf_rn(lam, U.re, hy.re) * ip, __fmaf_rn(lam, U.im, hy.im) * ip};
+          Ui = cf{__fmaf_rn(ld, U.re, hy.re) * ii, __fmaf_rn(ld, U.im, hy.im) * ii};
+        }
+      }
+      if (k == 0 && row == 0) {
+        st->meanP = Up.re;
+        st->meanI = Ui.re;
+      }
+    }
+    vp[m] = Up;
+    vi[m] = Ui;
+  }
+  reg_fft<+1>(vp, t, rp, lds + c, C, tw);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) SP[off + (t + T * m) * C + c] = vp[m];
+  reg_fft<+1>(vi, t, rp, lds + c, C, tw);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) SI[off + (t + T * m) * C + c] = vi[m];
+}
+
+// Row pass, inverse: block = Ri rows x T threads; the Hermitian completion is gathered
+// straight from the tile-major spectra.
+__global__ void __launch_bounds__(512) k_row_inv_r16(const cf *__restrict__ SI, const cf *__restrict__ SP,
+                                                      Layout lay, RegPlan rp, const cf *__restrict__ tw,
+                                                      float *__restrict__ uI, float *__restrict__ uP) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cf *lds = reinterpret_cast<cf *>(smem_raw);
+  const int M = lay.M, N = lay.N, C = lay.C, Wh = lay.Wh, T = rp.T;
+  const int LP = N + (N >> 4);
+  const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
+  const int m0 = xcd_remap(blockIdx.x, gridDim.x) * lay.Ri;
+  const int row = m0 + seq;
+  const int rowc = row < M ? row : M - 1;  // rows past the end compute a copy, never stored
+  cf v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int n = t + T * m;
+    const bool direct = n < Wh;
+    const int kk = direct ? n : N - n;
+    const size_t g = ((size_t)(kk >> lay.logC) * M + rowc) * C + (kk & (C - 1));
+    cf A = SI[g], B = SP[g];
+    if (kk == 0 || 2 * kk == N) {
+      A.im = 0.0f;
+      B.im = 0.0f;
+    }
+    v[m] = direct ? cf{A.re - B.im, A.im + B.re} : cf{A.re + B.im, B.re - A.im};
+  }
+  reg_fft<+1>(v, t, rp, lds + seq * LP, 1, tw);
+  if (row < M) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const size_t g = (size_t)row * N + t + T * m;
+      uI[g] = v[m].re;
+      uP[g] = v[m].im;
+    }
   }
 }
 
@@ -537,16 +757,9 @@ __global__ void k_state_reset(LamState *st) {
   st->lam_star = 0.0f;
   st->lam = 0.0f;
   st->lam_prev = 0.0f;
+  st->lam_prev2 = 0.0f;
   st->meanI = 0.0f;
   st->meanP = 0.0f;
-  st->arrive = 0;
-  lam_first_candidates(*st);
-}
-
-// Candidates for the first round of the next iteration (runs before the residual pass).
-__global__ void k_state_begin_iter(LamState *st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  st->phase = 0;
   lam_first_candidates(*st);
 }
 
@@ -590,8 +803,23 @@ Layout make_layout(int M, int N) {
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
   L.R = R;
+  // register-resident row passes (power-of-two N): T = N / 16 threads per sequence
+  L.Rf = L.Ri = 2;
+  if (reg_plan_ok(N)) {
+    const int T = N / 16, target = N >= 2048 ? 512 : 256;
+    const size_t lds_seq = (size_t)(N + N / 16) * sizeof(cf);
+    int seqs = target / T > 1 ? target / T : 1;
+    while (seqs > 1 && seqs * lds_seq > 80 * 1024) seqs /= 2;
+    L.Rf = 2 * seqs;
+    L.Ri = seqs;
+    if (const char *e = getenv("GFD_TUNE_RF")) L.Rf = atoi(e);
+    if (const char *e = getenv("GFD_TUNE_RI")) L.Ri = atoi(e);
+    while (L.Rf > 2 && L.Rf / 2 > (M + 1) / 2) L.Rf /= 2;
+    while (L.Ri > 1 && L.Ri > M) L.Ri /= 2;
+  }
   L.Ndiv = mkdiv(N);
   L.RCdiv = mkdiv(R * C);
+  L.RfCdiv = mkdiv(L.Rf * C);
   return L;
 }
 
@@ -656,7 +884,21 @@ static hipError_t row_fwd_any(const TI *x, const Layout &L, const FftPlan &pn, c
   return hipGetLastError();
 }
 
+template <class K>
+static hipError_t set_lds(K kern, size_t lds) {
+  return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t launch_row_fwd(const float *x, const Layout &L, const FftPlan &pn, const cf *twN, cf *S, hipStream_t st) {
+  if (reg_plan_ok(L.N)) {
+    const RegPlan rp = make_reg_plan(L.N);
+    const size_t lds = (size_t)(L.Rf / 2) * (L.N + L.N / 16) * sizeof(cf);
+    hipError_t e = set_lds(k_row_fwd_r16, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_fwd_r16, dim3((L.M + L.Rf - 1) / L.Rf), dim3((L.Rf / 2) * rp.T), lds, st, x, L, rp, twN,
+                       S);
+    return hipGetLastError();
+  }
   return row_fwd_any<float, float>(x, L, pn, twN, S, st);
 }
 hipError_t launch_row_fwd_d(const double *x, const Layout &L, const FftPlan &pn, const cd *twN, cd *S,
@@ -684,42 +926,73 @@ static hipError_t col_fwd_any(cpx<T> *S, const Layout &L, const FftPlan &pm, con
 hipError_t launch_col_fwd_d(cd *S, const Layout &L, const FftPlan &pm, const cd *twM, hipStream_t st) {
   return col_fwd_any<double>(S, L, pm, twM, st);
 }
+static size_t col_r16_lds(const Layout &L) { return (size_t)L.C * (L.M + L.M / 16) * sizeof(cf); }
+
 hipError_t launch_col_fwd_f(cf *S, const Layout &L, const FftPlan &pm, const cf *twM, hipStream_t st) {
+  if (reg_plan_ok(L.M)) {
+    const RegPlan rp = make_reg_plan(L.M);
+    const size_t lds = col_r16_lds(L);
+    hipError_t e = set_lds(k_col_fwd_r16<false>, lds);
+    if (e != hipSuccess) return e;
+    LamBuffers none = {};
+    hipLaunchKernelGGL(k_col_fwd_r16<false>, dim3(L.NT), dim3(L.C * rp.T), lds, st, S, nullptr, nullptr, nullptr, L, rp,
+                       twM, none);
+    return hipGetLastError();
+  }
   return col_fwd_any<float>(S, L, pm, twM, st);
 }
 
 hipError_t launch_col_fwd_resid(cf *S, float *q, const cf *H, const cf *Y, const Layout &L, const FftPlan &pm,
                                 const cf *twM, const LamBuffers &lb, hipStream_t st) {
+  if (reg_plan_ok(L.M)) {
+    const RegPlan rp = make_reg_plan(L.M);
+    const size_t lds = col_r16_lds(L);
+    hipError_t e = set_lds(k_col_fwd_r16<true>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_col_fwd_r16<true>, dim3(L.NT), dim3(L.C * rp.T), lds, st, S, q, H, Y, L, rp, twM, lb);
+    hipLaunchKernelGGL(k_lam_begin, dim3(1), dim3(256), 0, st, lb, L.NT);
+    return hipGetLastError();
+  }
   int threads;
   int E = pick_E((size_t)L.M * L.C, threads);
   size_t lds = (size_t)L.M * L.C * sizeof(cf);
-  hipLaunchKernelGGL(k_state_begin_iter, dim3(1), dim3(64), 0, st, lb.st);
   GFD_DISPATCH_E(E, {
     auto kern = k_col_fwd_resid<EE>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(L.NT), dim3(threads), lds, st, S, q, H, Y, L, pm, twM, lb);
   });
+  hipLaunchKernelGGL(k_lam_begin, dim3(1), dim3(256), 0, st, lb, L.NT);
   return hipGetLastError();
 }
 
 int lam_sweep_blocks(size_t nbins) {
   size_t want = (nbins / 4 + 255) / 256;
   if (want < 1) want = 1;
-  if (want > 1024) want = 1024;
+  if (want > 512) want = 512;
   return (int)want;
 }
 
 hipError_t launch_lam_sweep(const float *q, const float *H2, size_t nbins, const LamBuffers &lb, int last,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_lam_sweep<kLamMaxCand>, dim3(lam_sweep_blocks(nbins)), dim3(256), 0, st, q, H2, nbins, lb,
-                     last);
+  const int nb = lam_sweep_blocks(nbins);
+  hipLaunchKernelGGL(k_lam_sweep<kLamMaxCand>, dim3(nb), dim3(256), 0, st, q, H2, nbins, lb);
+  hipLaunchKernelGGL(k_lam_round, dim3(1), dim3(256), 0, st, lb, nb, last);
   return hipGetLastError();
 }
 
 hipError_t launch_col_inv(const cf *UE, const cf *HY, const float *H2, const float *dM, const float *dN,
                           const Layout &L, const FftPlan &pm, const cf *twM, const LamBuffers &lb, cf *SI, cf *SP,
                           hipStream_t st) {
+  if (reg_plan_ok(L.M)) {
+    const RegPlan rp = make_reg_plan(L.M);
+    const size_t lds = col_r16_lds(L);
+    hipError_t e = set_lds(k_col_inv_r16, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_col_inv_r16, dim3(L.NT), dim3(L.C * rp.T), lds, st, UE, HY, H2, dM, dN, L, rp, twM, lb.st, SI,
+                       SP);
+    return hipGetLastError();
+  }
   int threads;
   int E = pick_E((size_t)L.M * L.C, threads);
   size_t lds = (size_t)L.M * L.C * sizeof(cf);
@@ -734,6 +1007,15 @@ hipError_t launch_col_inv(const cf *UE, const cf *HY, const float *H2, const flo
 
 hipError_t launch_row_inv(const cf *SI, const cf *SP, const Layout &L, const FftPlan &pn, const cf *twN, float *uI,
                           float *uP, hipStream_t st) {
+  if (reg_plan_ok(L.N)) {
+    const RegPlan rp = make_reg_plan(L.N);
+    const size_t lds = (size_t)L.Ri * (L.N + L.N / 16) * sizeof(cf);
+    hipError_t e = set_lds(k_row_inv_r16, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_inv_r16, dim3((L.M + L.Ri - 1) / L.Ri), dim3(L.Ri * rp.T), lds, st, SI, SP, L, rp, twN, uI,
+                       uP);
+    return hipGetLastError();
+  }
   int threads;
   int E = pick_E((size_t)L.R * L.N, threads);
   size_t lds = (size_t)L.R * (L.N + 1) * sizeof(cf);

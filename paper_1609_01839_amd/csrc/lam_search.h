@@ -43,6 +43,7 @@ struct LamState {
   float Einf;        // ||h * u_E - y||^2 of this iteration
   float lam_star, lam;
   float lam_prev;    // last finite lambda_star (0 = none): centre of the first candidates
+  float lam_prev2;   // the one before (0 = none): their ratio sets the first spacing
   // bracket
   int haslo, hashi;
   float llo, lhi, Flo, Fhi, Dlo, Dhi;
@@ -51,7 +52,6 @@ struct LamState {
   float mu[kLamMaxCand];  // 1 / cand
   // offsets subtracted from u_I and u_p inside the guided filter (their means)
   float meanI, meanP;
-  unsigned arrive;   // arrival counter of the last-block reductions
 };
 
 GFD_HD inline float lam_relF(float hi, float lo, float TP) {
@@ -68,13 +68,16 @@ GFD_HD inline void lam_set_cand(LamState &s, int n, const float *c) {
   }
 }
 
-// First candidates of an iteration: around the previous lambda_star when there is one,
-// otherwise spread over the whole admissible range.
+// First candidates of an iteration: around the previous lambda_star when there is one, spaced
+// by the size of the last change (so that a settled sequence is bracketed tightly and a jump
+// is still caught), otherwise spread over the whole admissible range.
 GFD_HD inline void lam_first_candidates(LamState &s) {
   float c[kLamFirstCand];
   if (s.lam_prev > 0.0f) {
+    float sp = 1.0f;
+    if (s.lam_prev2 > 0.0f) sp = fminf(fmaxf(1.5f * fabsf(logf(s.lam_prev / s.lam_prev2)), 0.02f), 1.0f);
     for (int j = 0; j < kLamFirstCand; ++j)
-      c[j] = s.lam_prev * expf(0.5f * ((float)j - 0.5f * (kLamFirstCand - 1)));
+      c[j] = s.lam_prev * expf(sp * ((float)j - 0.5f * (kLamFirstCand - 1)));
   } else {
     const float x0 = logf(kLamFloor), x1 = logf(kLamCeil);
     for (int j = 0; j < kLamFirstCand; ++j)
@@ -138,7 +141,9 @@ GFD_HD inline int lam_decide(LamState &s, bool last) {
     }
     float est, width;
     float err = lam_estimate(s, est, width);
-    if (last || width <= 1e-6f || (err <= 1e-6f && width <= 0.05f)) {
+    // The secant-Hermite gap err is the secant's error; the Hermite estimate's own error is of
+    // the order of err^2 once the bracket is narrow enough for ln f to be smooth across it.
+    if (last || width <= 1e-6f || (err <= 1e-4f && width <= 0.05f)) {
       s.lam_star = est;
       s.phase = 1;
       return 1;

@@ -61,7 +61,7 @@ def test_fft_round_trip(M, N):
 
 
 GF_CASES = [(64, 64, 1), (64, 64, 3), (100, 130, 5), (256, 256, 7), (120, 96, 9), (480, 640, 17), (37, 41, 17),
-            (8, 300, 5), (1024, 1024, 17)]
+            (8, 300, 5), (1024, 1024, 17), (200, 260, 11), (150, 333, 13), (97, 512, 15)]
 
 
 @pytest.mark.parametrize("M,N,w", GF_CASES)
