@@ -34,7 +34,7 @@ typedef int gfd_status;
 
 enum {
   GFD_OK = 0,
-  GFD_ERR_ARG = -1,           /* invalid argument (NULL pointer, w even, eps < 0, ...) */
+  GFD_ERR_ARG = -1,           /* invalid argument (NULL pointer, w even, eps <= 0, ...) */
   GFD_ERR_SIZE = -2,          /* unsupported image or PSF size */
   GFD_ERR_HIP = -3,           /* a HIP runtime call failed */
   GFD_ERR_NOMEM = -4,         /* device allocation failed */
@@ -57,13 +57,47 @@ enum {
  *          (i - kh/2, j - kw/2).  Its sum must be non-zero (the solve for u_I divides by F(h) at
  *          the zero frequency).
  *   sigma2 noise variance, >= 0 (on the same intensity scale as y).
- *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N)) and regulariser (>= 0, finite).
+ *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N)) and regulariser (> 0, finite).
  *   rho    discrepancy factor of the set K (Sec. 3.2), 0 < rho <= 1; rho <= 0 selects Eq.(12).
  * The estimate starts at u_E = 0 (Step 0).  Allocates device memory; synchronises `stream`
  * once at the end so that *out is ready.  *out is untouched on error.
  */
 gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float *h, int kh, int kw,
                        double sigma2, int w, float eps, double rho, void *stream);
+
+/*
+ * gfd_image -- one image of a batch: the arguments of deconv_init, same meaning and rules.
+ */
+typedef struct gfd_image {
+  const float *y; /* device, M x N */
+  int M, N;
+  const float *h; /* device, kh x kw */
+  int kh, kw;
+  double sigma2;
+  int w;
+  float eps;
+  double rho;
+} gfd_image;
+
+/*
+ * deconv_init_batch -- one context for `count` independent images (1 <= count <= 4096), each
+ * deconvolved exactly as by its own deconv_init context (Sec. 3.1 per image, its own lambda).
+ *   images  host array of `count` descriptors, read during the call only.
+ * Every pass of an iteration is one launch over all images (per kernel variant: images are
+ * grouped by transform kind and filter radius), so a batch of small images fills the device.
+ * On a batch context:
+ *   deconv_iterate's u_out holds the estimates one after another in image order (image b
+ *   starts at sum_{c<b} M_c N_c floats) and lambda_out is count x n_iter, image-major;
+ *   deconv_set_estimate takes the same concatenated layout; deconv_set_scales applies the
+ *   scales to every image; deconv_get_status ORs the flags of all images; deconv_info reports
+ *   image 0 (deconv_image_info any image).  spectral_solve and discrepancy_lambda need a
+ *   single-image context (GFD_ERR_STATE otherwise).
+ * Errors name the index of the first offending descriptor; nothing is allocated on error.
+ */
+gfd_status deconv_init_batch(gfd_ctx **out, const gfd_image *images, int count, void *stream);
+
+/* deconv_image_info -- size, rho and target rho*P*sigma^2 of image `index` of the context. */
+gfd_status deconv_image_info(gfd_ctx *ctx, int index, int *M, int *N, double *rho, double *target);
 
 /*
  * deconv_iterate -- run n_iter iterations of Steps 1-3 (Sec. 3.1) from the current estimate.

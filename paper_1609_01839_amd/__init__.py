@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["GFDError", "GFDeconv", "deconvolve", "guided_filter", "spectral_solve", "discrepancy_lambda",
+__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "deconvolve", "guided_filter", "spectral_solve", "discrepancy_lambda",
            "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,6 +31,8 @@ _vp, _i, _f, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double
 # name -> (restype, argtypes)
 EXPORTS = {
     "deconv_init": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _vp, _i, _i, _d, _i, _f, _d, _vp]),
+    "deconv_init_batch": (_i, [ctypes.POINTER(_vp), _vp, _i, _vp]),
+    "deconv_image_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "deconv_iterate": (_i, [_vp, _i, _vp, _vp, _vp]),
     "guided_filter": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
     "spectral_solve": (_i, [_vp, _vp, _f, _vp, _vp, _vp]),
@@ -45,6 +47,12 @@ EXPORTS = {
     "deconv_destroy": (None, [_vp]),
     "gfd_last_error": (ctypes.c_char_p, []),
 }
+
+
+class GfdImage(ctypes.Structure):
+    """``gfd_image`` of the C ABI: one image of a batch."""
+    _fields_ = [("y", _vp), ("M", _i), ("N", _i), ("h", _vp), ("kh", _i), ("kw", _i), ("sigma2", _d), ("w", _i),
+                ("eps", _f), ("rho", _d)]
 
 
 class GFDError(RuntimeError):
@@ -183,6 +191,76 @@ class GFDeconv:
 
     def discrepancy_lambda(self, uE: torch.Tensor):
         return discrepancy_lambda(self, uE)
+
+
+class GFDeconvBatch(GFDeconv):
+    """Independent problems in one context: every pass of an iteration is one launch for all.
+
+    ``problems`` is a sequence of dicts with keys y, h, sigma2, w, eps and optionally rho (the
+    arguments of :class:`GFDeconv`).  Estimates are returned as a list of M_b x N_b views of
+    one flat tensor, lambdas as a (count, n) tensor.
+    """
+
+    def __init__(self, problems):
+        lib = load_library()
+        problems = list(problems)
+        if not problems:
+            raise ValueError("need at least one problem")
+        arr = (GfdImage * len(problems))()
+        self._keep = []
+        self.shapes = []
+        for b, pr in enumerate(problems):
+            y, h = pr["y"], pr["h"]
+            if y.dim() != 2 or h.dim() != 2:
+                raise ValueError("y and h must be 2-D")
+            M, N = (int(v) for v in y.shape)
+            rho = pr.get("rho")
+            arr[b] = GfdImage(_dev(y, f"y[{b}]"), M, N, _dev(h, f"h[{b}]"), int(h.shape[0]), int(h.shape[1]),
+                              float(pr["sigma2"]), int(pr["w"]), float(pr["eps"]), -1.0 if rho is None else float(rho))
+            self._keep += [y, h]
+            self.shapes.append((M, N))
+        self.count = len(problems)
+        self.device = problems[0]["y"].device
+        self.M, self.N = self.shapes[0]
+        self.total = sum(M * N for M, N in self.shapes)
+        ctx = _vp()
+        _check(lib.deconv_init_batch(ctypes.byref(ctx), ctypes.cast(arr, _vp), self.count, _stream(self.device)))
+        self._ctx = ctx
+
+    def split(self, flat: torch.Tensor):
+        out, off = [], 0
+        for M, N in self.shapes:
+            out.append(flat[off:off + M * N].view(M, N))
+            off += M * N
+        return out
+
+    def iterate(self, n: int, out: torch.Tensor | None = None, lambdas: torch.Tensor | None = None):
+        """Run n iterations of every problem; returns (list of estimates, (count, n) lambdas)."""
+        out = torch.empty((self.total,), device=self.device, dtype=torch.float32) if out is None else out
+        lambdas = (torch.empty((self.count, max(n, 0)), device=self.device, dtype=torch.float32)
+                   if lambdas is None else lambdas)
+        _check(load_library().deconv_iterate(self.handle, int(n), _dev(out, "out", (self.total,)),
+                                             _dev(lambdas, "lambdas", (self.count, n)) if n > 0 else None,
+                                             _stream(self.device)))
+        return self.split(out), lambdas
+
+    def set_estimate(self, estimates):
+        flat = torch.cat([u.reshape(-1) for u in estimates]).contiguous()
+        _check(load_library().deconv_set_estimate(self.handle, _dev(flat, "estimates", (self.total,)),
+                                                  _stream(self.device)))
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def image_info(self, b: int):
+        M, N, rho, T = _i(), _i(), _d(), _d()
+        _check(load_library().deconv_image_info(self.handle, int(b), ctypes.byref(M), ctypes.byref(N),
+                                                ctypes.byref(rho), ctypes.byref(T)))
+        return {"M": M.value, "N": N.value, "rho": rho.value, "target": T.value}
+
+    def spectral_solve(self, uE, lam):
+        raise GFDError(-5, "spectral_solve needs a single-image context")
+
+    def discrepancy_lambda(self, uE):
+        raise GFDError(-5, "discrepancy_lambda needs a single-image context")
 
 
 def deconvolve(y, h, sigma2, w, eps, iters, rho=None, scales=None):

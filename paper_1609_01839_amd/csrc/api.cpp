@@ -1,11 +1,17 @@
 // C ABI of the library: argument checks, context lifetime, per-image set-up, the iteration
-// (eager or as a replayed HIP graph) and the stand-alone entry points.  See gfdeconv.h.
+// (eager or as a replayed HIP graph) and the stand-alone entry points.
+//
+// A context holds one or more images.  Their device descriptors sit in one table and every
+// pass of the iteration is a single launch per kernel variant over the work items of all
+// images (plan builders in kernels_spec.hip / kernels_gf.hip), so a batch costs as many
+// launches per iteration as one image.
 #include <math.h>
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <set>
 #include <string>
@@ -14,41 +20,41 @@
 #include "../../include/gfdeconv.h"
 #include "gfd_internal.h"
 
-namespace gfd {
-hipError_t launch_state_set_lam(LamState *st, float lam, hipStream_t s);
-hipError_t launch_copy_lam_star(const LamState *st, float *out, hipStream_t s);
-}  // namespace gfd
-
 using namespace gfd;
 
-static const uint64_t kMagic = 0x6766646563763031ull;  // "gfdecv01"
-static const int kSweeps = 3;      // lambda evaluation rounds per iteration after the first (graph)
-static const int kSweepsFull = 10; // rounds of a stand-alone search (cold start allowed)
+static const uint64_t kMagic = 0x6766646563763032ull;  // "gfdecv02"
+static const int kSweeps = 3;       // lambda evaluation rounds per iteration after the first
+static const int kSweepsFull = 10;  // rounds of a stand-alone search (cold start allowed)
+static const int kMaxImages = 4096;
+static const int kStages = 6;
 
-struct gfd_ctx {
-  uint64_t magic;
-  int device;
+struct ImgMeta {
   int M, N, w;
   float eps;
   double sigma2, rho, T;
-  Layout lay;
-  FftPlan pm, pn;
-  cf *twM, *twN;
-  cf *H, *Y, *HY;
-  float *H2, *dM, *dN;
-  float *uE, *uI, *uP, *q;
-  cf *S1, *SI, *SP;
-  LamState *st, *st_aux;
-  float *partials;
-  float *lam_hist, *lam_hist_aux;
-  int *flag_hist, *flag_hist_aux;
-  float *scales;
-  double *rho_out;
-  int hist_cap;
-  int iters;
-  int use_graph;
-  hipGraphExec_t gexec;
-  hipStream_t cap_stream;
+};
+
+struct gfd_ctx {
+  uint64_t magic = 0;
+  int device = 0;
+  int count = 0;
+  std::vector<ImgMeta> meta;
+  ImgSet main, aux;  // aux: single-image contexts only (stand-alone solve and search)
+  Plan stage[kStages];
+  Plan iter, warm, aux_solve, aux_lam;
+  std::vector<void *> allocs;  // every device allocation of the context
+  LamState *st = nullptr;      // count states
+  LamState *st_aux = nullptr;
+  float *lam_hist = nullptr;   // count x hist_cap
+  int *flag_hist = nullptr;
+  float *scales = nullptr;     // hist_cap, shared by all images
+  float *uE_aux = nullptr;
+  double *rho_out = nullptr;   // 2 per image
+  int hist_cap = 0;
+  int iters = 0;
+  int use_graph = 1;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
 };
 
 static thread_local std::string g_err;
@@ -65,9 +71,9 @@ static gfd_status fail(gfd_status code, const char *fmt, ...) {
   return code;
 }
 
-#define HIPCHK(call)                                                                           \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
+#define HIPCHK(call)                                                                               \
+  do {                                                                                             \
+    hipError_t e_ = (call);                                                                        \
     if (e_ != hipSuccess) return fail(GFD_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
@@ -86,20 +92,23 @@ static bool live(gfd_ctx *c) {
 static void free_ctx(gfd_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  void *ptrs[] = {c->twM, c->twN, c->H, c->Y, c->HY, c->H2, c->dM, c->dN, c->uE, c->uI, c->uP, c->q, c->S1, c->SI,
-                  c->SP, c->st, c->st_aux, c->partials, c->lam_hist, c->lam_hist_aux, c->flag_hist,
-                  c->flag_hist_aux, c->scales, c->rho_out};
-  for (void *p : ptrs)
+  for (void *p : c->allocs)
     if (p) (void)hipFree(p);
+  for (ImgSet *s : {&c->main, &c->aux}) {
+    if (s->dev) (void)hipFree(s->dev);
+    if (s->items_dev) (void)hipFree(s->items_dev);
+  }
   c->magic = 0;
   delete c;
 }
 
 template <class T>
-static hipError_t dalloc(T **p, size_t count) {
+static hipError_t dalloc(gfd_ctx *c, T **p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  return hipMalloc((void **)p, count * sizeof(T));
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e == hipSuccess) c->allocs.push_back((void *)*p);
+  return e;
 }
 
 static std::vector<double> twiddles(int L) {
@@ -112,75 +121,57 @@ static std::vector<double> twiddles(int L) {
   return t;
 }
 
-static LamBuffers lam_buffers(gfd_ctx *c, bool aux) {
-  LamBuffers lb;
-  lb.st = aux ? c->st_aux : c->st;
-  lb.partials = c->partials;
-  lb.lam_hist = aux ? c->lam_hist_aux : c->lam_hist;
-  lb.flag_hist = aux ? c->flag_hist_aux : c->flag_hist;
-  lb.scales = aux ? nullptr : c->scales;
-  lb.hist_cap = aux ? 1 : c->hist_cap;
-  return lb;
+static hipError_t upload_table(ImgSet &set) {
+  if (!set.dev) {
+    hipError_t e = hipMalloc((void **)&set.dev, std::max<size_t>(set.imgs.size(), 1) * sizeof(Img));
+    if (e != hipSuccess) {
+      set.dev = nullptr;
+      return e;
+    }
+  }
+  return hipMemcpy(set.dev, set.imgs.data(), set.imgs.size() * sizeof(Img), hipMemcpyHostToDevice);
 }
 
-// The work of one iteration, Steps 1-3 of Sec. 3.1.
-static hipError_t enqueue_iteration(gfd_ctx *c, hipStream_t s) {
-  const Layout &L = c->lay;
-  LamBuffers lb = lam_buffers(c, false);
-  hipError_t e;
-  if ((e = launch_row_fwd(c->uE, L, c->pn, c->twN, c->S1, s)) != hipSuccess) return e;
-  if ((e = launch_col_fwd_resid(c->S1, c->q, c->H, c->Y, L, c->pm, c->twM, lb, s)) != hipSuccess) return e;
-  for (int k = 0; k < kSweeps; ++k)
-    if ((e = launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweeps - 1, s)) != hipSuccess) return e;
-  if ((e = launch_col_inv(c->S1, c->HY, c->H2, c->dM, c->dN, L, c->pm, c->twM, lb, c->SI, c->SP, s)) != hipSuccess)
-    return e;
-  if ((e = launch_row_inv(c->SI, c->SP, L, c->pn, c->twN, c->uI, c->uP, s)) != hipSuccess) return e;
-  return launch_guided_filter(c->uI, c->uP, c->uE, c->M, c->N, c->w, c->eps, &c->st->meanI, &c->st->meanP,
-                              c->st, s);
+static void append(Plan &dst, const Plan &src) {
+  dst.steps.insert(dst.steps.end(), src.steps.begin(), src.steps.end());
 }
 
-// The same launches as enqueue_iteration with an event recorded after each pass.
-static hipError_t enqueue_iteration_timed(gfd_ctx *c, hipStream_t s, hipEvent_t *ev) {
-  const Layout &L = c->lay;
-  LamBuffers lb = lam_buffers(c, false);
-  hipError_t e;
-  if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-  if ((e = launch_row_fwd(c->uE, L, c->pn, c->twN, c->S1, s)) != hipSuccess) return e;
-  if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-  if ((e = launch_col_fwd_resid(c->S1, c->q, c->H, c->Y, L, c->pm, c->twM, lb, s)) != hipSuccess) return e;
-  if ((e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-  for (int k = 0; k < kSweeps; ++k)
-    if ((e = launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweeps - 1, s)) != hipSuccess) return e;
-  if ((e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
-  if ((e = launch_col_inv(c->S1, c->HY, c->H2, c->dM, c->dN, L, c->pm, c->twM, lb, c->SI, c->SP, s)) != hipSuccess)
-    return e;
-  if ((e = hipEventRecord(ev[4], s)) != hipSuccess) return e;
-  if ((e = launch_row_inv(c->SI, c->SP, L, c->pn, c->twN, c->uI, c->uP, s)) != hipSuccess) return e;
-  if ((e = hipEventRecord(ev[5], s)) != hipSuccess) return e;
-  if ((e = launch_guided_filter(c->uI, c->uP, c->uE, c->M, c->N, c->w, c->eps, &c->st->meanI, &c->st->meanP,
-                                c->st, s)) != hipSuccess)
-    return e;
-  return hipEventRecord(ev[6], s);
-}
-
-// Lambda search for the current estimate outside the graph, with enough rounds for a cold start;
-// leaves lambda_star as the warm start of the next iteration (the iteration count is unchanged).
-static hipError_t enqueue_warm_start(gfd_ctx *c, hipStream_t s) {
-  const Layout &L = c->lay;
-  LamBuffers lb = lam_buffers(c, false);
-  hipError_t e;
-  if ((e = launch_row_fwd(c->uE, L, c->pn, c->twN, c->S1, s)) != hipSuccess) return e;
-  if ((e = launch_col_fwd_resid(c->S1, c->q, c->H, c->Y, L, c->pm, c->twM, lb, s)) != hipSuccess) return e;
-  for (int k = 0; k < kSweepsFull; ++k)
-    if ((e = launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweepsFull - 1, s)) != hipSuccess) return e;
-  return hipSuccess;
+// Launch plans of the context: the six passes of an iteration (Steps 1-3 of Sec. 3.1), the
+// warm-start search and, for one image, the stand-alone solve and search.
+static hipError_t build_plans(gfd_ctx *c) {
+  std::vector<int> all(c->count);
+  for (int i = 0; i < c->count; ++i) all[i] = i;
+  plan_row_fwd(c->stage[0], c->main, all);
+  plan_col_fwd(c->stage[1], c->main, all, true);
+  plan_lambda(c->stage[2], c->main, all, kSweeps);
+  plan_col_inv(c->stage[3], c->main, all);
+  plan_row_inv(c->stage[4], c->main, all);
+  plan_guided_filter(c->stage[5], c->main, all, true);
+  for (int k = 0; k < kStages; ++k) append(c->iter, c->stage[k]);
+  append(c->warm, c->stage[0]);
+  append(c->warm, c->stage[1]);
+  plan_lambda(c->warm, c->main, all, kSweepsFull);
+  hipError_t e = finalize_items(c->main);
+  if (e != hipSuccess) return e;
+  if (c->count == 1) {
+    const std::vector<int> one{0};
+    plan_row_fwd(c->aux_solve, c->aux, one);
+    plan_col_fwd(c->aux_solve, c->aux, one, false);
+    plan_col_inv(c->aux_solve, c->aux, one);
+    plan_row_inv(c->aux_solve, c->aux, one);
+    plan_row_fwd(c->aux_lam, c->aux, one);
+    plan_col_fwd(c->aux_lam, c->aux, one, true);
+    plan_lambda(c->aux_lam, c->aux, one, kSweepsFull);
+    e = finalize_items(c->aux);
+  }
+  return e;
 }
 
 static gfd_status capture_graph(gfd_ctx *c) {
   if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = enqueue_iteration(c, c->cap_stream);
+  hipError_t e = c->iter.enqueue(c->cap_stream);
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -196,133 +187,209 @@ static gfd_status capture_graph(gfd_ctx *c) {
   return GFD_OK;
 }
 
-extern "C" {
-
-const char *gfd_last_error(void) { return g_err.c_str(); }
-
-gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float *h, int kh, int kw, double sigma2,
-                       int w, float eps, double rho, void *stream) {
-  g_err.clear();
-  if (!out) return fail(GFD_ERR_ARG, "out is NULL");
-  if (!y || !h) return fail(GFD_ERR_ARG, "y and h must be device pointers");
+static gfd_status check_image(const gfd_image &d, int idx) {
+  const int M = d.M, N = d.N;
+  if (!d.y || !d.h) return fail(GFD_ERR_ARG, "image %d: y and h must be device pointers", idx);
   if (!size_ok(M) || !size_ok(N))
-    return fail(GFD_ERR_SIZE, "M=%d, N=%d: each must be 2^a 3^b 5^c in [2, 4096]", M, N);
-  if (kh < 1 || kw < 1 || kh % 2 == 0 || kw % 2 == 0 || kh > M || kw > N)
-    return fail(GFD_ERR_SIZE, "PSF %dx%d: sides must be odd and at most the image sides", kh, kw);
-  if (!(sigma2 >= 0.0) || !isfinite(sigma2)) return fail(GFD_ERR_ARG, "sigma2 must be finite and >= 0");
-  if (w < 1 || w % 2 == 0 || w > M || w > N) return fail(GFD_ERR_ARG, "w=%d must be odd, 1 <= w <= min(M, N)", w);
-  if (!(eps > 0.0f) || !isfinite(eps)) return fail(GFD_ERR_ARG, "eps must be finite and > 0");
-  if (!(rho <= 1.0) || !isfinite(rho)) return fail(GFD_ERR_ARG, "rho must be <= 1 (<= 0 selects Eq.(12))");
-  if (!guided_filter_supported(w)) return fail(GFD_ERR_UNIMPLEMENTED, "w=%d: windows wider than 17 are not built", w);
-  hipStream_t s = (hipStream_t)stream;
-  // the PSF sum decides solvability at the zero frequency: read the (small) PSF first
-  std::vector<float> hh((size_t)kh * kw);
-  HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipMemcpy(hh.data(), h, hh.size() * sizeof(float), hipMemcpyDeviceToHost));
-  double hsum = 0.0;
-  for (float v : hh) {
-    if (!isfinite(v)) return fail(GFD_ERR_ARG, "PSF has a non-finite entry");
-    hsum += v;
-  }
-  if (hsum == 0.0) return fail(GFD_ERR_ARG, "PSF sums to zero");
+    return fail(GFD_ERR_SIZE, "image %d: M=%d, N=%d: each must be 2^a 3^b 5^c in [2, 4096]", idx, M, N);
+  if (d.kh < 1 || d.kw < 1 || d.kh % 2 == 0 || d.kw % 2 == 0 || d.kh > M || d.kw > N)
+    return fail(GFD_ERR_SIZE, "image %d: PSF %dx%d: sides must be odd and at most the image sides", idx, d.kh, d.kw);
+  if (!(d.sigma2 >= 0.0) || !isfinite(d.sigma2)) return fail(GFD_ERR_ARG, "image %d: sigma2 must be finite and >= 0", idx);
+  if (d.w < 1 || d.w % 2 == 0 || d.w > M || d.w > N)
+    return fail(GFD_ERR_ARG, "image %d: w=%d must be odd, 1 <= w <= min(M, N)", idx, d.w);
+  if (!(d.eps > 0.0f) || !isfinite(d.eps)) return fail(GFD_ERR_ARG, "image %d: eps must be finite and > 0", idx);
+  if (!(d.rho <= 1.0) || !isfinite(d.rho))
+    return fail(GFD_ERR_ARG, "image %d: rho must be <= 1 (<= 0 selects Eq.(12))", idx);
+  if (!guided_filter_supported(d.w))
+    return fail(GFD_ERR_UNIMPLEMENTED, "image %d: w=%d: windows wider than 17 are not built", idx, d.w);
+  return GFD_OK;
+}
 
-  gfd_ctx *c = new gfd_ctx;
-  memset(c, 0, sizeof(*c));
-  c->magic = kMagic;
-  HIPCHK(hipGetDevice(&c->device));
-  c->M = M;
-  c->N = N;
-  c->w = w;
-  c->eps = eps;
-  c->sigma2 = sigma2;
-  c->lay = make_layout(M, N);
-  c->pm = make_plan(M);
-  c->pn = make_plan(N);
-  c->hist_cap = 1024;
-  c->use_graph = 1;
-  const Layout &L = c->lay;
+// Device buffers and FP64 set-up of image i (F(h), F(y), constants, rho and the target).
+static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream_t s, double *hp, cd *Hd, cd *Yd,
+                              double *work) {
+  const int M = src.M, N = src.N;
+  Img d;
+  memset(&d, 0, sizeof(d));
+  d.L = make_layout(M, N);
+  d.pm = make_plan(M);
+  d.pn = make_plan(N);
+  d.rm = make_reg_plan(reg_plan_ok(M) ? M : 256);
+  d.rn = make_reg_plan(reg_plan_ok(N) ? N : 256);
+  d.w = src.w;
+  d.eps = src.eps;
+  const Layout &L = d.L;
   const size_t P = (size_t)M * N, nb = L.bins();
-  const int nparts = (int)std::max<size_t>((size_t)L.NT, 1024);
+  d.nchunk = lam_sweep_chunks(nb);
+  d.npart = std::max(L.NT, d.nchunk);
+  cf *twM, *twN, *H, *Y, *HY, *S1, *SI, *SP;
+  float *H2, *dM, *dN, *uE, *uI, *uP, *q, *part;
+  cd *twMd, *twNd;
   hipError_t e = hipSuccess;
 #define ALLOC(ptr, n) \
-  if (e == hipSuccess) e = dalloc(&(ptr), (n))
-  ALLOC(c->twM, M);
-  ALLOC(c->twN, N);
-  ALLOC(c->H, nb);
-  ALLOC(c->Y, nb);
-  ALLOC(c->HY, nb);
-  ALLOC(c->H2, nb);
-  ALLOC(c->dM, M);
-  ALLOC(c->dN, L.Wh);
-  ALLOC(c->uE, P);
-  ALLOC(c->uI, P);
-  ALLOC(c->uP, P);
-  ALLOC(c->q, nb);
-  ALLOC(c->S1, nb);
-  ALLOC(c->SI, nb);
-  ALLOC(c->SP, nb);
-  ALLOC(c->st, 1);
-  ALLOC(c->st_aux, 1);
-  ALLOC(c->partials, (size_t)nparts * kLamAcc * 2);
-  ALLOC(c->lam_hist, c->hist_cap);
-  ALLOC(c->flag_hist, c->hist_cap);
-  ALLOC(c->lam_hist_aux, 1);
-  ALLOC(c->flag_hist_aux, 1);
-  ALLOC(c->scales, c->hist_cap);
-  ALLOC(c->rho_out, 2);
-  // FP64 temporaries of the set-up
-  double *hp = nullptr, *work = nullptr;
-  cd *Hd = nullptr, *Yd = nullptr, *twMd = nullptr, *twNd = nullptr;
-  ALLOC(hp, P);
-  ALLOC(work, 4 * 256);
-  ALLOC(Hd, nb);
-  ALLOC(Yd, nb);
+  if (e == hipSuccess) e = dalloc(c, &(ptr), (n))
+  ALLOC(twM, M);
+  ALLOC(twN, N);
+  ALLOC(H, nb);
+  ALLOC(Y, nb);
+  ALLOC(HY, nb);
+  ALLOC(H2, nb);
+  ALLOC(dM, M);
+  ALLOC(dN, L.Wh);
+  ALLOC(uE, P);
+  ALLOC(uI, P);
+  ALLOC(uP, P);
+  ALLOC(q, nb);
+  ALLOC(S1, nb);
+  ALLOC(SI, nb);
+  ALLOC(SP, nb);
+  ALLOC(part, (size_t)2 * kLamAcc * d.npart);
   ALLOC(twMd, M);
   ALLOC(twNd, N);
 #undef ALLOC
-  auto cleanup_tmp = [&]() {
-    void *t[] = {hp, work, Hd, Yd, twMd, twNd};
-    for (void *p : t)
-      if (p) (void)hipFree(p);
-  };
-  if (e != hipSuccess) {
-    cleanup_tmp();
-    free_ctx(c);
-    return fail(e == hipErrorOutOfMemory ? GFD_ERR_NOMEM : GFD_ERR_HIP, "allocation failed: %s",
-                hipGetErrorString(e));
-  }
+  if (e != hipSuccess) return e;
+  d.twM = twM;
+  d.twN = twN;
+  d.H = H;
+  d.Y = Y;
+  d.HY = HY;
+  d.H2 = H2;
+  d.dM = dM;
+  d.dN = dN;
+  d.uE = uE;
+  d.uI = uI;
+  d.uP = uP;
+  d.q = q;
+  d.S1 = S1;
+  d.SI = SI;
+  d.SP = SP;
+  d.part = part;
+  d.st = c->st + i;
+  d.lam_hist = c->lam_hist + (size_t)i * c->hist_cap;
+  d.flag_hist = c->flag_hist + (size_t)i * c->hist_cap;
+  d.scales = c->scales;
+  d.hist_cap = c->hist_cap;
+  gf_geometry(d);
   // twiddle tables, FP64 on the host
   std::vector<double> tm = twiddles(M), tn = twiddles(N);
   std::vector<float> tmf(tm.begin(), tm.end()), tnf(tn.begin(), tn.end());
   if (e == hipSuccess) e = hipMemcpy(twMd, tm.data(), tm.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(twNd, tn.data(), tn.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(c->twM, tmf.data(), tmf.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(c->twN, tnf.data(), tnf.size() * sizeof(float), hipMemcpyHostToDevice);
-  // F(h) and F(y) in FP64, then the FP32 constants
-  if (e == hipSuccess) e = launch_embed_psf(h, kh, kw, M, N, hp, s);
-  if (e == hipSuccess) e = launch_row_fwd_d(hp, L, c->pn, twNd, Hd, s);
-  if (e == hipSuccess) e = launch_col_fwd_d(Hd, L, c->pm, twMd, s);
-  if (e == hipSuccess) e = launch_row_fwd_fd(y, L, c->pn, twNd, Yd, s);
-  if (e == hipSuccess) e = launch_col_fwd_d(Yd, L, c->pm, twMd, s);
-  if (e == hipSuccess) e = launch_init_consts(Hd, Yd, L, c->H, c->Y, c->HY, c->H2, s);
-  if (e == hipSuccess) e = launch_d2_tables(M, N, L.Wh, c->dM, c->dN, s);
-  if (e == hipSuccess) e = launch_rho_target(y, M, N, h, kh, kw, sigma2, rho, work, c->rho_out, c->st, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->st_aux, c->st, sizeof(LamState), hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = launch_state_reset(c->st, s);
-  if (e == hipSuccess) e = launch_state_reset(c->st_aux, s);
-  if (e == hipSuccess) e = launch_fill_f(c->uE, P, 0.0f, s);
-  if (e == hipSuccess) e = launch_fill_f(c->scales, c->hist_cap, 1.0f, s);
-  if (e == hipSuccess) e = enqueue_warm_start(c, s);
+  if (e == hipSuccess) e = hipMemcpy(twM, tmf.data(), tmf.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(twN, tnf.data(), tnf.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_embed_psf(src.h, src.kh, src.kw, M, N, hp, s);
+  if (e == hipSuccess) e = launch_row_fwd_d(hp, L, d.pn, twNd, Hd, s);
+  if (e == hipSuccess) e = launch_col_fwd_d(Hd, L, d.pm, twMd, s);
+  if (e == hipSuccess) e = launch_row_fwd_fd(src.y, L, d.pn, twNd, Yd, s);
+  if (e == hipSuccess) e = launch_col_fwd_d(Yd, L, d.pm, twMd, s);
+  if (e == hipSuccess) e = launch_init_consts(Hd, Yd, L, H, Y, HY, H2, s);
+  if (e == hipSuccess) e = launch_d2_tables(M, N, L.Wh, dM, dN, s);
+  if (e == hipSuccess)
+    e = launch_rho_target(src.y, M, N, src.h, src.kh, src.kw, src.sigma2, src.rho, work, c->rho_out + 2 * i, d.st, s);
+  if (e == hipSuccess) e = launch_state_reset(d.st, s);
+  if (e == hipSuccess) e = launch_fill_f(uE, P, 0.0f, s);
+  // the FP64 temporaries are shared by the images: finish before the next image reuses them
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  double ro[2] = {0, 0};
-  if (e == hipSuccess) e = hipMemcpy(ro, c->rho_out, sizeof(ro), hipMemcpyDeviceToHost);
-  cleanup_tmp();
-  if (e != hipSuccess) {
-    free_ctx(c);
-    return fail(GFD_ERR_HIP, "set-up failed: %s", hipGetErrorString(e));
+  c->main.imgs.push_back(d);
+  ImgMeta m;
+  m.M = M;
+  m.N = N;
+  m.w = src.w;
+  m.eps = src.eps;
+  m.sigma2 = src.sigma2;
+  m.rho = 0.0;
+  m.T = 0.0;
+  c->meta.push_back(m);
+  return e;
+}
+
+static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, hipStream_t s) {
+  if (!out) return fail(GFD_ERR_ARG, "out is NULL");
+  if (!imgs || count < 1 || count > kMaxImages)
+    return fail(GFD_ERR_ARG, "need 1 <= count <= %d image descriptors", kMaxImages);
+  for (int i = 0; i < count; ++i) {
+    gfd_status rc = check_image(imgs[i], i);
+    if (rc != GFD_OK) return rc;
   }
-  c->rho = ro[0];
-  c->T = ro[1];
+  // the PSF sum decides solvability at the zero frequency: read the (small) PSFs first
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) {
+    std::vector<float> hh((size_t)imgs[i].kh * imgs[i].kw);
+    HIPCHK(hipMemcpy(hh.data(), imgs[i].h, hh.size() * sizeof(float), hipMemcpyDeviceToHost));
+    double hsum = 0.0;
+    for (float v : hh) {
+      if (!isfinite(v)) return fail(GFD_ERR_ARG, "image %d: PSF has a non-finite entry", i);
+      hsum += v;
+    }
+    if (hsum == 0.0) return fail(GFD_ERR_ARG, "image %d: PSF sums to zero", i);
+  }
+
+  gfd_ctx *c = new gfd_ctx;
+  c->magic = kMagic;
+  c->count = count;
+  c->hist_cap = 1024;
+  auto bail = [&](hipError_t e, const char *what) {
+    free_ctx(c);
+    return fail(e == hipErrorOutOfMemory ? GFD_ERR_NOMEM : GFD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return bail(e, "hipGetDevice");
+  size_t maxP = 0, maxB = 0;
+  for (int i = 0; i < count; ++i) {
+    maxP = std::max(maxP, (size_t)imgs[i].M * imgs[i].N);
+    maxB = std::max(maxB, make_layout(imgs[i].M, imgs[i].N).bins());
+  }
+  double *hp = nullptr, *work = nullptr;
+  cd *Hd = nullptr, *Yd = nullptr;
+  if (e == hipSuccess) e = dalloc(c, &c->st, count);
+  if (e == hipSuccess) e = dalloc(c, &c->lam_hist, (size_t)count * c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->flag_hist, (size_t)count * c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->scales, c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->rho_out, 2 * (size_t)count);
+  if (e == hipSuccess) e = dalloc(c, &hp, maxP);
+  if (e == hipSuccess) e = dalloc(c, &work, 4 * 256);
+  if (e == hipSuccess) e = dalloc(c, &Hd, maxB);
+  if (e == hipSuccess) e = dalloc(c, &Yd, maxB);
+  if (e == hipSuccess) e = launch_fill_f(c->scales, c->hist_cap, 1.0f, s);
+  if (e != hipSuccess) return bail(e, "allocation failed");
+  for (int i = 0; i < count && e == hipSuccess; ++i) e = setup_image(c, i, imgs[i], s, hp, Hd, Yd, work);
+  if (e != hipSuccess) return bail(e, "set-up failed");
+  // the shared FP64 temporaries are no longer needed
+  for (void *p : {(void *)hp, (void *)work, (void *)Hd, (void *)Yd}) {
+    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), p));
+    (void)hipFree(p);
+  }
+  if (count == 1) {
+    Img a = c->main.imgs[0];
+    if (e == hipSuccess) e = dalloc(c, &c->st_aux, 1);
+    if (e == hipSuccess) e = dalloc(c, &c->uE_aux, (size_t)a.L.M * a.L.N);
+    float *lh = nullptr;
+    int *fh = nullptr;
+    if (e == hipSuccess) e = dalloc(c, &lh, 1);
+    if (e == hipSuccess) e = dalloc(c, &fh, 1);
+    if (e != hipSuccess) return bail(e, "allocation failed");
+    a.uE = c->uE_aux;
+    a.st = c->st_aux;
+    a.lam_hist = lh;
+    a.flag_hist = fh;
+    a.hist_cap = 1;
+    a.scales = nullptr;
+    c->aux.imgs.push_back(a);
+    e = hipMemcpyAsync(c->st_aux, c->st, sizeof(LamState), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = launch_state_reset(c->st_aux, s);
+    if (e == hipSuccess) e = upload_table(c->aux);
+  }
+  if (e == hipSuccess) e = upload_table(c->main);
+  if (e == hipSuccess) e = build_plans(c);
+  if (e == hipSuccess) e = c->warm.enqueue(s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  std::vector<double> ro(2 * (size_t)count);
+  if (e == hipSuccess) e = hipMemcpy(ro.data(), c->rho_out, ro.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return bail(e, "set-up failed");
+  for (int i = 0; i < count; ++i) {
+    c->meta[i].rho = ro[2 * i];
+    c->meta[i].T = ro[2 * i + 1];
+  }
   {
     std::lock_guard<std::mutex> g(g_live_mu);
     g_live.insert(c);
@@ -331,6 +398,8 @@ gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float 
   return GFD_OK;
 }
 
+// Larger per-iteration histories; the descriptors are rewritten in place, so a captured
+// graph (which reads them at run time) stays valid.
 static gfd_status grow_history(gfd_ctx *c, int need) {
   if (need <= c->hist_cap) return GFD_OK;
   int cap = c->hist_cap;
@@ -338,26 +407,74 @@ static gfd_status grow_history(gfd_ctx *c, int need) {
   float *lh = nullptr, *sc = nullptr;
   int *fh = nullptr;
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMalloc((void **)&lh, cap * sizeof(float)));
-  HIPCHK(hipMalloc((void **)&fh, cap * sizeof(int)));
+  HIPCHK(hipMalloc((void **)&lh, (size_t)c->count * cap * sizeof(float)));
+  HIPCHK(hipMalloc((void **)&fh, (size_t)c->count * cap * sizeof(int)));
   HIPCHK(hipMalloc((void **)&sc, cap * sizeof(float)));
   HIPCHK(launch_fill_f(sc, cap, 1.0f, nullptr));
-  HIPCHK(hipMemcpy(lh, c->lam_hist, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
-  HIPCHK(hipMemcpy(fh, c->flag_hist, c->hist_cap * sizeof(int), hipMemcpyDeviceToDevice));
+  for (int i = 0; i < c->count; ++i) {
+    HIPCHK(hipMemcpy(lh + (size_t)i * cap, c->lam_hist + (size_t)i * c->hist_cap, c->hist_cap * sizeof(float),
+                     hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(fh + (size_t)i * cap, c->flag_hist + (size_t)i * c->hist_cap, c->hist_cap * sizeof(int),
+                     hipMemcpyDeviceToDevice));
+  }
   HIPCHK(hipMemcpy(sc, c->scales, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
   HIPCHK(hipDeviceSynchronize());
-  (void)hipFree(c->lam_hist);
-  (void)hipFree(c->flag_hist);
-  (void)hipFree(c->scales);
+  for (void *old : {(void *)c->lam_hist, (void *)c->flag_hist, (void *)c->scales}) {
+    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), old));
+    (void)hipFree(old);
+  }
+  c->allocs.push_back(lh);
+  c->allocs.push_back(fh);
+  c->allocs.push_back(sc);
   c->lam_hist = lh;
   c->flag_hist = fh;
   c->scales = sc;
   c->hist_cap = cap;
-  if (c->gexec) {  // the captured graph holds the old pointers
-    (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
+  for (int i = 0; i < c->count; ++i) {
+    Img &d = c->main.imgs[i];
+    d.lam_hist = lh + (size_t)i * cap;
+    d.flag_hist = fh + (size_t)i * cap;
+    d.scales = sc;
+    d.hist_cap = cap;
+  }
+  HIPCHK(upload_table(c->main));
+  return GFD_OK;
+}
+
+static gfd_status copy_estimates_out(gfd_ctx *c, float *u_out, hipStream_t s) {
+  size_t off = 0;
+  for (int i = 0; i < c->count; ++i) {
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+    HIPCHK(hipMemcpyAsync(u_out + off, c->main.imgs[i].uE, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    off += P;
   }
   return GFD_OK;
+}
+
+extern "C" {
+
+const char *gfd_last_error(void) { return g_err.c_str(); }
+
+gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float *h, int kh, int kw, double sigma2,
+                       int w, float eps, double rho, void *stream) {
+  g_err.clear();
+  gfd_image d;
+  d.y = y;
+  d.M = M;
+  d.N = N;
+  d.h = h;
+  d.kh = kh;
+  d.kw = kw;
+  d.sigma2 = sigma2;
+  d.w = w;
+  d.eps = eps;
+  d.rho = rho;
+  return init_common(out, &d, 1, (hipStream_t)stream);
+}
+
+gfd_status deconv_init_batch(gfd_ctx **out, const gfd_image *images, int count, void *stream) {
+  g_err.clear();
+  return init_common(out, images, count, (hipStream_t)stream);
 }
 
 gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_out, void *stream) {
@@ -373,12 +490,16 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
   }
   for (int i = 0; i < n_iter; ++i) {
     if (ctx->use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, s));
-    else HIPCHK(enqueue_iteration(ctx, s));
+    else HIPCHK(ctx->iter.enqueue(s));
   }
-  const size_t P = (size_t)ctx->M * ctx->N;
-  if (u_out) HIPCHK(hipMemcpyAsync(u_out, ctx->uE, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (u_out) {
+    rc = copy_estimates_out(ctx, u_out, s);
+    if (rc != GFD_OK) return rc;
+  }
   if (lambda_out && n_iter > 0)
-    HIPCHK(hipMemcpyAsync(lambda_out, ctx->lam_hist + ctx->iters, n_iter * sizeof(float), hipMemcpyDeviceToDevice, s));
+    for (int i = 0; i < ctx->count; ++i)
+      HIPCHK(hipMemcpyAsync(lambda_out + (size_t)i * n_iter, ctx->lam_hist + (size_t)i * ctx->hist_cap + ctx->iters,
+                            n_iter * sizeof(float), hipMemcpyDeviceToDevice, s));
   ctx->iters += n_iter;
   return GFD_OK;
 }
@@ -386,25 +507,29 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
 gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_stages, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
-  if (n_iter < 0 || n_stages < 0 || n_stages > 6 || (n_stages > 0 && !stage_ms_host))
+  if (n_iter < 0 || n_stages < 0 || n_stages > kStages || (n_stages > 0 && !stage_ms_host))
     return fail(GFD_ERR_ARG, "n_iter >= 0, 0 <= n_stages <= 6, stage_ms_host non-NULL");
   hipStream_t s = (hipStream_t)stream;
   gfd_status rc = grow_history(ctx, ctx->iters + n_iter);
   if (rc != GFD_OK) return rc;
-  hipEvent_t ev[7];
-  for (int i = 0; i < 7; ++i) HIPCHK(hipEventCreate(&ev[i]));
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  hipEvent_t ev[kStages + 1];
+  for (int i = 0; i <= kStages; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  double acc[kStages] = {0, 0, 0, 0, 0, 0};
   hipError_t e = hipSuccess;
   for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
-    e = enqueue_iteration_timed(ctx, s, ev);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
-    for (int k = 0; k < 6 && e == hipSuccess; ++k) {
+    e = hipEventRecord(ev[0], s);
+    for (int k = 0; k < kStages && e == hipSuccess; ++k) {
+      e = ctx->stage[k].enqueue(s);
+      if (e == hipSuccess) e = hipEventRecord(ev[k + 1], s);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[kStages]);
+    for (int k = 0; k < kStages && e == hipSuccess; ++k) {
       float ms = 0.0f;
       e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       acc[k] += ms;
     }
   }
-  for (int i = 0; i < 7; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i <= kStages; ++i) (void)hipEventDestroy(ev[i]);
   if (e != hipSuccess) return fail(GFD_ERR_HIP, "profiled iteration failed: %s", hipGetErrorString(e));
   ctx->iters += n_iter;
   for (int k = 0; k < n_stages; ++k) stage_ms_host[k] = (float)acc[k];
@@ -424,41 +549,38 @@ gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int 
   };
   if (overlap(u, uI) || overlap(u, up)) return fail(GFD_ERR_ARG, "u must not overlap uI or up");
   if (!guided_filter_supported(w)) return fail(GFD_ERR_UNIMPLEMENTED, "w=%d: windows wider than 17 are not built", w);
-  HIPCHK(launch_guided_filter(uI, up, u, M, N, w, eps, uI, up, nullptr, (hipStream_t)stream));
+  HIPCHK(launch_guided_filter_plain(uI, up, u, M, N, w, eps, (hipStream_t)stream));
   return GFD_OK;
 }
 
 gfd_status spectral_solve(gfd_ctx *ctx, const float *uE, float lambda, float *uI, float *up, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (ctx->count != 1) return fail(GFD_ERR_STATE, "spectral_solve needs a single-image context");
   if (!uE || !uI || !up) return fail(GFD_ERR_ARG, "uE, uI and up must be device pointers");
   if (!(lambda > 0.0f)) return fail(GFD_ERR_ARG, "lambda must be > 0 (or +inf)");
   hipStream_t s = (hipStream_t)stream;
-  gfd_ctx *c = ctx;
-  const Layout &L = c->lay;
-  LamBuffers lb = lam_buffers(c, true);
-  HIPCHK(launch_row_fwd(uE, L, c->pn, c->twN, c->S1, s));
-  HIPCHK(launch_col_fwd_f(c->S1, L, c->pm, c->twM, s));
-  HIPCHK(launch_state_set_lam(c->st_aux, lambda, s));
-  HIPCHK(launch_col_inv(c->S1, c->HY, c->H2, c->dM, c->dN, L, c->pm, c->twM, lb, c->SI, c->SP, s));
-  HIPCHK(launch_row_inv(c->SI, c->SP, L, c->pn, c->twN, uI, up, s));
+  const Img &a = ctx->aux.imgs[0];
+  const size_t bytes = (size_t)a.L.M * a.L.N * sizeof(float);
+  HIPCHK(hipMemcpyAsync(ctx->uE_aux, uE, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_state_set_lam(ctx->st_aux, lambda, s));
+  HIPCHK(ctx->aux_solve.enqueue(s));
+  HIPCHK(hipMemcpyAsync(uI, a.uI, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(up, a.uP, bytes, hipMemcpyDeviceToDevice, s));
   return GFD_OK;
 }
 
 gfd_status discrepancy_lambda(gfd_ctx *ctx, const float *uE, float *lambda_dev, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (ctx->count != 1) return fail(GFD_ERR_STATE, "discrepancy_lambda needs a single-image context");
   if (!uE || !lambda_dev) return fail(GFD_ERR_ARG, "uE and lambda_dev must be device pointers");
   hipStream_t s = (hipStream_t)stream;
-  gfd_ctx *c = ctx;
-  const Layout &L = c->lay;
-  LamBuffers lb = lam_buffers(c, true);
-  HIPCHK(launch_state_reset(c->st_aux, s));
-  HIPCHK(launch_row_fwd(uE, L, c->pn, c->twN, c->S1, s));
-  HIPCHK(launch_col_fwd_resid(c->S1, c->q, c->H, c->Y, L, c->pm, c->twM, lb, s));
-  for (int k = 0; k < kSweepsFull; ++k)
-    HIPCHK(launch_lam_sweep(c->q, c->H2, L.bins(), lb, k == kSweepsFull - 1, s));
-  HIPCHK(launch_copy_lam_star(c->st_aux, lambda_dev, s));
+  const Img &a = ctx->aux.imgs[0];
+  HIPCHK(hipMemcpyAsync(ctx->uE_aux, uE, (size_t)a.L.M * a.L.N * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_state_reset(ctx->st_aux, s));
+  HIPCHK(ctx->aux_lam.enqueue(s));
+  HIPCHK(launch_copy_lam_star(ctx->st_aux, lambda_dev, s));
   return GFD_OK;
 }
 
@@ -470,10 +592,10 @@ gfd_status deconv_set_scales(gfd_ctx *ctx, const float *s_dev, int n) {
   if (rc != GFD_OK) return rc;
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(launch_fill_f(ctx->scales, ctx->hist_cap, 1.0f, nullptr));
-  if (n > 0)
-    HIPCHK(hipMemcpy(ctx->scales + ctx->iters, s_dev, n * sizeof(float), hipMemcpyDeviceToDevice));
-  int ns = n > 0 ? ctx->iters + n : 0;
-  HIPCHK(hipMemcpy((char *)ctx->st + offsetof(LamState, nscale), &ns, sizeof(int), hipMemcpyHostToDevice));
+  if (n > 0) HIPCHK(hipMemcpy(ctx->scales + ctx->iters, s_dev, n * sizeof(float), hipMemcpyDeviceToDevice));
+  const int ns = n > 0 ? ctx->iters + n : 0;
+  for (int i = 0; i < ctx->count; ++i)
+    HIPCHK(hipMemcpy((char *)(ctx->st + i) + offsetof(LamState, nscale), &ns, sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipDeviceSynchronize());
   return GFD_OK;
 }
@@ -482,9 +604,14 @@ gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (!uE) return fail(GFD_ERR_ARG, "uE must be a device pointer");
-  HIPCHK(hipMemcpyAsync(ctx->uE, uE, (size_t)ctx->M * ctx->N * sizeof(float), hipMemcpyDeviceToDevice,
-                        (hipStream_t)stream));
-  HIPCHK(enqueue_warm_start(ctx, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  size_t off = 0;
+  for (int i = 0; i < ctx->count; ++i) {
+    const size_t P = (size_t)ctx->meta[i].M * ctx->meta[i].N;
+    HIPCHK(hipMemcpyAsync(ctx->main.imgs[i].uE, uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    off += P;
+  }
+  HIPCHK(ctx->warm.enqueue(s));
   return GFD_OK;
 }
 
@@ -492,9 +619,11 @@ gfd_status deconv_reset(gfd_ctx *ctx, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   hipStream_t s = (hipStream_t)stream;
-  HIPCHK(launch_fill_f(ctx->uE, (size_t)ctx->M * ctx->N, 0.0f, s));
-  HIPCHK(launch_state_reset(ctx->st, s));
-  HIPCHK(enqueue_warm_start(ctx, s));
+  for (int i = 0; i < ctx->count; ++i) {
+    HIPCHK(launch_fill_f(ctx->main.imgs[i].uE, (size_t)ctx->meta[i].M * ctx->meta[i].N, 0.0f, s));
+    HIPCHK(launch_state_reset(ctx->st + i, s));
+  }
+  HIPCHK(ctx->warm.enqueue(s));
   ctx->iters = 0;
   return GFD_OK;
 }
@@ -502,9 +631,21 @@ gfd_status deconv_reset(gfd_ctx *ctx, void *stream) {
 gfd_status deconv_info(gfd_ctx *ctx, double *rho, double *target, int *iterations) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
-  if (rho) *rho = ctx->rho;
-  if (target) *target = ctx->T;
+  if (rho) *rho = ctx->meta[0].rho;
+  if (target) *target = ctx->meta[0].T;
   if (iterations) *iterations = ctx->iters;
+  return GFD_OK;
+}
+
+gfd_status deconv_image_info(gfd_ctx *ctx, int index, int *M, int *N, double *rho, double *target) {
+  g_err.clear();
+  if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (index < 0 || index >= ctx->count) return fail(GFD_ERR_ARG, "index %d outside [0, %d)", index, ctx->count);
+  const ImgMeta &m = ctx->meta[index];
+  if (M) *M = m.M;
+  if (N) *N = m.N;
+  if (rho) *rho = m.rho;
+  if (target) *target = m.T;
   return GFD_OK;
 }
 
@@ -513,9 +654,14 @@ gfd_status deconv_get_status(gfd_ctx *ctx, unsigned *flags_host) {
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (!flags_host) return fail(GFD_ERR_ARG, "flags_host is NULL");
   HIPCHK(hipDeviceSynchronize());
-  unsigned f = 0;
-  HIPCHK(hipMemcpy(&f, (char *)ctx->st + offsetof(LamState, flags_all), sizeof(unsigned), hipMemcpyDeviceToHost));
-  *flags_host = f;
+  unsigned all = 0;
+  for (int i = 0; i < ctx->count; ++i) {
+    unsigned f = 0;
+    HIPCHK(hipMemcpy(&f, (char *)(ctx->st + i) + offsetof(LamState, flags_all), sizeof(unsigned),
+                     hipMemcpyDeviceToHost));
+    all |= f;
+  }
+  *flags_host = all;
   return GFD_OK;
 }
 

@@ -102,7 +102,7 @@ template <int R, int DIR, class T> __device__ __forceinline__ void dft(cpx<T> *v
 // consecutive sequences.  Otherwise consecutive threads take consecutive butterflies.
 template <class T, int R, int E, int DIR, bool COLMODE>
 __device__ __forceinline__ void stockham_pass(cpx<T> *buf, int nb, int lognb, int es, int bs,
-                                              const FftPlan &p, int q, const cpx<T> *__restrict__ tw) {
+                                              const FftPlan &p, int q, const GFD_AS1 cpx<T> *__restrict__ tw) {
   constexpr int NBF = (E + R - 1) / R;
   const int nthr = blockDim.x, tid = threadIdx.x;
   const int nbf = p.nbf[q];
@@ -157,8 +157,8 @@ __device__ __forceinline__ void stockham_pass(cpx<T> *buf, int nb, int lognb, in
 
 // Full transform; the caller has written the input to `buf` and synchronised.
 template <class T, int E, int DIR, bool COLMODE>
-__device__ void lds_fft(cpx<T> *buf, int nb, int lognb, int es, int bs, const FftPlan &p,
-                        const cpx<T> *__restrict__ tw) {
+__device__ __forceinline__ void lds_fft(cpx<T> *buf, int nb, int lognb, int es, int bs, const FftPlan &p,
+                        const GFD_AS1 cpx<T> *__restrict__ tw) {
   for (int q = 0; q < p.npass; ++q) {
     switch (p.radix[q]) {
       case 2: stockham_pass<T, 2, E, DIR, COLMODE>(buf, nb, lognb, es, bs, p, q, tw); break;

@@ -61,9 +61,10 @@ __device__ __forceinline__ void dftR(cf *x) {
 }
 
 // One pass.  `lds` addresses the sequence's region: slot(p) = lds[lds_pad(p) * ls].
+// Inactive threads (blocks sized for a larger image of a batch) only join the barriers.
 template <int R, int DIR>
-__device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L, bool last, cf *lds, int ls,
-                                         const cf *__restrict__ tw) {
+__device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L, bool last, bool active, cf *lds,
+                                         int ls, const GFD_AS1 cf *__restrict__ tw) {
   constexpr int NBF = 16 / R;
   const int tstride = L / (s * R);
 #pragma unroll
@@ -73,7 +74,7 @@ __device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L
     cf x[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) x[i] = v[b + i * NBF];
-    if (s > 1) {
+    if (s > 1 && active) {
 #pragma unroll
       for (int i = 1; i < R; ++i) {
         cf w = tw[i * k * tstride];
@@ -85,7 +86,7 @@ __device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L
     if (last) {
 #pragma unroll
       for (int i = 0; i < R; ++i) v[b + i * NBF] = x[i];
-    } else {
+    } else if (active) {
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int i = 0; i < R; ++i) lds[lds_pad(base + i * s) * ls] = x[i];
@@ -93,8 +94,10 @@ __device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L
   }
   if (!last) {
     __syncthreads();
+    if (active) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = lds[lds_pad(t + T * m) * ls];
+      for (int m = 0; m < 16; ++m) v[m] = lds[lds_pad(t + T * m) * ls];
+    }
     __syncthreads();
   }
 }
@@ -102,16 +105,16 @@ __device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L
 // Whole transform.  On entry v[m] = x[t + T m]; on exit v[m] = X[t + T m] (unnormalised).
 // Every thread of the block must call this (it contains barriers).
 template <int DIR>
-__device__ __forceinline__ void reg_fft(cf (&v)[16], int t, const RegPlan &p, cf *lds, int ls,
-                                        const cf *__restrict__ tw) {
+__device__ __forceinline__ void reg_fft(cf (&v)[16], int t, bool active, const RegPlan &p, cf *lds, int ls,
+                                        const GFD_AS1 cf *__restrict__ tw) {
   int s = 1;
   for (int q = 0; q < p.npass; ++q) {
     const bool last = q == p.npass - 1;
     switch (p.radix[q]) {
-      case 16: reg_pass<16, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
-      case 8: reg_pass<8, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
-      case 4: reg_pass<4, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
-      default: reg_pass<2, DIR>(v, t, p.T, s, p.L, last, lds, ls, tw); break;
+      case 16: reg_pass<16, DIR>(v, t, p.T, s, p.L, last, active, lds, ls, tw); break;
+      case 8: reg_pass<8, DIR>(v, t, p.T, s, p.L, last, active, lds, ls, tw); break;
+      case 4: reg_pass<4, DIR>(v, t, p.T, s, p.L, last, active, lds, ls, tw); break;
+      default: reg_pass<2, DIR>(v, t, p.T, s, p.L, last, active, lds, ls, tw); break;
     }
     s *= p.radix[q];
   }

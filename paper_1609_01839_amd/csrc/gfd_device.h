@@ -6,6 +6,18 @@
 
 namespace gfd {
 
+// Pointers loaded from device memory (descriptor tables) are generic to the compiler, which
+// then emits flat accesses with 64-bit VGPR addresses; G() marks them as global memory so
+// that loads and stores take an SGPR base and their own wait counter.  The qualifier exists
+// in the device pass only: the host pass parses kernel bodies but never generates them.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GFD_AS1 __attribute__((address_space(1)))
+#else
+#define GFD_AS1
+#endif
+template <class T> __device__ __forceinline__ GFD_AS1 T *G(T *p) { return (GFD_AS1 T *)p; }
+template <class T> __device__ __forceinline__ const GFD_AS1 T *G(const T *p) { return (const GFD_AS1 T *)p; }
+
 template <class T>
 struct alignas(2 * sizeof(T)) cpx {
   T re, im;

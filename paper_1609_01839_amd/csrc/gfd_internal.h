@@ -3,7 +3,11 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <functional>
+#include <vector>
+
 #include "fft_lds.h"
+#include "fft_reg.h"
 #include "lam_search.h"
 
 namespace gfd {
@@ -14,73 +18,108 @@ namespace gfd {
 // (m, c) of tile t at ((t * M) + m) * C + c.  Columns at or beyond Wh are zero padding.
 struct Layout {
   int M, N;
-  int Wh;        // N / 2 + 1
-  int C, logC;   // tile width (power of two)
-  int NT;        // number of tiles = ceil(Wh / C)
-  int R;         // image rows per block in the LDS-resident row passes (even)
-  int Rf, Ri;    // rows per block of the register-resident row passes (forward even, inverse)
-  FastDiv Ndiv;  // division by N
-  FastDiv RCdiv; // division by R * C
-  FastDiv RfCdiv;// division by Rf * C
-  size_t bins() const { return (size_t)NT * M * C; }
+  int Wh;         // N / 2 + 1
+  int C, logC;    // tile width (power of two)
+  int NT;         // number of tiles = ceil(Wh / C)
+  int R;          // image rows per block in the LDS-resident row passes (even)
+  int Rf, Ri;     // rows per block of the register-resident row passes (forward even, inverse)
+  FastDiv Ndiv;   // division by N
+  FastDiv RCdiv;  // division by R * C
+  FastDiv RfCdiv; // division by Rf * C
+  __host__ __device__ size_t bins() const { return (size_t)NT * M * C; }
 };
 
 Layout make_layout(int M, int N);
 FftPlan make_plan(int L);
 
-// Results of the residual pass: per-block partial sums and the bookkeeping to finish them.
-struct LamBuffers {
-  LamState *st;          // device
-  float *partials;       // device, [blocks][kLamAcc][2]
-  float *lam_hist;       // device, per iteration lambda (scale * lambda_star, +inf on the branch)
-  int *flag_hist;        // device, per iteration flags
-  const float *scales;   // device, nscale entries (may be null)
-  int hist_cap;          // capacity of the history arrays
-};
 constexpr int kLamAccFirst = 2 + 2 * kLamFirstCand;  // Einf, floor, f and slope per candidate
 constexpr int kLamAccSweep = 2 * kLamMaxCand;
 constexpr int kLamAcc = kLamAccFirst > kLamAccSweep ? kLamAccFirst : kLamAccSweep;
 
-// ---------------------------------------------------------------- launchers (kernels_*.hip)
-// Row pass, forward real-to-half-complex: x (M x N real) -> S (tile-major half spectrum).
-hipError_t launch_row_fwd(const float *x, const Layout &L, const FftPlan &pn, const cf *twN, cf *S,
-                          hipStream_t st);
+// Everything a kernel needs to know about one image.  Kernels receive a device table of these
+// plus a list of work items (image, block); one launch serves every image of a batch.
+struct Img {
+  Layout L;
+  FftPlan pm, pn;        // LDS-resident plans (any 2^a 3^b 5^c length)
+  RegPlan rm, rn;        // register-resident plans (power-of-two lengths)
+  const cf *twM, *twN;   // twiddles exp(-2 pi i n / L)
+  const cf *H, *Y, *HY;  // F(h), F(y), conj(F(h)) F(y), tile-major
+  const float *H2;       // |F(h)|^2, tile-major
+  const float *dM, *dN;  // |F(grad)|^2 = dM[m] + dN[k]
+  float *uE, *uI, *uP;   // images (u_E is also the filter's output)
+  float *q;              // Hermitian-weighted |R|^2, tile-major
+  cf *S1, *SI, *SP;      // spectra: row transforms / U_E, and the two solves
+  float *part;           // partial sums, [2 * kLamAcc][npart]
+  int npart;             // stride of `part` (>= NT and >= nchunk)
+  int nchunk;            // blocks of a lambda evaluation round
+  LamState *st;
+  float *lam_hist;
+  int *flag_hist;
+  const float *scales;
+  int hist_cap;
+  int w;
+  float eps;
+  int gfTX, gfTY, gfNBY;  // guided-filter strip geometry
+};
+
+struct Item {
+  int img, blk;  // blk < 0: padding item (no work)
+};
+
+// A sequence of launches (one per image group and pass) enqueued on a stream.
+using Launch = std::function<hipError_t(hipStream_t)>;
+struct Plan {
+  std::vector<Launch> steps;
+  hipError_t enqueue(hipStream_t s) const {
+    for (const auto &f : steps) {
+      hipError_t e = f(s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+};
+
+// Host-side view of a set of images for building launch plans.  `dev` is the device copy of
+// `imgs`; work lists are appended to items_host and uploaded once by finalize_items().
+struct ImgSet {
+  std::vector<Img> imgs;
+  Img *dev = nullptr;
+  std::vector<Item> items_host;
+  Item *items_dev = nullptr;
+};
+
+// Plan builders.  `sel` picks images of the set; launches reference set.dev and offsets into
+// set.items_dev, so finalize_items() must run before a plan is enqueued.
+void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel);
+void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid);
+void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds);
+void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
+void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
+void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool close_iteration);
+hipError_t finalize_items(ImgSet &set);
+void gf_geometry(Img &d);
+bool guided_filter_supported(int w);
+
+// Stand-alone guided filter on caller-provided images (context-free).
+hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
+                                      hipStream_t s);
+
+// Per-image set-up (FP64 transforms of h and y, constants, rho and the target).
+hipError_t launch_embed_psf(const float *h, int kh, int kw, int M, int N, double *hp, hipStream_t st);
 hipError_t launch_row_fwd_d(const double *x, const Layout &L, const FftPlan &pn, const cd *twN, cd *S,
                             hipStream_t st);
 hipError_t launch_row_fwd_fd(const float *x, const Layout &L, const FftPlan &pn, const cd *twN, cd *S,
                              hipStream_t st);
-// Column pass, forward, in place (transform only).
 hipError_t launch_col_fwd_d(cd *S, const Layout &L, const FftPlan &pm, const cd *twM, hipStream_t st);
-hipError_t launch_col_fwd_f(cf *S, const Layout &L, const FftPlan &pm, const cf *twM, hipStream_t st);
-// Column pass, forward, in place, fused with R = H U_E - Y, q = w |R|^2 and the first lambda
-// candidates; the last block starts the lambda search.
-hipError_t launch_col_fwd_resid(cf *S, float *q, const cf *H, const cf *Y, const Layout &L,
-                                const FftPlan &pm, const cf *twM, const LamBuffers &lb, hipStream_t st);
-// One evaluation round of the lambda search over (q, |H|^2).
-hipError_t launch_lam_sweep(const float *q, const float *H2, size_t nbins, const LamBuffers &lb, int last,
-                            hipStream_t st);
-// Spectral solves (Eqs. 8-9) with lambda from the state, then column inverse of both spectra.
-hipError_t launch_col_inv(const cf *UE, const cf *HY, const float *H2, const float *dM, const float *dN,
-                          const Layout &L, const FftPlan &pm, const cf *twM, const LamBuffers &lb,
-                          cf *SI, cf *SP, hipStream_t st);
-// Row pass, inverse: two half spectra -> two real images.
-hipError_t launch_row_inv(const cf *SI, const cf *SP, const Layout &L, const FftPlan &pn, const cf *twN,
-                          float *uI, float *uP, hipStream_t st);
-// Guided filter; cI / cP point at the offsets subtracted before forming products.  With a
-// state, the kernel also closes the iteration (counter, first lambda candidates of the next).
-hipError_t launch_guided_filter(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
-                                const float *cI, const float *cP, LamState *st, hipStream_t s);
-bool guided_filter_supported(int w);
-
-// Init helpers
-hipError_t launch_embed_psf(const float *h, int kh, int kw, int M, int N, double *hp, hipStream_t st);
 hipError_t launch_init_consts(const cd *Hd, const cd *Yd, const Layout &L, cf *H, cf *Y, cf *HY, float *H2,
                               hipStream_t st);
 hipError_t launch_d2_tables(int M, int N, int Wh, float *dM, float *dN, hipStream_t st);
-// rho of Eq.(12) and the target; writes doubles {rho, T} to out2 and fills the state constants.
 hipError_t launch_rho_target(const float *y, int M, int N, const float *h, int kh, int kw, double sigma2,
                              double rho_fixed, double *work, double *out2, LamState *st, hipStream_t st_);
 hipError_t launch_fill_f(float *p, size_t n, float v, hipStream_t st);
 hipError_t launch_state_reset(LamState *st, hipStream_t s);
+hipError_t launch_state_set_lam(LamState *st, float lam, hipStream_t s);
+hipError_t launch_copy_lam_star(const LamState *st, float *out, hipStream_t s);
+int lam_sweep_chunks(size_t nbins);
 
 }  // namespace gfd

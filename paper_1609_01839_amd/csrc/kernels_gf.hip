@@ -14,6 +14,8 @@
 // (the image means when known) before products are formed; the filter commutes with such
 // shifts (u shifts by the input's constant).  The radius is a template parameter so that the
 // horizontal sums unroll into back-to-back LDS reads.
+#include <map>
+
 #include "gfd_internal.h"
 
 namespace gfd {
@@ -65,32 +67,21 @@ __device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *
   }
 }
 
+// One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
 template <int R>
-__global__ void __launch_bounds__(kGfThreads) k_guided_filter(const float *__restrict__ uI, const float *__restrict__ uP,
-                                                              float *__restrict__ u, int M, int N, float eps, int TX,
-                                                              int TY, int nby, const float *__restrict__ cIp,
-                                                              const float *__restrict__ cPp, LamState *st) {
+__device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, const GFD_AS1 float *__restrict__ uP,
+                                         GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY, int nby,
+                                         int lb, float cI, float cP, float2 *__restrict__ ringAB,
+                                         float *__restrict__ vbuf, float *__restrict__ hbuf) {
   constexpr int W = 2 * R + 1;
   constexpr int RB = kGfRB;
-  __shared__ float2 ringAB[W * kGfThreads];
-  __shared__ float vbuf[RB * 4 * kGfThreads];
-  __shared__ float hbuf[RB * 4 * kGfThreads];
-
-  if (st != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
-    // the lambda phase of this iteration is over: advance the counter and seed the next search
-    st->k += 1;
-    st->phase = 0;
-    lam_first_candidates(*st);
-  }
   const float inv_w2 = 1.0f / (float)(W * W);
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = lb / nby, by = lb - bx * nby;
   const int x0 = bx * TX, y0 = by * TY;
   const int j = threadIdx.x;
   const int used = TX + 4 * R;
   const bool active = j < used;
   const int gx = wrap(x0 - 2 * R + j, N);
-  const float cI = *cIp, cP = *cPp;
   const int nrows = TY + 4 * R;  // stream rows it = 0 .. nrows-1 are image rows y0 - 2R + it
   const int ybase = y0 - 2 * R;
 
@@ -201,34 +192,116 @@ __global__ void __launch_bounds__(kGfThreads) k_guided_filter(const float *__res
   }
 }
 
-bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
-
+// Inside the iteration: one launch filters every image of the group (images of one radius).
+// The item of block 0 of each image also closes that image's iteration: the counter advances
+// and the first lambda candidates of the next search are seeded.  Nothing else in this launch
+// reads those fields, and the means used as offsets are left untouched.
 template <int R>
-static void launch_r(const float *uI, const float *uP, float *u, int M, int N, float eps, const float *cI,
-                     const float *cP, LamState *st, hipStream_t s) {
-  int TX = kGfThreads - 4 * R;
-  if (TX > N) TX = N;
-  int TY = 64;
-  if (TY > M) TY = M;
-  const int nbx = (N + TX - 1) / TX, nby = (M + TY - 1) / TY;
-  hipLaunchKernelGGL(k_guided_filter<R>, dim3(nbx * nby), dim3(kGfThreads), 0, s, uI, uP, u, M, N, eps, TX, TY, nby,
-                     cI, cP, st);
+__global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
+                                                     int nitems, int close_iteration) {
+  constexpr int Wn = 2 * R + 1;
+  __shared__ float2 ringAB[Wn * kGfThreads];
+  __shared__ float vbuf[kGfRB * 4 * kGfThreads];
+  __shared__ float hbuf[kGfRB * 4 * kGfThreads];
+  for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
+    const Item wi = W[ii];
+    if (wi.blk < 0) continue;
+    const Img &d = D[wi.img];
+    LamState *st = d.st;
+    const float cI = st->meanI, cP = st->meanP;
+    if (close_iteration && wi.blk == 0 && threadIdx.x == 0) {
+      st->k += 1;
+      st->phase = 0;
+      lam_first_candidates(*st);
+    }
+    gf_strip<R>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, ringAB, vbuf, hbuf);
+    __syncthreads();
+  }
 }
 
-hipError_t launch_guided_filter(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
-                                const float *cI, const float *cP, LamState *st, hipStream_t s) {
-  switch ((w - 1) / 2) {
-    case 0: launch_r<0>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 1: launch_r<1>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 2: launch_r<2>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 3: launch_r<3>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 4: launch_r<4>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 5: launch_r<5>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 6: launch_r<6>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 7: launch_r<7>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    case 8: launch_r<8>(uI, uP, u, M, N, eps, cI, cP, st, s); break;
-    default: return hipErrorInvalidValue;
+// Stand-alone filter: the offsets are the first pixels of the inputs.
+template <int R>
+__global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
+                                                         float *__restrict__ u, int M, int N, float eps, int TX,
+                                                         int TY, int nby) {
+  constexpr int Wn = 2 * R + 1;
+  __shared__ float2 ringAB[Wn * kGfThreads];
+  __shared__ float vbuf[kGfRB * 4 * kGfThreads];
+  __shared__ float hbuf[kGfRB * 4 * kGfThreads];
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  gf_strip<R>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], ringAB, vbuf, hbuf);
+}
+
+bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
+
+static void gf_tiles(int M, int N, int R, int &TX, int &TY, int &nbx, int &nby) {
+  TX = kGfThreads - 4 * R;
+  if (TX > N) TX = N;
+  TY = 64;
+  if (TY > M) TY = M;
+  nbx = (N + TX - 1) / TX;
+  nby = (M + TY - 1) / TY;
+}
+
+void gf_geometry(Img &d) {
+  int nbx;
+  gf_tiles(d.L.M, d.L.N, (d.w - 1) / 2, d.gfTX, d.gfTY, nbx, d.gfNBY);
+}
+
+#define GFD_R_SWITCH(r, X)                                                                                  \
+  switch (r) {                                                                                              \
+    case 0: X(0); break;                                                                                    \
+    case 1: X(1); break;                                                                                    \
+    case 2: X(2); break;                                                                                    \
+    case 3: X(3); break;                                                                                    \
+    case 4: X(4); break;                                                                                    \
+    case 5: X(5); break;                                                                                    \
+    case 6: X(6); break;                                                                                    \
+    case 7: X(7); break;                                                                                    \
+    case 8: X(8); break;                                                                                    \
+    default: break;                                                                                         \
   }
+
+void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool close_iteration) {
+  std::map<int, std::vector<int>> byR;
+  for (int i : sel) byR[(set.imgs[i].w - 1) / 2].push_back(i);
+  for (auto &kv : byR) {
+    const size_t off = set.items_host.size();
+    for (int i : kv.second) {
+      const Img &d = set.imgs[i];
+      const int nblk = (d.L.N + d.gfTX - 1) / d.gfTX * d.gfNBY;
+      // every 8th item runs on one XCD: give each XCD a contiguous run of strips
+      const int padded = (nblk + 7) / 8 * 8, per = padded / 8;
+      for (int q = 0; q < padded; ++q) {
+        const int blk = (q % 8) * per + q / 8;
+        set.items_host.push_back(Item{i, blk < nblk ? blk : -1});
+      }
+    }
+    const size_t n = set.items_host.size() - off;
+    ImgSet *setp = &set;
+    const int r = kv.first, close = close_iteration ? 1 : 0;
+    p.steps.push_back([=](hipStream_t s) -> hipError_t {
+      if (n == 0) return hipSuccess;
+#define GFD_LAUNCH_GF(RR)                                                                                    \
+  hipLaunchKernelGGL(k_gf_g<RR>, dim3((unsigned)n), dim3(kGfThreads), 0, s, (const Img *)setp->dev,          \
+                     (const Item *)(setp->items_dev + off), (int)n, close)
+      GFD_R_SWITCH(r, GFD_LAUNCH_GF)
+#undef GFD_LAUNCH_GF
+      return hipGetLastError();
+    });
+  }
+}
+
+hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
+                                      hipStream_t s) {
+  const int r = (w - 1) / 2;
+  if (!guided_filter_supported(w)) return hipErrorInvalidValue;
+  int TX, TY, nbx, nby;
+  gf_tiles(M, N, r, TX, TY, nbx, nby);
+#define GFD_LAUNCH_GFP(RR) \
+  hipLaunchKernelGGL(k_gf_plain<RR>, dim3(nbx * nby), dim3(kGfThreads), 0, s, uI, uP, u, M, N, eps, TX, TY, nby)
+  GFD_R_SWITCH(r, GFD_LAUNCH_GFP)
+#undef GFD_LAUNCH_GFP
   return hipGetLastError();
 }
 

@@ -1,40 +1,29 @@
 // Spectral part of the iteration on gfx950: row / column FFT passes over a tile-major half
 // spectrum, the residual and lambda reductions (Sec. 3.2, Eqs.(10)-(11)), the two Fourier
 // solves (Sec. 3.1, Eqs.(8)-(9)) and the per-image set-up.
+//
+// Hot-path kernels take a device table of image descriptors (Img) and a work list of
+// (image, block) items: one launch serves every image of a batch that shares the kernel
+// variant, and a single image is a batch of one.  Work lists are padded per image to a
+// multiple of 8 items and each image's blocks are permuted so that the blocks the hardware
+// sends to one XCD (every 8th) are neighbouring tiles or rows sharing that XCD's L2.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
-#include "fft_reg.h"
+#include <algorithm>
+#include <map>
+#include <tuple>
+
 #include "gfd_internal.h"
 
 namespace gfd {
 
-// ============================================================================ helpers
-
-template <class T>
-__device__ __forceinline__ T zero_of() { return (T)0; }
-
-// Sum NV (hi, lo) accumulators of `nparts` block partials with every thread of the block;
-// deterministic order.  Result in thread 0.
-template <int NV>
-__device__ void reduce_partials(const float *__restrict__ partials, int nparts, float (&hi)[NV], float (&lo)[NV],
-                                float *scratch) {
-#pragma unroll
-  for (int v = 0; v < NV; ++v) hi[v] = lo[v] = 0.0f;
-  for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
-    const float *src = partials + (size_t)p * kLamAcc * 2;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      df_add(hi[v], lo[v], src[2 * v], src[2 * v + 1]);
-    }
-  }
-  block_reduce_df<NV>(hi, lo, scratch);
-}
+// ============================================================================ reductions
 
 // Plain FP32 butterfly over the wave, then compensated across waves; thread 0 gets the sum.
 template <int NV>
-__device__ void block_sum_plain_then_df(float (&acc)[NV], float (&hi)[NV], float (&lo)[NV], float *scratch) {
+__device__ __forceinline__ void block_sum_plain_then_df(float (&acc)[NV], float (&hi)[NV], float (&lo)[NV], float *scratch) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -58,12 +47,37 @@ __device__ void block_sum_plain_then_df(float (&acc)[NV], float (&hi)[NV], float
   __syncthreads();
 }
 
-// Commit the lambda of this iteration (called by one thread once the search is finished).
-__device__ void lam_commit(LamState *st, const LamBuffers &lb) {
-  float ls = st->lam_star;
+// Partial sums are stored structure-of-arrays, part[(2 a + {0: hi, 1: lo}) * npart + block].
+__device__ __forceinline__ void store_partials(GFD_AS1 float *part, int npart, int blk, int nv, const float *hi,
+                                               const float *lo) {
+  for (int a = 0; a < nv; ++a) {
+    part[(size_t)(2 * a) * npart + blk] = hi[a];
+    part[(size_t)(2 * a + 1) * npart + blk] = lo[a];
+  }
+}
+
+// Compensated sum of the partials of `nparts` blocks with every thread of the block;
+// deterministic order; result in thread 0.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict__ part, int npart, int nparts, float (&hi)[NV],
+                                float (&lo)[NV], float *scratch) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) hi[v] = lo[v] = 0.0f;
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      df_add(hi[v], lo[v], part[(size_t)(2 * v) * npart + p], part[(size_t)(2 * v + 1) * npart + p]);
+  }
+  block_reduce_df<NV>(hi, lo, scratch);
+}
+
+// Commit the lambda of this iteration (one thread, once the search is finished).
+__device__ void lam_commit(const Img &d) {
+  LamState *st = d.st;
+  const float ls = st->lam_star;
   float lam = ls;
   if (!isinf(ls)) {
-    float sc = (lb.scales != nullptr && st->k < st->nscale) ? lb.scales[st->k] : 1.0f;
+    const float sc = (d.scales != nullptr && st->k < st->nscale) ? d.scales[st->k] : 1.0f;
     lam = sc * ls;
     if (!(st->flags & kFlagNoRoot)) {
       st->lam_prev2 = st->lam_prev;
@@ -72,24 +86,41 @@ __device__ void lam_commit(LamState *st, const LamBuffers &lb) {
   }
   st->lam = lam;
   st->flags_all |= (unsigned)st->flags;
-  if (lb.lam_hist != nullptr && st->k < lb.hist_cap) {
-    lb.lam_hist[st->k] = lam;
-    lb.flag_hist[st->k] = st->flags;
+  if (d.lam_hist != nullptr && st->k < d.hist_cap) {
+    d.lam_hist[st->k] = lam;
+    d.flag_hist[st->k] = st->flags;
   }
 }
 
-// ============================================================================ row pass, forward
-// Block handles rows [r0, r0 + R): rows are paired into complex sequences z = x_a + i x_b,
-// transformed, and separated into the two half spectra X_a[k] = (Z[k] + conj Z[N-k]) / 2,
-// X_b[k] = (Z[k] - conj Z[N-k]) / 2i, written tile-major.
-template <class T, class TI, int E>
-__global__ void __launch_bounds__(1024) k_row_fwd(const TI *__restrict__ x, Layout lay, FftPlan pn,
-                                                  const cpx<T> *__restrict__ tw, cpx<T> *__restrict__ S) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem_raw);
+// Per-bin contribution to the first lambda round: Einf, the floor and the candidates.
+template <int NC>
+__device__ __forceinline__ void first_round_terms(float qq, float t2, const float (&mu)[NC],
+                                                  float (&acc)[2 + 2 * NC]) {
+  acc[0] += qq;
+  {
+    const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, 1.0f / kLamFloor, 1.0f));
+    acc[1] = __fmaf_rn(qq, r * r, acc[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu[j], 1.0f));
+    const float qg = qq * (r * r);
+    acc[2 + j] += qg;
+    acc[2 + NC + j] = __fmaf_rn(qg, 1.0f - r, acc[2 + NC + j]);
+  }
+}
+
+// ============================================================================ device bodies (any length)
+
+// Row pass, forward, rows [r0, r0 + R): rows are paired into complex sequences z = x_a + i x_b,
+// transformed in LDS, and separated into the two half spectra
+// X_a[k] = (Z[k] + conj Z[N-k]) / 2, X_b[k] = (Z[k] - conj Z[N-k]) / 2i, written tile-major.
+template <class T, int E, class XP, class SP>
+__device__ __forceinline__ void row_fwd_body(XP x, const Layout &lay, const FftPlan &pn,
+                                             const GFD_AS1 cpx<T> *__restrict__ tw, SP S, int blk, cpx<T> *buf) {
   const int M = lay.M, N = lay.N, R = lay.R, LP = N + 1;
   const int npair = R >> 1;
-  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;  // neighbouring row blocks share an XCD's L2
+  const int r0 = blk * R;
   for (int e = threadIdx.x; e < npair * N; e += blockDim.x) {
     const int b = fdiv(e, lay.Ndiv), n = e - b * N;
     const int ra = r0 + 2 * b, rb = ra + 1;
@@ -118,195 +149,127 @@ __global__ void __launch_bounds__(1024) k_row_fwd(const TI *__restrict__ x, Layo
   }
 }
 
-// ============================================================================ column pass, forward
-template <class T, int E>
-__global__ void __launch_bounds__(1024) k_col_fwd(cpx<T> *__restrict__ S, Layout lay, FftPlan pm,
-                                                  const cpx<T> *__restrict__ tw) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem_raw);
+// Column pass, forward, of one tile: its C columns are transformed in LDS.
+template <class T, int E, class TP>
+__device__ __forceinline__ void col_fwd_load_fft(TP tile, const Layout &lay, const FftPlan &pm,
+                                                 const GFD_AS1 cpx<T> *__restrict__ tw, cpx<T> *buf) {
   const int n = lay.M * lay.C;
-  cpx<T> *tile = S + (size_t)blockIdx.x * n;
   for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = tile[e];
   __syncthreads();
   lds_fft<T, E, -1, true>(buf, lay.C, lay.logC, lay.C, 1, pm, tw);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) tile[e] = buf[e];
 }
 
-// Column pass fused with the residual R = H U_E - Y of Eq.(10), the Hermitian-weighted
-// q = w |R|^2 (w = 1 on columns 0 and N/2, else 2), Einf = sum q / P, and the first lambda
-// candidates of the search.  Each block writes its compensated partial sums; k_lam_begin
-// finishes them.
-template <int E>
-__global__ void __launch_bounds__(1024) k_col_fwd_resid(cf *__restrict__ S, float *__restrict__ q,
-                                                        const cf *__restrict__ H, const cf *__restrict__ Y,
-                                                        Layout lay, FftPlan pm, const cf *__restrict__ tw,
-                                                        LamBuffers lb) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cf *buf = reinterpret_cast<cf *>(smem_raw);
-  __shared__ float scratch[2 * kLamAcc * 16];
-  LamState *st = lb.st;
-  const int n = lay.M * lay.C;
-  const size_t off = (size_t)blockIdx.x * n;
-  cf *tile = S + off;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = tile[e];
-  __syncthreads();
-  lds_fft<float, E, -1, true>(buf, lay.C, lay.logC, lay.C, 1, pm, tw);
-
-  constexpr int NC = kLamFirstCand;
-  float mu[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) mu[j] = st->mu[j];
-  const float mu_floor = 1.0f / kLamFloor;
-  float acc[2 + 2 * NC];
-#pragma unroll
-  for (int v = 0; v < 2 + 2 * NC; ++v) acc[v] = 0.0f;
-  const int N = lay.N, Wh = lay.Wh, C = lay.C;
-  const int kbase = blockIdx.x * C;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const cf U = buf[e];
-    tile[e] = U;
-    const int k = kbase + (e & (C - 1));
-    float qq = 0.0f, t2 = 0.0f;
-    if (k < Wh) {
-      const cf h = H[off + e], y = Y[off + e];
-      const cf r = cmul(h, U) - y;
-      const float wgt = (k == 0 || 2 * k == N) ? 1.0f : 2.0f;
-      qq = wgt * abs2f(r);
-      t2 = abs2f(h);
-    }
-    q[off + e] = qq;
-    acc[0] += qq;
-    {
-      float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu_floor, 1.0f));
-      acc[1] = __fmaf_rn(qq, r * r, acc[1]);
-    }
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu[j], 1.0f));
-      const float qg = qq * (r * r);
-      acc[2 + j] += qg;
-      acc[2 + NC + j] = __fmaf_rn(qg, 1.0f - r, acc[2 + NC + j]);
-    }
-  }
-  float hi[2 + 2 * NC], lo[2 + 2 * NC];
-  block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
-  if (threadIdx.x == 0) {
-    float *dst = lb.partials + (size_t)blockIdx.x * kLamAcc * 2;
-    for (int v = 0; v < 2 + 2 * NC; ++v) {
-      dst[2 * v] = hi[v];
-      dst[2 * v + 1] = lo[v];
-    }
-  }
-}
-
-// ============================================================================ lambda sweep
-// One evaluation round: per-block sums over the bins of q g_j and q g_j (1 - r_j) for the
-// current candidates (k_lam_round finishes them).
-template <int NC>
-__global__ void __launch_bounds__(256) k_lam_sweep(const float *__restrict__ q, const float *__restrict__ H2,
-                                                   size_t nbins, LamBuffers lb) {
-  __shared__ float scratch[2 * kLamAcc * 4];
-  LamState *st = lb.st;
-  if (st->phase != 0) return;  // lambda already fixed for this iteration
-  float mu[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) mu[j] = st->mu[j];
-  float acc[2 * NC];
-#pragma unroll
-  for (int v = 0; v < 2 * NC; ++v) acc[v] = 0.0f;
-  const size_t n4 = nbins / 4;
-  const float4 *q4 = reinterpret_cast<const float4 *>(q);
-  const float4 *h4 = reinterpret_cast<const float4 *>(H2);
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
-    const float4 qa = q4[i], ta = h4[i];
-    const float qs[4] = {qa.x, qa.y, qa.z, qa.w}, ts[4] = {ta.x, ta.y, ta.z, ta.w};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const float r = __builtin_amdgcn_rcpf(__fmaf_rn(ts[u], mu[j], 1.0f));
-        const float qg = qs[u] * (r * r);
-        acc[j] += qg;
-        acc[NC + j] = __fmaf_rn(qg, 1.0f - r, acc[NC + j]);
-      }
-    }
-  }
-  if (blockIdx.x == 0) {  // tail that does not fill a float4
-    for (size_t i = n4 * 4 + threadIdx.x; i < nbins; i += blockDim.x) {
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        const float r = __builtin_amdgcn_rcpf(__fmaf_rn(H2[i], mu[j], 1.0f));
-        const float qg = q[i] * (r * r);
-        acc[j] += qg;
-        acc[NC + j] = __fmaf_rn(qg, 1.0f - r, acc[NC + j]);
-      }
-    }
-  }
-  float hi[2 * NC], lo[2 * NC];
-  block_sum_plain_then_df<2 * NC>(acc, hi, lo, scratch);
-  if (threadIdx.x == 0) {
-    float *dst = lb.partials + (size_t)blockIdx.x * kLamAcc * 2;
-    for (int v = 0; v < 2 * NC; ++v) {
-      dst[2 * v] = hi[v];
-      dst[2 * v + 1] = lo[v];
-    }
-  }
-}
-
-// ============================================================================ lambda decisions
-// One block finishes the partial sums of the residual pass (round 0) or of a sweep and runs the
-// search state machine; deterministic order.
-__global__ void __launch_bounds__(256) k_lam_begin(LamBuffers lb, int nparts) {
-  __shared__ float scratch[2 * kLamAcc * 4];
-  constexpr int NC = kLamFirstCand;
-  float hi[2 + 2 * NC], lo[2 + 2 * NC];
-  reduce_partials<2 + 2 * NC>(lb.partials, nparts, hi, lo, scratch);
-  if (threadIdx.x == 0) {
-    LamState *st = lb.st;
-    st->phase = 0;
-    st->flags = 0;
-    float cand[NC];
-    for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
-    if (lam_begin(*st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(st, lb);
-  }
-}
-
-__global__ void __launch_bounds__(256) k_lam_round(LamBuffers lb, int nparts, int last) {
-  __shared__ float scratch[2 * kLamAcc * 4];
-  constexpr int NC = kLamMaxCand;
-  if (lb.st->phase != 0) return;
-  float hi[2 * NC], lo[2 * NC];
-  reduce_partials<2 * NC>(lb.partials, nparts, hi, lo, scratch);
-  if (threadIdx.x == 0) {
-    LamState *st = lb.st;
-    float cand[NC];
-    for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
-    lam_absorb(*st, NC, cand, hi, lo, hi + NC);
-    if (lam_decide(*st, last != 0)) lam_commit(st, lb);
-  }
-}
-
-// ============================================================================ solves + column inverse
-// F(u_p) = (conj(H) Y + lam F(u_E)) / (|H|^2 + lam)                         (Eq. 9)
-// F(u_I) = (conj(H) Y + lam D2 F(u_E)) / (|H|^2 + lam D2), D2 = |F(grad)|^2 (Eq. 8)
+// Spectral solves of Eqs.(8)-(9) for one bin:
+//   F(u_p) = (conj(H) Y + lam F(u_E)) / (|H|^2 + lam)
+//   F(u_I) = (conj(H) Y + lam D2 F(u_E)) / (|H|^2 + lam D2),  D2 = |F(grad)|^2,
 // written with mu = 1/lam when lam >= 1 so that nothing overflows for large lam; lam = +inf
-// copies F(u_E) to both.  The 1/P of the inverse transform is applied here.  The U_I spectrum
-// waits in registers while U_p is transformed in LDS.
+// copies F(u_E) to both.  The 1/P of the inverse transform is folded in.
+struct SolveParams {
+  float lam, invP, mu;
+  bool inf_branch, big;
+};
+__device__ __forceinline__ SolveParams solve_params(const LamState *st) {
+  SolveParams s;
+  s.lam = st->lam;
+  s.invP = st->invP;
+  s.inf_branch = isinf(s.lam);
+  s.big = s.lam >= 1.0f;
+  s.mu = s.big ? 1.0f / s.lam : 0.0f;
+  return s;
+}
+__device__ __forceinline__ void solve_bin(const SolveParams &sp, cf U, cf hy, float t2, float d2, cf &Up, cf &Ui) {
+  if (sp.inf_branch) {
+    Up = cscale(U, sp.invP);
+    Ui = Up;
+  } else if (sp.big) {
+    const float ip = sp.invP * __builtin_amdgcn_rcpf(__fmaf_rn(sp.mu, t2, 1.0f));
+    const float ii = sp.invP * __builtin_amdgcn_rcpf(__fmaf_rn(sp.mu, t2, d2));
+    Up = cf{(__fmaf_rn(sp.mu, hy.re, U.re)) * ip, (__fmaf_rn(sp.mu, hy.im, U.im)) * ip};
+    Ui = cf{(__fmaf_rn(sp.mu, hy.re, d2 * U.re)) * ii, (__fmaf_rn(sp.mu, hy.im, d2 * U.im)) * ii};
+  } else {
+    const float ip = sp.invP * __builtin_amdgcn_rcpf(t2 + sp.lam);
+    const float ld = sp.lam * d2;
+    const float ii = sp.invP * __builtin_amdgcn_rcpf(t2 + ld);
+    Up = cf{__fmaf_rn(sp.lam, U.re, hy.re) * ip, __fmaf_rn(sp.lam, U.im, hy.im) * ip};
+    Ui = cf{__fmaf_rn(ld, U.re, hy.re) * ii, __fmaf_rn(ld, U.im, hy.im) * ii};
+  }
+}
+
+// ============================================================================ hot-path kernels, any length
+
+#define GFD_ITEM_LOOP                                        \
+  for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) { \
+    const Item wi = W[ii];                                   \
+    if (wi.blk < 0) continue;                                \
+    const Img &d = D[wi.img];
+#define GFD_ITEM_END \
+  __syncthreads();   \
+  }
+
 template <int E>
-__global__ void __launch_bounds__(1024) k_col_inv(const cf *__restrict__ UE, const cf *__restrict__ HY,
-                                                  const float *__restrict__ H2, const float *__restrict__ dM,
-                                                  const float *__restrict__ dN, Layout lay, FftPlan pm,
-                                                  const cf *__restrict__ tw, LamState *st,
-                                                  cf *__restrict__ SI, cf *__restrict__ SP) {
+__global__ void __launch_bounds__(1024) k_row_fwd_g(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *buf = reinterpret_cast<cf *>(smem_raw);
-  const int n = lay.M * lay.C, C = lay.C, Wh = lay.Wh;
-  const size_t off = (size_t)blockIdx.x * n;
-  const float lam = st->lam, invP = st->invP;
-  const bool inf_branch = isinf(lam);
-  const bool big = lam >= 1.0f;
-  const float mu = big ? 1.0f / lam : 0.0f;
-  const int kbase = blockIdx.x * C;
+  GFD_ITEM_LOOP
+  row_fwd_body<float, E>(G(d.uE), d.L, d.pn, G(d.twN), G(d.S1), wi.blk, buf);
+  GFD_ITEM_END
+}
+
+template <int E, bool RESID>
+__global__ void __launch_bounds__(1024) k_col_fwd_g(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cf *buf = reinterpret_cast<cf *>(smem_raw);
+  __shared__ float scratch[kLamAcc * 16];
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
+  const int n = lay.M * lay.C, C = lay.C;
+  const size_t off = (size_t)wi.blk * n;
+  GFD_AS1 cf *tile = G(d.S1) + off;
+  col_fwd_load_fft<float, E>(tile, lay, d.pm, G(d.twM), buf);
+  if (!RESID) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) tile[e] = buf[e];
+  } else {
+    // fused with the residual R = H U_E - Y of Eq.(10), q = w |R|^2 (w = 1 on columns 0 and
+    // N/2, else 2), Einf = sum q / P and the first lambda candidates
+    constexpr int NC = kLamFirstCand;
+    float mu[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) mu[j] = d.st->mu[j];
+    float acc[2 + 2 * NC];
+#pragma unroll
+    for (int a = 0; a < 2 + 2 * NC; ++a) acc[a] = 0.0f;
+    const int kbase = wi.blk * C;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      const cf U = buf[e];
+      tile[e] = U;
+      const int k = kbase + (e & (C - 1));
+      float qq = 0.0f, t2 = 0.0f;
+      if (k < lay.Wh) {
+        const cf h = G(d.H)[off + e], y = G(d.Y)[off + e];
+        const cf r = cmul(h, U) - y;
+        qq = ((k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f) * abs2f(r);
+        t2 = abs2f(h);
+      }
+      G(d.q)[off + e] = qq;
+      first_round_terms<NC>(qq, t2, mu, acc);
+    }
+    float hi[2 + 2 * NC], lo[2 + 2 * NC];
+    block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
+    if (threadIdx.x == 0) store_partials(G(d.part), d.npart, wi.blk, 2 + 2 * NC, hi, lo);
+  }
+  GFD_ITEM_END
+}
+
+template <int E>
+__global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cf *buf = reinterpret_cast<cf *>(smem_raw);
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
+  const int n = lay.M * lay.C, C = lay.C;
+  const size_t off = (size_t)wi.blk * n;
+  const SolveParams sp = solve_params(d.st);
+  const int kbase = wi.blk * C;
   cf ui[E];
 #pragma unroll
   for (int u = 0; u < E; ++u) {
@@ -314,31 +277,11 @@ __global__ void __launch_bounds__(1024) k_col_inv(const cf *__restrict__ UE, con
     if (e < n) {
       const int k = kbase + (e & (C - 1)), m = e >> lay.logC;
       cf Up = {0.0f, 0.0f}, Ui = {0.0f, 0.0f};
-      if (k < Wh) {
-        const cf U = UE[off + e];
-        if (inf_branch) {
-          Up = cscale(U, invP);
-          Ui = Up;
-        } else {
-          const cf hy = HY[off + e];
-          const float t2 = H2[off + e];
-          const float d2 = dM[m] + dN[k];
-          if (big) {
-            const float ip = invP * __builtin_amdgcn_rcpf(__fmaf_rn(mu, t2, 1.0f));
-            const float ii = invP * __builtin_amdgcn_rcpf(__fmaf_rn(mu, t2, d2));
-            Up = cf{(__fmaf_rn(mu, hy.re, U.re)) * ip, (__fmaf_rn(mu, hy.im, U.im)) * ip};
-            Ui = cf{(__fmaf_rn(mu, hy.re, d2 * U.re)) * ii, (__fmaf_rn(mu, hy.im, d2 * U.im)) * ii};
-          } else {
-            const float ip = invP * __builtin_amdgcn_rcpf(t2 + lam);
-            const float ld = lam * d2;
-            const float ii = invP * __builtin_amdgcn_rcpf(t2 + ld);
-            Up = cf{__fmaf_rn(lam, U.re, hy.re) * ip, __fmaf_rn(lam, U.im, hy.im) * ip};
-            Ui = cf{__fmaf_rn(ld, U.re, hy.re) * ii, __fmaf_rn(ld, U.im, hy.im) * ii};
-          }
-        }
+      if (k < lay.Wh) {
+        solve_bin(sp, G(d.S1)[off + e], G(d.HY)[off + e], G(d.H2)[off + e], G(d.dM)[m] + G(d.dN)[k], Up, Ui);
         if (k == 0 && m == 0) {  // zero frequency: the means of u_p and u_I
-          st->meanP = Up.re;
-          st->meanI = Ui.re;
+          d.st->meanP = Up.re;
+          d.st->meanI = Ui.re;
         }
       }
       buf[e] = Up;
@@ -346,8 +289,8 @@ __global__ void __launch_bounds__(1024) k_col_inv(const cf *__restrict__ UE, con
     }
   }
   __syncthreads();
-  lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, pm, tw);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) SP[off + e] = buf[e];
+  lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
+  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SP)[off + e] = buf[e];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < E; ++u) {
@@ -355,23 +298,23 @@ __global__ void __launch_bounds__(1024) k_col_inv(const cf *__restrict__ UE, con
     if (e < n) buf[e] = ui[u];
   }
   __syncthreads();
-  lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, pm, tw);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) SI[off + e] = buf[e];
+  lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
+  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SI)[off + e] = buf[e];
+  GFD_ITEM_END
 }
 
-// ============================================================================ row pass, inverse
-// Row m of the two half spectra A (of u_I) and B (of u_p) are combined into the full
-// spectrum Z = A + iB (with Z[N-k] = conj A[k] + i conj B[k]); its inverse transform is
+// Row pass, inverse: row m of the two half spectra A (of u_I) and B (of u_p) are combined into
+// the full spectrum Z = A + iB (with Z[N-k] = conj A[k] + i conj B[k]); its inverse transform is
 // u_I + i u_p.  Columns 0 and N/2 of a real row's spectrum are real: their imaginary parts
 // (rounding residue) are dropped.
 template <int E>
-__global__ void __launch_bounds__(1024) k_row_inv(const cf *__restrict__ SI, const cf *__restrict__ SP,
-                                                  Layout lay, FftPlan pn, const cf *__restrict__ tw,
-                                                  float *__restrict__ uI, float *__restrict__ uP) {
+__global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *buf = reinterpret_cast<cf *>(smem_raw);
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
   const int M = lay.M, N = lay.N, R = lay.R, C = lay.C, Wh = lay.Wh, LP = N + 1;
-  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;  // neighbouring row blocks share an XCD's L2
+  const int r0 = wi.blk * R;
   const int per_t = R * C, total = lay.NT * per_t;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     const int t = fdiv(e, lay.RCdiv), rem = e - t * per_t;
@@ -379,7 +322,7 @@ __global__ void __launch_bounds__(1024) k_row_inv(const cf *__restrict__ SI, con
     const int m = r0 + rho, k = t * C + c;
     if (m >= M || k >= Wh) continue;
     const size_t g = ((size_t)t * M + m) * C + c;
-    cf A = SI[g], B = SP[g];
+    cf A = G(d.SI)[g], B = G(d.SP)[g];
     if (k == 0 || 2 * k == N) {
       A.im = 0.0f;
       B.im = 0.0f;
@@ -389,43 +332,49 @@ __global__ void __launch_bounds__(1024) k_row_inv(const cf *__restrict__ SI, con
     if (k > 0 && N - k >= Wh) z[N - k] = cf{A.re + B.im, B.re - A.im};
   }
   __syncthreads();
-  lds_fft<float, E, +1, false>(buf, R, 0, 1, LP, pn, tw);
+  lds_fft<float, E, +1, false>(buf, R, 0, 1, LP, d.pn, G(d.twN));
   for (int e = threadIdx.x; e < R * N; e += blockDim.x) {
     const int rho = fdiv(e, lay.Ndiv), nn = e - rho * N;
     const int m = r0 + rho;
     if (m >= M) continue;
     const cf z = buf[rho * LP + nn];
-    uI[(size_t)m * N + nn] = z.re;
-    uP[(size_t)m * N + nn] = z.im;
+    G(d.uI)[(size_t)m * N + nn] = z.re;
+    G(d.uP)[(size_t)m * N + nn] = z.im;
   }
+  GFD_ITEM_END
 }
 
+// ============================================================================ hot-path kernels, power-of-two lengths
+// Register-resident radix-16 transforms (fft_reg.h): two LDS exchanges per transform, first
+// and last passes straight from / to global memory.  Threads beyond an image's need (blocks
+// sized for a larger image of the batch) only join the barriers.
 
-// ============================================================================ power-of-two lengths
-// The same passes with the register-resident radix-16 transform of fft_reg.h: two LDS
-// exchanges per transform instead of one per radix pass, and the first / last passes read and
-// write global memory directly.
-
-// Row pass, forward: block = npair sequences x T threads.
-__global__ void __launch_bounds__(512) k_row_fwd_r16(const float *__restrict__ x, Layout lay, RegPlan rp,
-                                                      const cf *__restrict__ tw, cf *__restrict__ S) {
+__global__ void __launch_bounds__(512) k_row_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+                                                     int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
-  const int M = lay.M, N = lay.N, R = lay.Rf, T = rp.T;
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
+  const int M = lay.M, N = lay.N, R = lay.Rf, T = d.rn.T;
   const int LP = N + (N >> 4);
   const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
-  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * R;
+  const bool active = seq < (R >> 1);
+  const int r0 = wi.blk * R;
   const int ra = r0 + 2 * seq, rb = ra + 1;
   cf v[16];
+  if (active) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int n = t + T * m;
-    v[m] = cf{ra < M ? x[(size_t)ra * N + n] : 0.0f, rb < M ? x[(size_t)rb * N + n] : 0.0f};
+    for (int m = 0; m < 16; ++m) {
+      const int n = t + T * m;
+      v[m] = cf{ra < M ? G(d.uE)[(size_t)ra * N + n] : 0.0f, rb < M ? G(d.uE)[(size_t)rb * N + n] : 0.0f};
+    }
   }
   cf *my = lds + seq * LP;
-  reg_fft<-1>(v, t, rp, my, 1, tw);
+  reg_fft<-1>(v, t, active, d.rn, my, 1, G(d.twN));
+  if (active) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) my[lds_pad(t + T * m)] = v[m];
+    for (int m = 0; m < 16; ++m) my[lds_pad(t + T * m)] = v[m];
+  }
   __syncthreads();
   const int C = lay.C, per_t = R * C, Wh = lay.Wh;
   const int total = lay.NT * per_t;
@@ -442,181 +391,258 @@ __global__ void __launch_bounds__(512) k_row_fwd_r16(const float *__restrict__ x
       if ((rho & 1) == 0) X = cf{(Zk.re + Zn.re) * 0.5f, (Zk.im - Zn.im) * 0.5f};
       else X = cf{(Zk.im + Zn.im) * 0.5f, (Zn.re - Zk.re) * 0.5f};
     }
-    S[((size_t)tt * M + m) * C + c] = X;
+    G(d.S1)[((size_t)tt * M + m) * C + c] = X;
   }
+  GFD_ITEM_END
 }
 
-// Column pass, forward (optionally fused with the residual and the first lambda candidates,
-// as k_col_fwd_resid): block = C columns x T threads, column c = tid % C.
 template <bool RESID>
-__global__ void __launch_bounds__(512) k_col_fwd_r16(cf *__restrict__ S, float *__restrict__ q,
-                                                      const cf *__restrict__ H, const cf *__restrict__ Y, Layout lay,
-                                                      RegPlan rp, const cf *__restrict__ tw, LamBuffers lb) {
+__global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+                                                     int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
   __shared__ float scratch[kLamAcc * 16];
-  const int C = lay.C, T = rp.T;
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
+  const int C = lay.C, T = d.rm.T;
   const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
-  const size_t off = (size_t)blockIdx.x * lay.M * C;
-  cf *tile = S + off;
+  const bool active = t < T;
+  const size_t off = (size_t)wi.blk * lay.M * C;
+  GFD_AS1 cf *tile = G(d.S1) + off;
   cf v[16];
+  if (active) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = tile[(t + T * m) * C + c];
-  reg_fft<-1>(v, t, rp, lds + c, C, tw);
+    for (int m = 0; m < 16; ++m) v[m] = tile[(t + T * m) * C + c];
+  }
+  reg_fft<-1>(v, t, active, d.rm, lds + c, C, G(d.twM));
   if (!RESID) {
+    if (active) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) tile[(t + T * m) * C + c] = v[m];
-    return;
+      for (int m = 0; m < 16; ++m) tile[(t + T * m) * C + c] = v[m];
+    }
+  } else {
+    constexpr int NC = kLamFirstCand;
+    float mu[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) mu[j] = d.st->mu[j];
+    float acc[2 + 2 * NC];
+#pragma unroll
+    for (int a = 0; a < 2 + 2 * NC; ++a) acc[a] = 0.0f;
+    const int k = wi.blk * C + c;
+    const bool valid = active && k < lay.Wh;
+    const float wgt = (k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f;
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int e = (t + T * m) * C + c;
+        tile[e] = v[m];
+        float qq = 0.0f, t2 = 0.0f;
+        if (valid) {
+          const cf h = G(d.H)[off + e], y = G(d.Y)[off + e];
+          const cf r = cmul(h, v[m]) - y;
+          qq = wgt * abs2f(r);
+          t2 = abs2f(h);
+        }
+        G(d.q)[off + e] = qq;
+        first_round_terms<NC>(qq, t2, mu, acc);
+      }
+    }
+    float hi[2 + 2 * NC], lo[2 + 2 * NC];
+    block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
+    if (threadIdx.x == 0) store_partials(G(d.part), d.npart, wi.blk, 2 + 2 * NC, hi, lo);
   }
-  LamState *st = lb.st;
-  constexpr int NC = kLamFirstCand;
-  float mu[NC];
-#pragma unroll
-  for (int j = 0; j < NC; ++j) mu[j] = st->mu[j];
-  const float mu_floor = 1.0f / kLamFloor;
-  float acc[2 + 2 * NC];
-#pragma unroll
-  for (int a = 0; a < 2 + 2 * NC; ++a) acc[a] = 0.0f;
-  const int k = blockIdx.x * C + c;
-  const bool valid = k < lay.Wh;
-  const float wgt = (k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int e = (t + T * m) * C + c;
-    tile[e] = v[m];
-    float qq = 0.0f, t2 = 0.0f;
-    if (valid) {
-      const cf h = H[off + e], y = Y[off + e];
-      const cf r = cmul(h, v[m]) - y;
-      qq = wgt * abs2f(r);
-      t2 = abs2f(h);
-    }
-    q[off + e] = qq;
-    acc[0] += qq;
-    {
-      const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu_floor, 1.0f));
-      acc[1] = __fmaf_rn(qq, r * r, acc[1]);
-    }
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const float r = __builtin_amdgcn_rcpf(__fmaf_rn(t2, mu[j], 1.0f));
-      const float qg = qq * (r * r);
-      acc[2 + j] += qg;
-      acc[2 + NC + j] = __fmaf_rn(qg, 1.0f - r, acc[2 + NC + j]);
-    }
-  }
-  float hi[2 + 2 * NC], lo[2 + 2 * NC];
-  block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
-  if (threadIdx.x == 0) {
-    float *dst = lb.partials + (size_t)blockIdx.x * kLamAcc * 2;
-    for (int a = 0; a < 2 + 2 * NC; ++a) {
-      dst[2 * a] = hi[a];
-      dst[2 * a + 1] = lo[a];
-    }
-  }
+  GFD_ITEM_END
 }
 
-// Solves (Eqs. 8-9) and column inverse of both spectra; U_I waits in registers.
-__global__ void __launch_bounds__(512) k_col_inv_r16(const cf *__restrict__ UE, const cf *__restrict__ HY,
-                                                      const float *__restrict__ H2, const float *__restrict__ dM,
-                                                      const float *__restrict__ dN, Layout lay, RegPlan rp,
-                                                      const cf *__restrict__ tw, LamState *st, cf *__restrict__ SI,
-                                                      cf *__restrict__ SP) {
+__global__ void __launch_bounds__(512) k_col_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+                                                     int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
-  const int C = lay.C, T = rp.T;
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
+  const int C = lay.C, T = d.rm.T;
   const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
-  const size_t off = (size_t)blockIdx.x * lay.M * C;
-  const float lam = st->lam, invP = st->invP;
-  const bool inf_branch = isinf(lam);
-  const bool big = lam >= 1.0f;
-  const float mu = big ? 1.0f / lam : 0.0f;
-  const int k = blockIdx.x * C + c;
-  const bool valid = k < lay.Wh;
-  const float dk = valid ? dN[k] : 0.0f;
+  const bool active = t < T;
+  const size_t off = (size_t)wi.blk * lay.M * C;
+  const SolveParams sp = solve_params(d.st);
+  const int k = wi.blk * C + c;
+  const bool valid = active && k < lay.Wh;
+  const float dk = valid ? G(d.dN)[k] : 0.0f;
   cf vp[16], vi[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int row = t + T * m;
-    const int e = row * C + c;
     cf Up = {0.0f, 0.0f}, Ui = {0.0f, 0.0f};
     if (valid) {
-      const cf U = UE[off + e];
-      if (inf_branch) {
-        Up = cscale(U, invP);
-        Ui = Up;
-      } else {
-        const cf hy = HY[off + e];
-        const float t2 = H2[off + e];
-        const float d2 = dM[row] + dk;
-        if (big) {
-          const float ip = invP * __builtin_amdgcn_rcpf(__fmaf_rn(mu, t2, 1.0f));
-          const float ii = invP * __builtin_amdgcn_rcpf(__fmaf_rn(mu, t2, d2));
-          Up = cf{(__fmaf_rn(mu, hy.re, U.re)) * ip, (__fmaf_rn(mu, hy.im, U.im)) * ip};
-          Ui = cf{(__fmaf_rn(mu, hy.re, d2 * U.re)) * ii, (__fmaf_rn(mu, hy.im, d2 * U.im)) * ii};
-        } else {
-          const float ip = invP * __builtin_amdgcn_rcpf(t2 + lam);
-          const float ld = lam * d2;
-          const float ii = invP * __builtin_amdgcn_rcpf(t2 + ld);
-          Up = cf{__fmaf_rn(lam, U.re, hy.re) * ip, __fmaf_rn(lam, U.im, hy.im) * ip};
-          Ui = cf{__fmaf_rn(ld, U.re, hy.re) * ii, __fmaf_rn(ld, U.im, hy.im) * ii};
-        }
-      }
+      const int e = row * C + c;
+      solve_bin(sp, G(d.S1)[off + e], G(d.HY)[off + e], G(d.H2)[off + e], G(d.dM)[row] + dk, Up, Ui);
       if (k == 0 && row == 0) {
-        st->meanP = Up.re;
-        st->meanI = Ui.re;
+        d.st->meanP = Up.re;
+        d.st->meanI = Ui.re;
       }
     }
     vp[m] = Up;
     vi[m] = Ui;
   }
-  reg_fft<+1>(vp, t, rp, lds + c, C, tw);
+  reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
+  if (active) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) SP[off + (t + T * m) * C + c] = vp[m];
-  reg_fft<+1>(vi, t, rp, lds + c, C, tw);
+    for (int m = 0; m < 16; ++m) G(d.SP)[off + (t + T * m) * C + c] = vp[m];
+  }
+  reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
+  if (active) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) SI[off + (t + T * m) * C + c] = vi[m];
+    for (int m = 0; m < 16; ++m) G(d.SI)[off + (t + T * m) * C + c] = vi[m];
+  }
+  GFD_ITEM_END
 }
 
-// Row pass, inverse: block = Ri rows x T threads; the Hermitian completion is gathered
-// straight from the tile-major spectra.
-__global__ void __launch_bounds__(512) k_row_inv_r16(const cf *__restrict__ SI, const cf *__restrict__ SP,
-                                                      Layout lay, RegPlan rp, const cf *__restrict__ tw,
-                                                      float *__restrict__ uI, float *__restrict__ uP) {
+// Row pass, inverse; the Hermitian completion is gathered straight from the tile-major spectra.
+__global__ void __launch_bounds__(512) k_row_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+                                                     int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
-  const int M = lay.M, N = lay.N, C = lay.C, Wh = lay.Wh, T = rp.T;
+  GFD_ITEM_LOOP
+  const Layout &lay = d.L;
+  const int M = lay.M, N = lay.N, C = lay.C, Wh = lay.Wh, T = d.rn.T;
   const int LP = N + (N >> 4);
   const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
-  const int m0 = xcd_remap(blockIdx.x, gridDim.x) * lay.Ri;
-  const int row = m0 + seq;
+  const bool active = seq < lay.Ri;
+  const int row = wi.blk * lay.Ri + seq;
   const int rowc = row < M ? row : M - 1;  // rows past the end compute a copy, never stored
   cf v[16];
+  if (active) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int n = t + T * m;
-    const bool direct = n < Wh;
-    const int kk = direct ? n : N - n;
-    const size_t g = ((size_t)(kk >> lay.logC) * M + rowc) * C + (kk & (C - 1));
-    cf A = SI[g], B = SP[g];
-    if (kk == 0 || 2 * kk == N) {
-      A.im = 0.0f;
-      B.im = 0.0f;
+    for (int m = 0; m < 16; ++m) {
+      const int n = t + T * m;
+      const bool direct = n < Wh;
+      const int kk = direct ? n : N - n;
+      const size_t g = ((size_t)(kk >> lay.logC) * M + rowc) * C + (kk & (C - 1));
+      cf A = G(d.SI)[g], B = G(d.SP)[g];
+      if (kk == 0 || 2 * kk == N) {
+        A.im = 0.0f;
+        B.im = 0.0f;
+      }
+      v[m] = direct ? cf{A.re - B.im, A.im + B.re} : cf{A.re + B.im, B.re - A.im};
     }
-    v[m] = direct ? cf{A.re - B.im, A.im + B.re} : cf{A.re + B.im, B.re - A.im};
   }
-  reg_fft<+1>(v, t, rp, lds + seq * LP, 1, tw);
-  if (row < M) {
+  reg_fft<+1>(v, t, active, d.rn, lds + seq * LP, 1, G(d.twN));
+  if (active && row < M) {
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const size_t g = (size_t)row * N + t + T * m;
-      uI[g] = v[m].re;
-      uP[g] = v[m].im;
+      G(d.uI)[g] = v[m].re;
+      G(d.uP)[g] = v[m].im;
     }
   }
+  GFD_ITEM_END
 }
 
-// ============================================================================ init kernels
+// ============================================================================ lambda search kernels
+// After the residual pass: one block per image finishes the first round.
+__global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
+  __shared__ float scratch[2 * kLamAcc * 16];
+  GFD_ITEM_LOOP
+  constexpr int NC = kLamFirstCand;
+  float hi[2 + 2 * NC], lo[2 + 2 * NC];
+  reduce_partials<2 + 2 * NC>(G(d.part), d.npart, d.L.NT, hi, lo, scratch);
+  if (threadIdx.x == 0) {
+    LamState *st = d.st;
+    st->phase = 0;
+    st->flags = 0;
+    float cand[NC];
+    for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
+    if (lam_begin(*st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(d);
+  }
+  GFD_ITEM_END
+}
+
+// One evaluation round: per-chunk sums of q g_j and q g_j (1 - r_j) over the bins.
+__global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
+  __shared__ float scratch[kLamAcc * 4];
+  constexpr int NC = kLamMaxCand;
+  GFD_ITEM_LOOP
+  if (d.st->phase == 0) {
+    float mu[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) mu[j] = d.st->mu[j];
+    float acc[2 * NC];
+#pragma unroll
+    for (int v = 0; v < 2 * NC; ++v) acc[v] = 0.0f;
+    const size_t nbins = d.L.bins(), n4 = nbins / 4;
+    const GFD_AS1 float4 *q4 = reinterpret_cast<const GFD_AS1 float4 *>(G(d.q));
+    const GFD_AS1 float4 *h4 = reinterpret_cast<const GFD_AS1 float4 *>(G(d.H2));
+    for (size_t i = (size_t)wi.blk * blockDim.x + threadIdx.x; i < n4; i += (size_t)d.nchunk * blockDim.x) {
+      const float4 qa = q4[i], ta = h4[i];
+      const float qs[4] = {qa.x, qa.y, qa.z, qa.w}, ts[4] = {ta.x, ta.y, ta.z, ta.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float r = __builtin_amdgcn_rcpf(__fmaf_rn(ts[u], mu[j], 1.0f));
+          const float qg = qs[u] * (r * r);
+          acc[j] += qg;
+          acc[NC + j] = __fmaf_rn(qg, 1.0f - r, acc[NC + j]);
+        }
+      }
+    }
+    if (wi.blk == 0) {  // bins that do not fill a float4
+      for (size_t i = n4 * 4 + threadIdx.x; i < nbins; i += blockDim.x) {
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+          const float r = __builtin_amdgcn_rcpf(__fmaf_rn(G(d.H2)[i], mu[j], 1.0f));
+          const float qg = G(d.q)[i] * (r * r);
+          acc[j] += qg;
+          acc[NC + j] = __fmaf_rn(qg, 1.0f - r, acc[NC + j]);
+        }
+      }
+    }
+    float hi[2 * NC], lo[2 * NC];
+    block_sum_plain_then_df<2 * NC>(acc, hi, lo, scratch);
+    if (threadIdx.x == 0) store_partials(G(d.part), d.npart, wi.blk, 2 * NC, hi, lo);
+  }
+  GFD_ITEM_END
+}
+
+// One block per image folds a round into the bracket and picks the next candidates.
+__global__ void __launch_bounds__(1024) k_lam_round(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
+                                                    int last) {
+  __shared__ float scratch[2 * kLamAcc * 16];
+  constexpr int NC = kLamMaxCand;
+  GFD_ITEM_LOOP
+  if (d.st->phase == 0) {
+    float hi[2 * NC], lo[2 * NC];
+    reduce_partials<2 * NC>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
+    if (threadIdx.x == 0) {
+      LamState *st = d.st;
+      float cand[NC];
+      for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
+      lam_absorb(*st, NC, cand, hi, lo, hi + NC);
+      if (lam_decide(*st, last != 0)) lam_commit(d);
+    }
+  }
+  GFD_ITEM_END
+}
+
+// ============================================================================ set-up kernels (one image)
+template <class T, class TI, int E>
+__global__ void __launch_bounds__(1024) k_row_fwd_plain(const TI *__restrict__ x, Layout lay, FftPlan pn,
+                                                        const cpx<T> *__restrict__ tw, cpx<T> *__restrict__ S) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  row_fwd_body<T, E>(G(x), lay, pn, G(tw), G(S), blockIdx.x, reinterpret_cast<cpx<T> *>(smem_raw));
+}
+
+template <class T, int E>
+__global__ void __launch_bounds__(1024) k_col_fwd_plain(cpx<T> *__restrict__ S, Layout lay, FftPlan pm,
+                                                        const cpx<T> *__restrict__ tw) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem_raw);
+  const int n = lay.M * lay.C;
+  GFD_AS1 cpx<T> *tile = G(S) + (size_t)blockIdx.x * n;
+  col_fwd_load_fft<T, E>(tile, lay, pm, G(tw), buf);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) tile[e] = buf[e];
+}
+
 // Periodic embedding: entry (i, j) of the centred kh x kw PSF goes to ((i - kh/2) mod M,
 // (j - kw/2) mod N).  With kh <= M and kw <= N the targets are distinct, so the scatter
 // needs no atomics; the array is cleared first.
@@ -634,8 +660,7 @@ __global__ void k_embed_psf(const float *__restrict__ h, int kh, int kw, int M, 
 // Constants of the solves in FP32, derived in FP64: H, Y (residual), conj(H) Y and |H|^2
 // (solves and search).  |H|^2 uses the same FP32 expression as the residual pass.
 __global__ void k_init_consts(const cd *__restrict__ Hd, const cd *__restrict__ Yd, size_t n, int Wh, int M, int C,
-                              int logC, cf *__restrict__ H, cf *__restrict__ Y, cf *__restrict__ HY,
-                              float *__restrict__ H2) {
+                              cf *__restrict__ H, cf *__restrict__ Y, cf *__restrict__ HY, float *__restrict__ H2) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const size_t t = i / ((size_t)M * C);
     const int c = (int)(i & (size_t)(C - 1));
@@ -665,7 +690,7 @@ __global__ void k_d2_tables(int M, int N, int Wh, float *dM, float *dN) {
   }
 }
 
-// FP64 sums over y for Eq.(12): stage 1 per-block partial sums of y and y^2.
+// FP64 sums over y for Eq.(12): per-block sums of y and y^2, then of (y - mean)^2.
 __global__ void k_ysums(const float *__restrict__ y, size_t n, double *__restrict__ part) {
   __shared__ double sh[2][256];
   double s1 = 0.0, s2 = 0.0;
@@ -690,7 +715,6 @@ __global__ void k_ysums(const float *__restrict__ y, size_t n, double *__restric
   }
 }
 
-// Stage 2: centred sum of squares sum (y - mean)^2 (second pass, per block).
 __global__ void k_ycentred(const float *__restrict__ y, size_t n, const double *__restrict__ part, int nparts,
                            double *__restrict__ part2) {
   __shared__ double sh[256];
@@ -703,8 +727,8 @@ __global__ void k_ycentred(const float *__restrict__ y, size_t n, const double *
   __syncthreads();
   double s = 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double d = (double)y[i] - mean;
-    s += d * d;
+    double dd = (double)y[i] - mean;
+    s += dd * dd;
   }
   sh[threadIdx.x] = s;
   __syncthreads();
@@ -715,8 +739,8 @@ __global__ void k_ycentred(const float *__restrict__ y, size_t n, const double *
   if (threadIdx.x == 0) part2[blockIdx.x] = sh[0];
 }
 
-// Stage 3: rho of Eq.(12) (radicand clipped to [1e-12, 1]) unless fixed, target
-// T = rho P sigma^2, and the constants of the search state.
+// rho of Eq.(12) (radicand clipped to [1e-12, 1]) unless fixed, target T = rho P sigma^2, and
+// the constants of the search state.
 __global__ void k_rho_final(const double *__restrict__ part, const double *__restrict__ part2, int nparts,
                             const float *__restrict__ h, int nh, size_t n, double sigma2, double rho_fixed,
                             double *out2, LamState *st) {
@@ -799,7 +823,7 @@ Layout make_layout(int M, int N) {
   L.C = C;
   L.logC = ilog2(C);
   L.NT = (L.Wh + C - 1) / C;
-  // rows per block in the row passes: aim at >= 128-byte segments, keep LDS <= 64 KiB
+  // rows per block in the LDS-resident row passes: aim at >= 128-byte segments, LDS <= 64 KiB
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
   L.R = R;
@@ -824,8 +848,7 @@ Layout make_layout(int M, int N) {
 }
 
 FftPlan make_plan(int L) {
-  FftPlan p;
-  p = FftPlan{};
+  FftPlan p = FftPlan{};
   p.L = L;
   int rad[kMaxPasses];
   int n = 0, rest = L, a = 0;
@@ -851,37 +874,21 @@ FftPlan make_plan(int L) {
   return p;
 }
 
-// Elements per thread for a block of `threads` threads over `elems` elements.
+int lam_sweep_chunks(size_t nbins) {
+  size_t want = (nbins / 4 + 255) / 256;
+  if (want < 1) want = 1;
+  if (want > 512) want = 512;
+  return (int)want;
+}
+
+// Threads and elements per thread of a LDS-resident transform over `elems` elements.
 static int pick_E(size_t elems, int &threads) {
   threads = 256;
   while ((size_t)threads * 16 < elems && threads < 1024) threads *= 2;
   size_t e = (elems + threads - 1) / threads;
   if (e <= 4) return 4;
   if (e <= 8) return 8;
-  return 16;  // callers keep elems <= 16 * 1024
-}
-
-#define GFD_DISPATCH_E(E_, ...)                  \
-  switch (E_) {                                  \
-    case 4: { constexpr int EE = 4; __VA_ARGS__; } break;   \
-    case 8: { constexpr int EE = 8; __VA_ARGS__; } break;   \
-    default: { constexpr int EE = 16; __VA_ARGS__; } break; \
-  }
-
-template <class T, class TI>
-static hipError_t row_fwd_any(const TI *x, const Layout &L, const FftPlan &pn, const cpx<T> *tw, cpx<T> *S,
-                              hipStream_t st) {
-  int threads;
-  int E = pick_E((size_t)(L.R / 2) * L.N, threads);
-  size_t lds = (size_t)(L.R / 2) * (L.N + 1) * sizeof(cpx<T>);
-  int blocks = (L.M + L.R - 1) / L.R;
-  GFD_DISPATCH_E(E, {
-    auto kern = k_row_fwd<T, TI, EE>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, x, L, pn, tw, S);
-  });
-  return hipGetLastError();
+  return 16;  // elems <= 16 * 1024 by construction of the layout
 }
 
 template <class K>
@@ -889,143 +896,219 @@ static hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_row_fwd(const float *x, const Layout &L, const FftPlan &pn, const cf *twN, cf *S, hipStream_t st) {
-  if (reg_plan_ok(L.N)) {
-    const RegPlan rp = make_reg_plan(L.N);
-    const size_t lds = (size_t)(L.Rf / 2) * (L.N + L.N / 16) * sizeof(cf);
-    hipError_t e = set_lds(k_row_fwd_r16, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_fwd_r16, dim3((L.M + L.Rf - 1) / L.Rf), dim3((L.Rf / 2) * rp.T), lds, st, x, L, rp, twN,
-                       S);
-    return hipGetLastError();
+// Append the work items of one image (blocks 0 .. nblk-1), padded to a multiple of 8 and
+// permuted so that every 8th item (one XCD's share) covers a contiguous run of blocks.
+static void append_items(ImgSet &set, int img, int nblk) {
+  const int nx = 8;
+  const int padded = (nblk + nx - 1) / nx * nx;
+  const int per = padded / nx;
+  for (int i = 0; i < padded; ++i) {
+    const int xcd = i % nx, local = i / nx;
+    const int blk = xcd * per + local;
+    set.items_host.push_back(Item{img, blk < nblk ? blk : -1});
   }
-  return row_fwd_any<float, float>(x, L, pn, twN, S, st);
 }
+
+struct ItemRange {
+  size_t off, n;
+};
+
+static ItemRange add_items(ImgSet &set, const std::vector<int> &imgs, const std::function<int(const Img &)> &nblk) {
+  ItemRange r{set.items_host.size(), 0};
+  for (int i : imgs) append_items(set, i, nblk(set.imgs[i]));
+  r.n = set.items_host.size() - r.off;
+  return r;
+}
+
+// One launch over an item range (grid = number of items, one item per block).
+template <class K, class... A>
+static Launch make_launch(ImgSet *setp, K kern, ItemRange r, int threads, size_t lds, A... extra) {
+  return [=](hipStream_t s) -> hipError_t {
+    if (r.n == 0) return hipSuccess;
+    if (lds > 48 * 1024) {
+      hipError_t e = set_lds(kern, lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)r.n), dim3(threads), lds, s, (const Img *)setp->dev,
+                       (const Item *)(setp->items_dev + r.off), (int)r.n, extra...);
+    return hipGetLastError();
+  };
+}
+
+// Group images by a key and call `emit` for each group.
+using GKey = std::tuple<int, int, int>;  // (register-resident?, threads, E)
+static void group_by(const ImgSet &set, const std::vector<int> &sel, const std::function<GKey(const Img &)> &key,
+                     const std::function<void(const GKey &, const std::vector<int> &)> &emit) {
+  std::map<GKey, std::vector<int>> g;
+  for (int i : sel) g[key(set.imgs[i])].push_back(i);
+  for (auto &kv : g) emit(kv.first, kv.second);
+}
+
+template <class K4, class K8, class K16>
+static auto pickE(int E, K4 a, K8 b, K16 c) {
+  return E == 4 ? a : E == 8 ? b : c;
+}
+
+void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
+  group_by(set, sel, [](const Img &d) {
+    if (reg_plan_ok(d.L.N)) return GKey{1, 0, 0};
+    int th; int E = pick_E((size_t)(d.L.R / 2) * d.L.N, th);
+    return GKey{0, th, E};
+  }, [&](const GKey &k, const std::vector<int> &imgs) {
+    if (std::get<0>(k)) {
+      int threads = 0; size_t lds = 0;
+      for (int i : imgs) {
+        const Img &d = set.imgs[i];
+        threads = std::max(threads, (d.L.Rf / 2) * d.rn.T);
+        lds = std::max(lds, (size_t)(d.L.Rf / 2) * (d.L.N + d.L.N / 16) * sizeof(cf));
+      }
+      ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Rf - 1) / d.L.Rf; });
+      p.steps.push_back(make_launch(&set, k_row_fwd_r16, r, threads, lds));
+    } else {
+      const int threads = std::get<1>(k), E = std::get<2>(k);
+      size_t lds = 0;
+      for (int i : imgs) lds = std::max(lds, (size_t)(set.imgs[i].L.R / 2) * (set.imgs[i].L.N + 1) * sizeof(cf));
+      ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.R - 1) / d.L.R; });
+      p.steps.push_back(make_launch(&set, pickE(E, k_row_fwd_g<4>, k_row_fwd_g<8>, k_row_fwd_g<16>), r, threads, lds));
+    }
+  });
+}
+
+void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid) {
+  group_by(set, sel, [](const Img &d) {
+    if (reg_plan_ok(d.L.M)) return GKey{1, 0, 0};
+    int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
+    return GKey{0, th, E};
+  }, [&](const GKey &k, const std::vector<int> &imgs) {
+    ItemRange r = add_items(set, imgs, [](const Img &d) { return d.L.NT; });
+    if (std::get<0>(k)) {
+      int threads = 0; size_t lds = 0;
+      for (int i : imgs) {
+        const Img &d = set.imgs[i];
+        threads = std::max(threads, d.L.C * d.rm.T);
+        lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
+      }
+      p.steps.push_back(resid ? make_launch(&set, k_col_fwd_r16<true>, r, threads, lds)
+                              : make_launch(&set, k_col_fwd_r16<false>, r, threads, lds));
+    } else {
+      const int threads = std::get<1>(k), E = std::get<2>(k);
+      size_t lds = 0;
+      for (int i : imgs) lds = std::max(lds, (size_t)set.imgs[i].L.M * set.imgs[i].L.C * sizeof(cf));
+      if (resid)
+        p.steps.push_back(make_launch(&set, pickE(E, k_col_fwd_g<4, true>, k_col_fwd_g<8, true>, k_col_fwd_g<16, true>),
+                                      r, threads, lds));
+      else
+        p.steps.push_back(make_launch(
+            &set, pickE(E, k_col_fwd_g<4, false>, k_col_fwd_g<8, false>, k_col_fwd_g<16, false>), r, threads, lds));
+    }
+  });
+}
+
+void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds) {
+  ItemRange one = add_items(set, sel, [](const Img &) { return 1; });
+  p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0));
+  ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
+  for (int k = 0; k < rounds; ++k) {
+    p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0));
+    p.steps.push_back(make_launch(&set, k_lam_round, one, 1024, 0, (int)(k == rounds - 1)));
+  }
+}
+
+void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
+  group_by(set, sel, [](const Img &d) {
+    if (reg_plan_ok(d.L.M)) return GKey{1, 0, 0};
+    int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
+    return GKey{0, th, E};
+  }, [&](const GKey &k, const std::vector<int> &imgs) {
+    ItemRange r = add_items(set, imgs, [](const Img &d) { return d.L.NT; });
+    if (std::get<0>(k)) {
+      int threads = 0; size_t lds = 0;
+      for (int i : imgs) {
+        const Img &d = set.imgs[i];
+        threads = std::max(threads, d.L.C * d.rm.T);
+        lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
+      }
+      p.steps.push_back(make_launch(&set, k_col_inv_r16, r, threads, lds));
+    } else {
+      const int threads = std::get<1>(k), E = std::get<2>(k);
+      size_t lds = 0;
+      for (int i : imgs) lds = std::max(lds, (size_t)set.imgs[i].L.M * set.imgs[i].L.C * sizeof(cf));
+      p.steps.push_back(make_launch(&set, pickE(E, k_col_inv_g<4>, k_col_inv_g<8>, k_col_inv_g<16>), r, threads, lds));
+    }
+  });
+}
+
+void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
+  group_by(set, sel, [](const Img &d) {
+    if (reg_plan_ok(d.L.N)) return GKey{1, 0, 0};
+    int th; int E = pick_E((size_t)d.L.R * d.L.N, th);
+    return GKey{0, th, E};
+  }, [&](const GKey &k, const std::vector<int> &imgs) {
+    if (std::get<0>(k)) {
+      int threads = 0; size_t lds = 0;
+      for (int i : imgs) {
+        const Img &d = set.imgs[i];
+        threads = std::max(threads, d.L.Ri * d.rn.T);
+        lds = std::max(lds, (size_t)d.L.Ri * (d.L.N + d.L.N / 16) * sizeof(cf));
+      }
+      ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Ri - 1) / d.L.Ri; });
+      p.steps.push_back(make_launch(&set, k_row_inv_r16, r, threads, lds));
+    } else {
+      const int threads = std::get<1>(k), E = std::get<2>(k);
+      size_t lds = 0;
+      for (int i : imgs) lds = std::max(lds, (size_t)set.imgs[i].L.R * (set.imgs[i].L.N + 1) * sizeof(cf));
+      ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.R - 1) / d.L.R; });
+      p.steps.push_back(make_launch(&set, pickE(E, k_row_inv_g<4>, k_row_inv_g<8>, k_row_inv_g<16>), r, threads, lds));
+    }
+  });
+}
+
+hipError_t finalize_items(ImgSet &set) {
+  if (set.items_dev) {
+    hipError_t e = hipFree(set.items_dev);
+    set.items_dev = nullptr;
+    if (e != hipSuccess) return e;
+  }
+  size_t n = std::max<size_t>(set.items_host.size(), 1);
+  hipError_t e = hipMalloc((void **)&set.items_dev, n * sizeof(Item));
+  if (e != hipSuccess) return e;
+  if (!set.items_host.empty())
+    e = hipMemcpy(set.items_dev, set.items_host.data(), set.items_host.size() * sizeof(Item), hipMemcpyHostToDevice);
+  return e;
+}
+
+// ---------------------------------------------------------------- set-up launchers (one image)
+template <class T, class TI>
+static hipError_t row_fwd_plain(const TI *x, const Layout &L, const FftPlan &pn, const cpx<T> *tw, cpx<T> *S,
+                                hipStream_t st) {
+  int threads;
+  int E = pick_E((size_t)(L.R / 2) * L.N, threads);
+  size_t lds = (size_t)(L.R / 2) * (L.N + 1) * sizeof(cpx<T>);
+  int blocks = (L.M + L.R - 1) / L.R;
+  auto kern = pickE(E, k_row_fwd_plain<T, TI, 4>, k_row_fwd_plain<T, TI, 8>, k_row_fwd_plain<T, TI, 16>);
+  hipError_t e = set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, x, L, pn, tw, S);
+  return hipGetLastError();
+}
+
 hipError_t launch_row_fwd_d(const double *x, const Layout &L, const FftPlan &pn, const cd *twN, cd *S,
                             hipStream_t st) {
-  return row_fwd_any<double, double>(x, L, pn, twN, S, st);
+  return row_fwd_plain<double, double>(x, L, pn, twN, S, st);
 }
 hipError_t launch_row_fwd_fd(const float *x, const Layout &L, const FftPlan &pn, const cd *twN, cd *S,
                              hipStream_t st) {
-  return row_fwd_any<double, float>(x, L, pn, twN, S, st);
+  return row_fwd_plain<double, float>(x, L, pn, twN, S, st);
 }
 
-template <class T>
-static hipError_t col_fwd_any(cpx<T> *S, const Layout &L, const FftPlan &pm, const cpx<T> *tw, hipStream_t st) {
-  int threads;
-  int E = pick_E((size_t)L.M * L.C, threads);
-  size_t lds = (size_t)L.M * L.C * sizeof(cpx<T>);
-  GFD_DISPATCH_E(E, {
-    auto kern = k_col_fwd<T, EE>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(L.NT), dim3(threads), lds, st, S, L, pm, tw);
-  });
-  return hipGetLastError();
-}
 hipError_t launch_col_fwd_d(cd *S, const Layout &L, const FftPlan &pm, const cd *twM, hipStream_t st) {
-  return col_fwd_any<double>(S, L, pm, twM, st);
-}
-static size_t col_r16_lds(const Layout &L) { return (size_t)L.C * (L.M + L.M / 16) * sizeof(cf); }
-
-hipError_t launch_col_fwd_f(cf *S, const Layout &L, const FftPlan &pm, const cf *twM, hipStream_t st) {
-  if (reg_plan_ok(L.M)) {
-    const RegPlan rp = make_reg_plan(L.M);
-    const size_t lds = col_r16_lds(L);
-    hipError_t e = set_lds(k_col_fwd_r16<false>, lds);
-    if (e != hipSuccess) return e;
-    LamBuffers none = {};
-    hipLaunchKernelGGL(k_col_fwd_r16<false>, dim3(L.NT), dim3(L.C * rp.T), lds, st, S, nullptr, nullptr, nullptr, L, rp,
-                       twM, none);
-    return hipGetLastError();
-  }
-  return col_fwd_any<float>(S, L, pm, twM, st);
-}
-
-hipError_t launch_col_fwd_resid(cf *S, float *q, const cf *H, const cf *Y, const Layout &L, const FftPlan &pm,
-                                const cf *twM, const LamBuffers &lb, hipStream_t st) {
-  if (reg_plan_ok(L.M)) {
-    const RegPlan rp = make_reg_plan(L.M);
-    const size_t lds = col_r16_lds(L);
-    hipError_t e = set_lds(k_col_fwd_r16<true>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_col_fwd_r16<true>, dim3(L.NT), dim3(L.C * rp.T), lds, st, S, q, H, Y, L, rp, twM, lb);
-    hipLaunchKernelGGL(k_lam_begin, dim3(1), dim3(256), 0, st, lb, L.NT);
-    return hipGetLastError();
-  }
   int threads;
   int E = pick_E((size_t)L.M * L.C, threads);
-  size_t lds = (size_t)L.M * L.C * sizeof(cf);
-  GFD_DISPATCH_E(E, {
-    auto kern = k_col_fwd_resid<EE>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(L.NT), dim3(threads), lds, st, S, q, H, Y, L, pm, twM, lb);
-  });
-  hipLaunchKernelGGL(k_lam_begin, dim3(1), dim3(256), 0, st, lb, L.NT);
-  return hipGetLastError();
-}
-
-int lam_sweep_blocks(size_t nbins) {
-  size_t want = (nbins / 4 + 255) / 256;
-  if (want < 1) want = 1;
-  if (want > 512) want = 512;
-  return (int)want;
-}
-
-hipError_t launch_lam_sweep(const float *q, const float *H2, size_t nbins, const LamBuffers &lb, int last,
-                            hipStream_t st) {
-  const int nb = lam_sweep_blocks(nbins);
-  hipLaunchKernelGGL(k_lam_sweep<kLamMaxCand>, dim3(nb), dim3(256), 0, st, q, H2, nbins, lb);
-  hipLaunchKernelGGL(k_lam_round, dim3(1), dim3(256), 0, st, lb, nb, last);
-  return hipGetLastError();
-}
-
-hipError_t launch_col_inv(const cf *UE, const cf *HY, const float *H2, const float *dM, const float *dN,
-                          const Layout &L, const FftPlan &pm, const cf *twM, const LamBuffers &lb, cf *SI, cf *SP,
-                          hipStream_t st) {
-  if (reg_plan_ok(L.M)) {
-    const RegPlan rp = make_reg_plan(L.M);
-    const size_t lds = col_r16_lds(L);
-    hipError_t e = set_lds(k_col_inv_r16, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_col_inv_r16, dim3(L.NT), dim3(L.C * rp.T), lds, st, UE, HY, H2, dM, dN, L, rp, twM, lb.st, SI,
-                       SP);
-    return hipGetLastError();
-  }
-  int threads;
-  int E = pick_E((size_t)L.M * L.C, threads);
-  size_t lds = (size_t)L.M * L.C * sizeof(cf);
-  GFD_DISPATCH_E(E, {
-    auto kern = k_col_inv<EE>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(L.NT), dim3(threads), lds, st, UE, HY, H2, dM, dN, L, pm, twM, lb.st, SI, SP);
-  });
-  return hipGetLastError();
-}
-
-hipError_t launch_row_inv(const cf *SI, const cf *SP, const Layout &L, const FftPlan &pn, const cf *twN, float *uI,
-                          float *uP, hipStream_t st) {
-  if (reg_plan_ok(L.N)) {
-    const RegPlan rp = make_reg_plan(L.N);
-    const size_t lds = (size_t)L.Ri * (L.N + L.N / 16) * sizeof(cf);
-    hipError_t e = set_lds(k_row_inv_r16, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_inv_r16, dim3((L.M + L.Ri - 1) / L.Ri), dim3(L.Ri * rp.T), lds, st, SI, SP, L, rp, twN, uI,
-                       uP);
-    return hipGetLastError();
-  }
-  int threads;
-  int E = pick_E((size_t)L.R * L.N, threads);
-  size_t lds = (size_t)L.R * (L.N + 1) * sizeof(cf);
-  int blocks = (L.M + L.R - 1) / L.R;
-  GFD_DISPATCH_E(E, {
-    auto kern = k_row_inv<EE>;
-    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, SI, SP, L, pn, twN, uI, uP);
-  });
+  size_t lds = (size_t)L.M * L.C * sizeof(cd);
+  auto kern = pickE(E, k_col_fwd_plain<double, 4>, k_col_fwd_plain<double, 8>, k_col_fwd_plain<double, 16>);
+  hipError_t e = set_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(L.NT), dim3(threads), lds, st, S, L, pm, twM);
   return hipGetLastError();
 }
 
@@ -1043,7 +1126,7 @@ hipError_t launch_init_consts(const cd *Hd, const cd *Yd, const Layout &L, cf *H
   size_t n = L.bins();
   int blocks = (int)((n + 255) / 256);
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_init_consts, dim3(blocks), dim3(256), 0, st, Hd, Yd, n, L.Wh, L.M, L.C, L.logC, H, Y, HY, H2);
+  hipLaunchKernelGGL(k_init_consts, dim3(blocks), dim3(256), 0, st, Hd, Yd, n, L.Wh, L.M, L.C, H, Y, HY, H2);
   return hipGetLastError();
 }
 

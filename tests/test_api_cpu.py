@@ -80,3 +80,20 @@ def test_foreign_and_null_contexts():
     lib.deconv_destroy(None)
     lib.deconv_destroy(bogus)   # unknown pointers are ignored, never dereferenced
     assert "invalid" in lib.gfd_last_error().decode() or lib.gfd_last_error() is not None
+
+
+def test_batch_descriptors_are_checked_without_gpu():
+    lib = gfd.load_library()
+    ctx = ctypes.c_void_p()
+    fake = 0x1000
+    good = gfd.GfdImage(fake, 64, 64, fake, 3, 3, 1.0, 3, 1.0, -1.0)
+    bad = gfd.GfdImage(fake, 64, 64, fake, 3, 3, 1.0, 4, 1.0, -1.0)      # even window
+    arr = (gfd.GfdImage * 3)(good, good, bad)
+    rc = lib.deconv_init_batch(ctypes.byref(ctx), ctypes.cast(arr, ctypes.c_void_p), 3, None)
+    assert rc == -1 and ctx.value is None
+    assert "image 2" in lib.gfd_last_error().decode()
+    assert lib.deconv_init_batch(ctypes.byref(ctx), ctypes.cast(arr, ctypes.c_void_p), 0, None) == -1
+    assert lib.deconv_init_batch(ctypes.byref(ctx), None, 1, None) == -1
+    assert lib.deconv_init_batch(ctypes.byref(ctx), ctypes.cast(arr, ctypes.c_void_p), 5000, None) == -1
+    assert lib.deconv_image_info(None, 0, None, None, None, None) == -5
+    assert ctypes.sizeof(gfd.GfdImage) == 56

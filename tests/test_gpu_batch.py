@@ -1,0 +1,113 @@
+"""Batched contexts: one context for many independent images gives, image by image, exactly
+what separate single-image contexts give (same kernels and arithmetic, one launch per pass),
+and matches the FP64 oracle like a single image does."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1609_01839_amd as gfd
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+# mixed kinds: register-resident transforms (powers of two >= 256), LDS transforms (others)
+SMALL_SIZES = [(64, 80), (96, 96), (256, 256), (75, 90), (128, 120), (256, 512), (45, 75), (512, 256)]
+
+
+def to_gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def problems(cases):
+    return [dict(y=to_gpu(c.y), h=to_gpu(c.h.astype(np.float32)), sigma2=c.sigma2, w=c.w, eps=c.eps) for c in cases]
+
+
+def single_runs(probs, chunks, estimates=None):
+    out = []
+    for k, p in enumerate(probs):
+        with gfd.GFDeconv(p["y"], p["h"], p["sigma2"], p["w"], p["eps"]) as g:
+            if estimates is not None:
+                g.set_estimate(estimates[k])
+            lams = []
+            for n in chunks:
+                u, lam = g.iterate(n)
+                lams.append(lam.cpu().numpy())
+            out.append((u.cpu().numpy(), np.concatenate(lams), g.info()))
+    return out
+
+
+def test_batch_equals_single_contexts():
+    cases = synth.make_batch(10, sizes=SMALL_SIZES)
+    print("batch:", " ".join(f"{c.y.shape[0]}x{c.y.shape[1]}/w{c.w}" for c in cases))
+    probs = problems(cases)
+    ref = single_runs(probs, [2, 4])
+    with gfd.GFDeconvBatch(probs) as g:
+        us1, lam1 = g.iterate(2)
+        us1 = [u.cpu().numpy() for u in us1]
+        us, lam2 = g.iterate(4)
+        lams = np.concatenate([lam1.cpu().numpy(), lam2.cpu().numpy()], axis=1)
+        for b, (u_ref, lam_ref, info) in enumerate(ref):
+            assert np.array_equal(us[b].cpu().numpy(), u_ref), b
+            assert np.array_equal(lams[b], lam_ref), b
+            ii = g.image_info(b)
+            assert (ii["M"], ii["N"]) == u_ref.shape
+            assert ii["rho"] == info["rho"] and ii["target"] == info["target"]
+        assert g.info()["iterations"] == 6
+
+
+def test_batch_graph_equals_eager_and_reset():
+    cases = synth.make_batch(5, sizes=SMALL_SIZES, config=7)
+    probs = problems(cases)
+    res = []
+    with gfd.GFDeconvBatch(probs) as g:
+        for use_graph in (True, False):
+            g.set_graph(use_graph)
+            g.reset()
+            us, lam = g.iterate(4)
+            res.append(([u.cpu().numpy() for u in us], lam.cpu().numpy()))
+    for a, b in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res[0][1], res[1][1])
+
+
+def test_batch_set_estimate_uses_concatenated_layout():
+    cases = synth.make_batch(4, sizes=SMALL_SIZES, config=9)
+    probs = problems(cases)
+    rng = np.random.default_rng(5)
+    est = [to_gpu(rng.uniform(0, 255, c.y.shape)) for c in cases]
+    ref = single_runs(probs, [2], estimates=est)
+    with gfd.GFDeconvBatch(probs) as g:
+        g.set_estimate(est)
+        us, lam = g.iterate(2)
+        for b, (u_ref, lam_ref, _) in enumerate(ref):
+            assert np.array_equal(us[b].cpu().numpy(), u_ref), b
+            assert np.array_equal(lam.cpu().numpy()[b], lam_ref), b
+
+
+def test_batch_matches_oracle():
+    cases = synth.make_batch(3, sizes=[(64, 80), (96, 96), (256, 256)], config=11)
+    probs = problems(cases)
+    iters = 4
+    with gfd.GFDeconvBatch(probs) as g:
+        us, lam = g.iterate(iters)
+        us = [u.cpu().numpy() for u in us]
+        lam = lam.cpu().numpy()
+    for b, c in enumerate(cases):
+        eps = float(np.float32(c.eps))
+        ref_u, info = oracle.deconvolve(c.y.astype(np.float64), c.h.astype(np.float32).astype(np.float64), c.sigma2,
+                                        c.w, eps, iters)
+        e = float(np.linalg.norm(us[b] - ref_u) / np.linalg.norm(ref_u))
+        le = max(abs(float(lam[b, k]) - info["lam"][k]) / info["lam"][k] for k in range(iters))
+        print(f"{c.name}: rel L2 {e:.2e}, lambda {le:.2e}")
+        assert e < 1e-5 and le < 1e-4
+
+
+def test_batch_rejects_single_image_calls():
+    cases = synth.make_batch(2, sizes=[(64, 80)], config=13)
+    with gfd.GFDeconvBatch(problems(cases)) as g:
+        lib = gfd.load_library()
+        lam = torch.empty(1, device=DEV)
+        u = torch.zeros(64 * 80, device=DEV)
+        assert lib.discrepancy_lambda(g.handle, u.data_ptr(), lam.data_ptr(), None) == -5
