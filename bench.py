@@ -32,8 +32,8 @@ ALG_BYTES = {
     "guided_filter": (12, 0),   # read u_I, u_p (8P); write u (4P)
 }
 KERNEL_SYMBOL = {
-    "row_fwd": "k_row_fwd", "col_fwd_resid": "k_col_fwd_resid", "lambda_sweeps": "k_lam_sweep",
-    "col_inv_solve": "k_col_inv", "row_inv": "k_row_inv", "guided_filter": "k_guided_filter",
+    "row_fwd": "k_row_fwd_r16", "col_fwd_resid": "k_col_fwd_r16<true>", "lambda_sweeps": "k_lam_sweep",
+    "col_inv_solve": "k_col_inv_r16", "row_inv": "k_row_inv_r16", "guided_filter": "k_gf_g<8>",
 }
 
 
@@ -69,6 +69,66 @@ def cpu_baseline(case, seconds_hint: float = 20.0) -> dict:
                       f"{dt:.1f} s, numpy float64, one thread"}
 
 
+def batch_leg(steps: int, warmup: int, n_images: int = 64) -> dict:
+    """Mixed-size batch: one context (one launch per pass for all images, graph replay) against
+    the one-image-per-launch path (a context per image, kernels launched one by one, images in
+    sequence).  Both run the same kernels on the same inputs."""
+    import numpy as np
+    import torch
+
+    import paper_1609_01839_amd as gfd
+    import synth
+
+    dev = torch.device("cuda:0")
+    cases = synth.make_batch(n_images)
+    probs = [dict(y=torch.from_numpy(c.y).to(dev), h=torch.from_numpy(c.h.astype(np.float32)).to(dev),
+                  sigma2=c.sigma2, w=c.w, eps=c.eps) for c in cases]
+    total_px = sum(c.y.size for c in cases)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, n):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(n):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / n
+
+    with gfd.GFDeconvBatch(probs) as gb:
+        out = torch.empty((gb.total,), device=dev, dtype=torch.float32)
+        lam = torch.empty((gb.count, 1), device=dev, dtype=torch.float32)
+        for _ in range(warmup):
+            gb.iterate(1, out, lam)
+        ms_batch = timed(lambda: gb.iterate(1, out, lam), steps)
+    singles = [gfd.GFDeconv(p["y"], p["h"], p["sigma2"], p["w"], p["eps"]) for p in probs]
+    outs = [torch.empty(p["y"].shape, device=dev, dtype=torch.float32) for p in probs]
+    lam1 = torch.empty((1,), device=dev, dtype=torch.float32)
+    for g in singles:
+        g.set_graph(False)
+
+    def one_pass():
+        for g, o in zip(singles, outs):
+            g.iterate(1, o, lam1)
+
+    for _ in range(max(1, warmup // 2)):
+        one_pass()
+    ms_single = timed(one_pass, max(2, steps // 4))
+    for g in singles:
+        g.close()
+    sizes = sorted({c.y.shape for c in cases})
+    return {"workload": f"{n_images} piecewise-constant synthetic images of sizes drawn from "
+                        f"{', '.join(f'{a}x{b}' for a, b in sizes)}, PSFs 9x9 box / 25x25 Gaussian / 15x15 "
+                        f"1/(1+x^2+y^2), BSNR 20-40 dB, w in {{5, 7, 9}}, one step = one iteration of every image",
+            "images": n_images, "pixels": total_px,
+            "value": round(total_px / (ms_batch * 1e-3) / 1e6, 1), "unit": "Mpixel-iters/s",
+            "ms_per_step": round(ms_batch, 4),
+            "one_image_per_launch": {"value": round(total_px / (ms_single * 1e-3) / 1e6, 1),
+                                     "ms_per_step": round(ms_single, 4)},
+            "speedup_vs_one_image_per_launch": round(ms_single / ms_batch, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +137,7 @@ def main():
     ap.add_argument("--size", type=int, default=4096, help="image side (default: the 4096^2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=10)
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed-size batch leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the deconvolution of one frame runs on a single device "
@@ -147,9 +208,12 @@ def main():
                       "stage_us": {k: round(v * 1e3, 2) for k, v in per_iter.items()},
                       "wall_s": round(wall, 4)},
     }
+    g.close()
+    del y, h, out
+    if not args.no_batch:
+        line["batch"] = batch_leg(max(args.steps // 2, 5), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case)
-    g.close()
     print(json.dumps(line))
 
 

@@ -342,6 +342,7 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
   double *hp = nullptr, *work = nullptr;
   cd *Hd = nullptr, *Yd = nullptr;
   if (e == hipSuccess) e = dalloc(c, &c->st, count);
+  c->main.st_base = c->st;
   if (e == hipSuccess) e = dalloc(c, &c->lam_hist, (size_t)count * c->hist_cap);
   if (e == hipSuccess) e = dalloc(c, &c->flag_hist, (size_t)count * c->hist_cap);
   if (e == hipSuccess) e = dalloc(c, &c->scales, c->hist_cap);
@@ -375,6 +376,7 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
     a.hist_cap = 1;
     a.scales = nullptr;
     c->aux.imgs.push_back(a);
+    c->aux.st_base = c->st_aux;
     e = hipMemcpyAsync(c->st_aux, c->st, sizeof(LamState), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = launch_state_reset(c->st_aux, s);
     if (e == hipSuccess) e = upload_table(c->aux);

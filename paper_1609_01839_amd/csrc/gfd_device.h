@@ -60,10 +60,12 @@ __device__ __forceinline__ void df_add(float &hi, float &lo, float bh, float bl)
 }
 
 // ---------------------------------------------------------------- reductions
-// Compensated sum of NV (hi, lo) pairs over the whole block; result valid in thread 0.
-// `scratch` must hold 2 * NV * (blockDim.x / 64) floats.  Fixed order: deterministic.
+// Compensated sum of NV (hi, lo) pairs over the whole block.  The waves' results are combined
+// by NV threads in parallel (thread v sums value v over the waves in wave order), then thread 0
+// collects them: every thread below NV ends with its value in hi[v], lo[v] and thread 0 with all.
+// `scratch` must hold 2 * NV * max(blockDim.x / 64, 1) floats.  Fixed order: deterministic.
 template <int NV>
-__device__ void block_reduce_df(float (&hi)[NV], float (&lo)[NV], float *scratch) {
+__device__ __forceinline__ void block_reduce_df(float (&hi)[NV], float (&lo)[NV], float *scratch) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -83,12 +85,24 @@ __device__ void block_reduce_df(float (&hi)[NV], float (&lo)[NV], float *scratch
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  const int t = threadIdx.x;
+  float h = 0.0f, l = 0.0f;
+  if (t < NV) {
+    h = scratch[t * 2];
+    l = scratch[t * 2 + 1];
+    for (int w = 1; w < nw; ++w) df_add(h, l, scratch[(w * NV + t) * 2], scratch[(w * NV + t) * 2 + 1]);
+  }
+  __syncthreads();
+  if (t < NV) {
+    scratch[t * 2] = h;
+    scratch[t * 2 + 1] = l;
+  }
+  __syncthreads();
+  if (t == 0) {
+#pragma unroll
     for (int v = 0; v < NV; ++v) {
-      float h = scratch[v * 2], l = scratch[v * 2 + 1];
-      for (int w = 1; w < nw; ++w) df_add(h, l, scratch[(w * NV + v) * 2], scratch[(w * NV + v) * 2 + 1]);
-      hi[v] = h;
-      lo[v] = l;
+      hi[v] = scratch[v * 2];
+      lo[v] = scratch[v * 2 + 1];
     }
   }
   __syncthreads();

@@ -83,6 +83,7 @@ struct Plan {
 // `imgs`; work lists are appended to items_host and uploaded once by finalize_items().
 struct ImgSet {
   std::vector<Img> imgs;
+  LamState *st_base = nullptr;  // states of the images, imgs[i].st == st_base + i
   Img *dev = nullptr;
   std::vector<Item> items_host;
   Item *items_dev = nullptr;

@@ -210,9 +210,17 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, 
     LamState *st = d.st;
     const float cI = st->meanI, cP = st->meanP;
     if (close_iteration && wi.blk == 0 && threadIdx.x == 0) {
+      LamState s;
+      s.lam_prev = st->lam_prev;
+      s.lam_prev2 = st->lam_prev2;
+      lam_first_candidates(s);
+      for (int j = 0; j < kLamFirstCand; ++j) {
+        st->cand[j] = s.cand[j];
+        st->mu[j] = s.mu[j];
+      }
+      st->nc = s.nc;
       st->k += 1;
       st->phase = 0;
-      lam_first_candidates(*st);
     }
     gf_strip<R>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, ringAB, vbuf, hbuf);
     __syncthreads();

@@ -21,9 +21,10 @@ namespace gfd {
 
 // ============================================================================ reductions
 
-// Plain FP32 butterfly over the wave, then compensated across waves; thread 0 gets the sum.
+// Plain FP32 butterfly over the wave, then compensated across the waves in wave order by NV
+// threads in parallel: thread v (< NV) ends with value v in (h, l).
 template <int NV>
-__device__ __forceinline__ void block_sum_plain_then_df(float (&acc)[NV], float (&hi)[NV], float (&lo)[NV], float *scratch) {
+__device__ __forceinline__ void block_sum_plain_then_df(float (&acc)[NV], float &h, float &l, float *scratch) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
@@ -36,23 +37,20 @@ __device__ __forceinline__ void block_sum_plain_then_df(float (&acc)[NV], float 
     for (int v = 0; v < NV; ++v) scratch[wid * NV + v] = acc[v];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int v = 0; v < NV; ++v) {
-      float h = 0.0f, l = 0.0f;
-      for (int w = 0; w < nw; ++w) df_add(h, l, scratch[w * NV + v], 0.0f);
-      hi[v] = h;
-      lo[v] = l;
-    }
+  h = 0.0f;
+  l = 0.0f;
+  if ((int)threadIdx.x < NV) {
+    for (int w = 0; w < nw; ++w) df_add(h, l, scratch[w * NV + threadIdx.x], 0.0f);
   }
-  __syncthreads();
 }
 
-// Partial sums are stored structure-of-arrays, part[(2 a + {0: hi, 1: lo}) * npart + block].
-__device__ __forceinline__ void store_partials(GFD_AS1 float *part, int npart, int blk, int nv, const float *hi,
-                                               const float *lo) {
-  for (int a = 0; a < nv; ++a) {
-    part[(size_t)(2 * a) * npart + blk] = hi[a];
-    part[(size_t)(2 * a + 1) * npart + blk] = lo[a];
+// Partial sums are stored structure-of-arrays, part[(2 a + {0: hi, 1: lo}) * npart + block];
+// thread a (< nv) stores value a.
+__device__ __forceinline__ void store_partial(GFD_AS1 float *part, int npart, int blk, int nv, float h, float l) {
+  const int a = threadIdx.x;
+  if (a < nv) {
+    part[(size_t)(2 * a) * npart + blk] = h;
+    part[(size_t)(2 * a + 1) * npart + blk] = l;
   }
 }
 
@@ -71,24 +69,24 @@ __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict_
   block_reduce_df<NV>(hi, lo, scratch);
 }
 
-// Commit the lambda of this iteration (one thread, once the search is finished).
-__device__ void lam_commit(const Img &d) {
-  LamState *st = d.st;
-  const float ls = st->lam_star;
+// Commit the lambda of this iteration (one thread, once the search is finished).  The search
+// state is a private copy `st` that the caller writes back.
+__device__ __forceinline__ void lam_commit(const Img &d, LamState &st) {
+  const float ls = st.lam_star;
   float lam = ls;
   if (!isinf(ls)) {
-    const float sc = (d.scales != nullptr && st->k < st->nscale) ? d.scales[st->k] : 1.0f;
+    const float sc = (d.scales != nullptr && st.k < st.nscale) ? d.scales[st.k] : 1.0f;
     lam = sc * ls;
-    if (!(st->flags & kFlagNoRoot)) {
-      st->lam_prev2 = st->lam_prev;
-      st->lam_prev = ls;
+    if (!(st.flags & kFlagNoRoot)) {
+      st.lam_prev2 = st.lam_prev;
+      st.lam_prev = ls;
     }
   }
-  st->lam = lam;
-  st->flags_all |= (unsigned)st->flags;
-  if (d.lam_hist != nullptr && st->k < d.hist_cap) {
-    d.lam_hist[st->k] = lam;
-    d.flag_hist[st->k] = st->flags;
+  st.lam = lam;
+  st.flags_all |= (unsigned)st.flags;
+  if (d.lam_hist != nullptr && st.k < d.hist_cap) {
+    d.lam_hist[st.k] = lam;
+    d.flag_hist[st.k] = st.flags;
   }
 }
 
@@ -253,9 +251,9 @@ __global__ void __launch_bounds__(1024) k_col_fwd_g(const Img *__restrict__ D, c
       G(d.q)[off + e] = qq;
       first_round_terms<NC>(qq, t2, mu, acc);
     }
-    float hi[2 + 2 * NC], lo[2 + 2 * NC];
-    block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
-    if (threadIdx.x == 0) store_partials(G(d.part), d.npart, wi.blk, 2 + 2 * NC, hi, lo);
+    float h, l;
+    block_sum_plain_then_df<2 + 2 * NC>(acc, h, l, scratch);
+    store_partial(G(d.part), d.npart, wi.blk, 2 + 2 * NC, h, l);
   }
   GFD_ITEM_END
 }
@@ -447,9 +445,9 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
         first_round_terms<NC>(qq, t2, mu, acc);
       }
     }
-    float hi[2 + 2 * NC], lo[2 + 2 * NC];
-    block_sum_plain_then_df<2 + 2 * NC>(acc, hi, lo, scratch);
-    if (threadIdx.x == 0) store_partials(G(d.part), d.npart, wi.blk, 2 + 2 * NC, hi, lo);
+    float h, l;
+    block_sum_plain_then_df<2 + 2 * NC>(acc, h, l, scratch);
+    store_partial(G(d.part), d.npart, wi.blk, 2 + 2 * NC, h, l);
   }
   GFD_ITEM_END
 }
@@ -539,33 +537,43 @@ __global__ void __launch_bounds__(512) k_row_inv_r16(const Img *__restrict__ D, 
 }
 
 // ============================================================================ lambda search kernels
+// The search kernels work on a private copy of the image's state (one thread) and write it
+// back, so that the serial search code does not wait on memory at every field access.
+// `stv` is the array of the states of the set's images (index = image), read first so that an
+// image whose lambda is already fixed skips the round after one load.
+
 // After the residual pass: one block per image finishes the first round.
-__global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
+__global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
+                                                    LamState *__restrict__ stv) {
   __shared__ float scratch[2 * kLamAcc * 16];
   GFD_ITEM_LOOP
   constexpr int NC = kLamFirstCand;
   float hi[2 + 2 * NC], lo[2 + 2 * NC];
   reduce_partials<2 + 2 * NC>(G(d.part), d.npart, d.L.NT, hi, lo, scratch);
   if (threadIdx.x == 0) {
-    LamState *st = d.st;
-    st->phase = 0;
-    st->flags = 0;
+    LamState st = stv[wi.img];
+    st.phase = 0;
+    st.flags = 0;
     float cand[NC];
-    for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
-    if (lam_begin(*st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(d);
+    for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
+    if (lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(d, st);
+    stv[wi.img] = st;
   }
   GFD_ITEM_END
 }
 
 // One evaluation round: per-chunk sums of q g_j and q g_j (1 - r_j) over the bins.
-__global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, const Item *__restrict__ W, int nitems) {
+__global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
+                                                   const LamState *__restrict__ stv) {
   __shared__ float scratch[kLamAcc * 4];
   constexpr int NC = kLamMaxCand;
-  GFD_ITEM_LOOP
-  if (d.st->phase == 0) {
+  for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
+    const Item wi = W[ii];
+    if (wi.blk < 0 || stv[wi.img].phase != 0) continue;
+    const Img &d = D[wi.img];
     float mu[NC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) mu[j] = d.st->mu[j];
+    for (int j = 0; j < NC; ++j) mu[j] = stv[wi.img].mu[j];
     float acc[2 * NC];
 #pragma unroll
     for (int v = 0; v < 2 * NC; ++v) acc[v] = 0.0f;
@@ -597,31 +605,34 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
         }
       }
     }
-    float hi[2 * NC], lo[2 * NC];
-    block_sum_plain_then_df<2 * NC>(acc, hi, lo, scratch);
-    if (threadIdx.x == 0) store_partials(G(d.part), d.npart, wi.blk, 2 * NC, hi, lo);
+    float h, l;
+    block_sum_plain_then_df<2 * NC>(acc, h, l, scratch);
+    store_partial(G(d.part), d.npart, wi.blk, 2 * NC, h, l);
+    __syncthreads();
   }
-  GFD_ITEM_END
 }
 
 // One block per image folds a round into the bracket and picks the next candidates.
 __global__ void __launch_bounds__(1024) k_lam_round(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                    int last) {
+                                                    LamState *__restrict__ stv, int last) {
   __shared__ float scratch[2 * kLamAcc * 16];
   constexpr int NC = kLamMaxCand;
-  GFD_ITEM_LOOP
-  if (d.st->phase == 0) {
+  for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
+    const Item wi = W[ii];
+    if (wi.blk < 0 || stv[wi.img].phase != 0) continue;
+    const Img &d = D[wi.img];
     float hi[2 * NC], lo[2 * NC];
     reduce_partials<2 * NC>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
     if (threadIdx.x == 0) {
-      LamState *st = d.st;
+      LamState st = stv[wi.img];
       float cand[NC];
-      for (int j = 0; j < NC; ++j) cand[j] = st->cand[j];
-      lam_absorb(*st, NC, cand, hi, lo, hi + NC);
-      if (lam_decide(*st, last != 0)) lam_commit(d);
+      for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
+      lam_absorb(st, NC, cand, hi, lo, hi + NC);
+      if (lam_decide(st, last != 0)) lam_commit(d, st);
+      stv[wi.img] = st;
     }
+    __syncthreads();
   }
-  GFD_ITEM_END
 }
 
 // ============================================================================ set-up kernels (one image)
@@ -1006,11 +1017,11 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
 
 void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds) {
   ItemRange one = add_items(set, sel, [](const Img &) { return 1; });
-  p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0));
+  p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0, set.st_base));
   ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
   for (int k = 0; k < rounds; ++k) {
-    p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0));
-    p.steps.push_back(make_launch(&set, k_lam_round, one, 1024, 0, (int)(k == rounds - 1)));
+    p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0, (const LamState *)set.st_base));
+    p.steps.push_back(make_launch(&set, k_lam_round, one, 1024, 0, set.st_base, (int)(k == rounds - 1)));
   }
 }
 
