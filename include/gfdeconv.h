@@ -170,6 +170,28 @@ gfd_status deconv_set_graph(gfd_ctx *ctx, int use_graph);
  */
 gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_stages, void *stream);
 
+/*
+ * deconv_backward -- reverse mode of the iterations run since the estimate was last set
+ * (deconv_init, deconv_reset or deconv_set_estimate): given g_u = dLoss/du for the current
+ * estimate u^K, the gradient of the loss with respect to the guided-filter regulariser eps
+ * (Sec. 2, Eqs.(3)-(5); one eps for all iterations) and to the per-iteration lambda scales s_k
+ * (lambda_k = s_k lambda*_k, deconv_set_scales), differentiating through the guided filter, the
+ * two solves (Eqs.(8)-(9)), the transforms and, implicitly, through lambda* defined by the
+ * discrepancy equation (Sec. 3.2, Eq.(11)).  An iteration that took lambda = +inf passes the
+ * gradient through the identity solves and has zero scale gradient.
+ *   grad_u           device: the images' g_u, one after another (M x N each).
+ *   grad_eps_dev     device, one float per image, or NULL.
+ *   grad_scales_dev  device, count x K floats (image-major), or NULL.
+ *   checkpoint_every the forward iterations are replayed from their logged lambdas; every
+ *                    c-th pre-estimate is kept and each segment of c iterations is recomputed
+ *                    before it is differentiated (0 selects c = 5).  Memory: about
+ *                    (K / c + c + 16) images per image.  The result does not depend on c.
+ * Stream-ordered; allocates device memory on first use.  The context's own estimate, search
+ * state and histories are left unchanged.
+ */
+gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_dev, float *grad_scales_dev,
+                           int checkpoint_every, void *stream);
+
 /* deconv_destroy -- frees the context; NULL and already-destroyed contexts are ignored. */
 void deconv_destroy(gfd_ctx *ctx);
 

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "deconvolve", "guided_filter", "spectral_solve", "discrepancy_lambda",
+__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "spectral_solve", "discrepancy_lambda",
            "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -44,6 +44,7 @@ EXPORTS = {
     "deconv_get_status": (_i, [_vp, ctypes.POINTER(ctypes.c_uint)]),
     "deconv_set_graph": (_i, [_vp, _i]),
     "deconv_profile": (_i, [_vp, _i, ctypes.POINTER(_f), _i, _vp]),
+    "deconv_backward": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "deconv_destroy": (None, [_vp]),
     "gfd_last_error": (ctypes.c_char_p, []),
 }
@@ -161,9 +162,11 @@ class GFDeconv:
 
     def set_estimate(self, uE: torch.Tensor):
         _check(load_library().deconv_set_estimate(self.handle, _dev(uE, "uE", (self.M, self.N)), _stream(self.device)))
+        self._k_start = self.info()["iterations"]
 
     def reset(self):
         _check(load_library().deconv_reset(self.handle, _stream(self.device)))
+        self._k_start = 0
 
     def set_graph(self, use_graph: bool):
         _check(load_library().deconv_set_graph(self.handle, 1 if use_graph else 0))
@@ -185,6 +188,24 @@ class GFDeconv:
         ms = (ctypes.c_float * 6)()
         _check(load_library().deconv_profile(self.handle, int(n), ms, 6, _stream(self.device)))
         return dict(zip(self.STAGES, list(ms)))
+
+    def backward(self, grad_u: torch.Tensor, checkpoint_every: int = 5):
+        """Gradient of a loss with respect to eps and to the lambda scales of the iterations run
+        since the estimate was last set, given ``grad_u`` = dLoss/du for the current estimate.
+        Returns (g_eps, g_scales) as GPU tensors of shapes (count,) and (count, K)."""
+        info = self.info()
+        K = info["iterations"] - getattr(self, "_k_start", 0)
+        count = getattr(self, "count", 1)
+        total = getattr(self, "total", self.M * self.N)
+        g = grad_u.reshape(-1).contiguous()
+        if g.numel() != total:
+            raise ValueError(f"grad_u must hold {total} values")
+        g_eps = torch.empty((count,), device=self.device, dtype=torch.float32)
+        g_s = torch.empty((count, max(K, 0)), device=self.device, dtype=torch.float32)
+        _check(load_library().deconv_backward(self.handle, _dev(g, "grad_u"), g_eps.data_ptr(),
+                                              g_s.data_ptr() if K > 0 else None, int(checkpoint_every),
+                                              _stream(self.device)))
+        return g_eps, g_s
 
     def spectral_solve(self, uE: torch.Tensor, lam: float):
         return spectral_solve(self, uE, lam)
@@ -249,6 +270,7 @@ class GFDeconvBatch(GFDeconv):
         _check(load_library().deconv_set_estimate(self.handle, _dev(flat, "estimates", (self.total,)),
                                                   _stream(self.device)))
         torch.cuda.current_stream(self.device).synchronize()
+        self._k_start = self.info()["iterations"]
 
     def image_info(self, b: int):
         M, N, rho, T = _i(), _i(), _d(), _d()
@@ -261,6 +283,45 @@ class GFDeconvBatch(GFDeconv):
 
     def discrepancy_lambda(self, uE):
         raise GFDError(-5, "discrepancy_lambda needs a single-image context")
+
+
+class GFDeconvFn(torch.autograd.Function):
+    """u^K of ``iters`` iterations from u_E = 0, differentiable with respect to eps (a 0-d
+    tensor) and the per-iteration lambda scales (a tensor of ``iters`` values) through the
+    library's hand-written adjoint (deconv_backward); y, h and the other arguments are
+    constants."""
+
+    @staticmethod
+    def forward(ctx, eps, scales, y, h, sigma2, w, iters, rho, checkpoint_every):
+        g = GFDeconv(y, h, sigma2, w, float(eps), rho)
+        try:
+            g.set_scales(scales.detach().float())
+            u, _ = g.iterate(int(iters))
+        except Exception:
+            g.close()
+            raise
+        ctx.g = g
+        ctx.checkpoint_every = int(checkpoint_every)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        g = ctx.g
+        try:
+            g_eps, g_s = g.backward(grad_u.float(), ctx.checkpoint_every)
+        finally:
+            g.close()
+            ctx.g = None
+        return g_eps[0], g_s[0], None, None, None, None, None, None, None
+
+
+def deconvolve_autograd(y, h, sigma2, w, eps, iters, scales=None, rho=None, checkpoint_every=5):
+    """Differentiable deconvolution: returns u^K; gradients flow to ``eps`` and ``scales`` when
+    they are tensors that require them."""
+    dev = y.device
+    eps_t = eps if isinstance(eps, torch.Tensor) else torch.tensor(float(eps), device=dev)
+    s = scales if scales is not None else torch.ones(int(iters), device=dev)
+    return GFDeconvFn.apply(eps_t, s, y, h, float(sigma2), int(w), int(iters), rho, int(checkpoint_every))
 
 
 def deconvolve(y, h, sigma2, w, eps, iters, rho=None, scales=None):

@@ -47,15 +47,47 @@ struct gfd_ctx {
   LamState *st_aux = nullptr;
   float *lam_hist = nullptr;   // count x hist_cap
   int *flag_hist = nullptr;
+  float *lam_star_hist = nullptr;  // count x hist_cap
+  std::vector<float *> u0;     // per image: the estimate the iterations started from
   float *scales = nullptr;     // hist_cap, shared by all images
   float *uE_aux = nullptr;
   double *rho_out = nullptr;   // 2 per image
   int hist_cap = 0;
   int iters = 0;
+  int k_start = 0;  // first iteration since the estimate was last set (what the backward differentiates)
   int use_graph = 1;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
+  struct Bwd *bwd = nullptr;   // reverse-mode buffers and plans, built on first use
 };
+
+// Reverse mode: descriptor sets over the same images.
+//   bwd:  replays iterations (its own estimate uR and search state) and runs the adjoint
+//   grad: two entries per image, the transforms of g_I and g_p
+//   gout: the inverse transform of the adjoint spectrum into the gradient buffer
+struct Bwd {
+  ImgSet bwd, grad, gout;
+  Plan fwd_a, fwd_b, gf, box[3], grad_fft, spec, col, gout_inv, inf;
+  ItemRange one{0, 0};
+  LamState *st = nullptr;
+  AdjState *ad = nullptr;
+  std::vector<float *> uR, gu;
+  std::vector<std::vector<float *>> ck;  // per image, checkpoint slots
+  std::vector<std::vector<float *>> seg; // per image, pre-estimates of one segment
+  std::vector<void *> allocs;
+  int hist_cap = 0;
+};
+
+static void free_bwd(Bwd *b) {
+  if (!b) return;
+  for (void *p : b->allocs)
+    if (p) (void)hipFree(p);
+  for (ImgSet *s : {&b->bwd, &b->grad, &b->gout}) {
+    if (s->dev) (void)hipFree(s->dev);
+    if (s->items_dev) (void)hipFree(s->items_dev);
+  }
+  delete b;
+}
 
 static thread_local std::string g_err;
 static std::mutex g_live_mu;
@@ -90,6 +122,8 @@ static bool live(gfd_ctx *c) {
 }
 
 static void free_ctx(gfd_ctx *c) {
+  free_bwd(c->bwd);
+  c->bwd = nullptr;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void *p : c->allocs)
@@ -244,6 +278,8 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   ALLOC(SI, nb);
   ALLOC(SP, nb);
   ALLOC(part, (size_t)2 * kLamAcc * d.npart);
+  float *u0 = nullptr;
+  ALLOC(u0, P);
   ALLOC(twMd, M);
   ALLOC(twNd, N);
 #undef ALLOC
@@ -267,6 +303,7 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   d.st = c->st + i;
   d.lam_hist = c->lam_hist + (size_t)i * c->hist_cap;
   d.flag_hist = c->flag_hist + (size_t)i * c->hist_cap;
+  d.lam_star_hist = c->lam_star_hist + (size_t)i * c->hist_cap;
   d.scales = c->scales;
   d.hist_cap = c->hist_cap;
   gf_geometry(d);
@@ -288,6 +325,8 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
     e = launch_rho_target(src.y, M, N, src.h, src.kh, src.kw, src.sigma2, src.rho, work, c->rho_out + 2 * i, d.st, s);
   if (e == hipSuccess) e = launch_state_reset(d.st, s);
   if (e == hipSuccess) e = launch_fill_f(uE, P, 0.0f, s);
+  if (e == hipSuccess) e = launch_fill_f(u0, P, 0.0f, s);
+  c->u0.push_back(u0);
   // the FP64 temporaries are shared by the images: finish before the next image reuses them
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   c->main.imgs.push_back(d);
@@ -345,6 +384,7 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
   c->main.st_base = c->st;
   if (e == hipSuccess) e = dalloc(c, &c->lam_hist, (size_t)count * c->hist_cap);
   if (e == hipSuccess) e = dalloc(c, &c->flag_hist, (size_t)count * c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->lam_star_hist, (size_t)count * c->hist_cap);
   if (e == hipSuccess) e = dalloc(c, &c->scales, c->hist_cap);
   if (e == hipSuccess) e = dalloc(c, &c->rho_out, 2 * (size_t)count);
   if (e == hipSuccess) e = dalloc(c, &hp, maxP);
@@ -373,6 +413,7 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
     a.st = c->st_aux;
     a.lam_hist = lh;
     a.flag_hist = fh;
+    a.lam_star_hist = nullptr;
     a.hist_cap = 1;
     a.scales = nullptr;
     c->aux.imgs.push_back(a);
@@ -401,45 +442,52 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
 }
 
 // Larger per-iteration histories; the descriptors are rewritten in place, so a captured
-// graph (which reads them at run time) stays valid.
+// graph (which reads them at run time) stays valid.  The reverse-mode sets copy these
+// pointers and are rebuilt on their next use.
 static gfd_status grow_history(gfd_ctx *c, int need) {
   if (need <= c->hist_cap) return GFD_OK;
   int cap = c->hist_cap;
   while (cap < need) cap *= 2;
-  float *lh = nullptr, *sc = nullptr;
+  float *lh = nullptr, *lsh = nullptr, *sc = nullptr;
   int *fh = nullptr;
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipMalloc((void **)&lh, (size_t)c->count * cap * sizeof(float)));
+  HIPCHK(hipMalloc((void **)&lsh, (size_t)c->count * cap * sizeof(float)));
   HIPCHK(hipMalloc((void **)&fh, (size_t)c->count * cap * sizeof(int)));
   HIPCHK(hipMalloc((void **)&sc, cap * sizeof(float)));
   HIPCHK(launch_fill_f(sc, cap, 1.0f, nullptr));
   for (int i = 0; i < c->count; ++i) {
-    HIPCHK(hipMemcpy(lh + (size_t)i * cap, c->lam_hist + (size_t)i * c->hist_cap, c->hist_cap * sizeof(float),
-                     hipMemcpyDeviceToDevice));
-    HIPCHK(hipMemcpy(fh + (size_t)i * cap, c->flag_hist + (size_t)i * c->hist_cap, c->hist_cap * sizeof(int),
-                     hipMemcpyDeviceToDevice));
+    const size_t o = (size_t)i * cap, oo = (size_t)i * c->hist_cap;
+    HIPCHK(hipMemcpy(lh + o, c->lam_hist + oo, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(lsh + o, c->lam_star_hist + oo, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(fh + o, c->flag_hist + oo, c->hist_cap * sizeof(int), hipMemcpyDeviceToDevice));
   }
   HIPCHK(hipMemcpy(sc, c->scales, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
   HIPCHK(hipDeviceSynchronize());
-  for (void *old : {(void *)c->lam_hist, (void *)c->flag_hist, (void *)c->scales}) {
+  for (void *old : {(void *)c->lam_hist, (void *)c->lam_star_hist, (void *)c->flag_hist, (void *)c->scales}) {
     c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), old));
     (void)hipFree(old);
   }
   c->allocs.push_back(lh);
+  c->allocs.push_back(lsh);
   c->allocs.push_back(fh);
   c->allocs.push_back(sc);
   c->lam_hist = lh;
+  c->lam_star_hist = lsh;
   c->flag_hist = fh;
   c->scales = sc;
   c->hist_cap = cap;
   for (int i = 0; i < c->count; ++i) {
     Img &d = c->main.imgs[i];
     d.lam_hist = lh + (size_t)i * cap;
+    d.lam_star_hist = lsh + (size_t)i * cap;
     d.flag_hist = fh + (size_t)i * cap;
     d.scales = sc;
     d.hist_cap = cap;
   }
   HIPCHK(upload_table(c->main));
+  free_bwd(c->bwd);
+  c->bwd = nullptr;
   return GFD_OK;
 }
 
@@ -451,6 +499,178 @@ static gfd_status copy_estimates_out(gfd_ctx *c, float *u_out, hipStream_t s) {
     off += P;
   }
   return GFD_OK;
+}
+
+// ---------------------------------------------------------------- reverse mode
+template <class T>
+static hipError_t balloc(Bwd *b, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e == hipSuccess) b->allocs.push_back((void *)*p);
+  return e;
+}
+
+// Buffers, descriptor sets and launch plans of the reverse mode.
+static hipError_t build_bwd(gfd_ctx *c) {
+  Bwd *b = new Bwd;
+  c->bwd = b;
+  b->hist_cap = c->hist_cap;
+  const int n = c->count;
+  hipError_t e = balloc(b, &b->st, n);
+  if (e == hipSuccess) e = balloc(b, &b->ad, n);
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    const Img &m = c->main.imgs[i];
+    const size_t P = (size_t)m.L.M * m.L.N, nb = m.L.bins();
+    Img d = m;
+    float *uR, *ga, *gmu, *gpb, *gve, *gc, *gd, *gu, *gI, *gP, *gpart, *geh, *gsh;
+    cf *SgI, *SgP, *Gs, *Gz;
+#define BALLOC(ptr, cnt) \
+  if (e == hipSuccess) e = balloc(b, &(ptr), (cnt))
+    BALLOC(uR, P);
+    BALLOC(ga, P);
+    BALLOC(gmu, P);
+    BALLOC(gpb, P);
+    BALLOC(gve, P);
+    BALLOC(gc, P);
+    BALLOC(gd, P);
+    BALLOC(gu, P);
+    BALLOC(gI, P);
+    BALLOC(gP, P);
+    BALLOC(SgI, nb);
+    BALLOC(SgP, nb);
+    BALLOC(Gs, nb);
+    BALLOC(Gz, nb);
+    BALLOC(geh, c->hist_cap);
+    BALLOC(gsh, c->hist_cap);
+#undef BALLOC
+    if (e != hipSuccess) break;
+    adj_geometry(d);
+    e = balloc(b, &gpart, (size_t)adj_strips(d));
+    if (e != hipSuccess) break;
+    e = hipMemset(Gz, 0, nb * sizeof(cf));
+    d.uE = uR;
+    d.st = b->st + i;
+    d.ga = ga;
+    d.gmu = gmu;
+    d.gpb = gpb;
+    d.gve = gve;
+    d.gc = gc;
+    d.gd = gd;
+    d.gu = gu;
+    d.gI = gI;
+    d.gP = gP;
+    d.geps_part = gpart;
+    d.SgI = SgI;
+    d.SgP = SgP;
+    d.G = Gs;
+    d.ad = b->ad + i;
+    d.geps_hist = geh;
+    d.gs_hist = gsh;
+    b->bwd.imgs.push_back(d);
+    Img gi = d, gp = d;  // transforms of g_I and g_p
+    gi.uE = gI;
+    gi.S1 = SgI;
+    gp.uE = gP;
+    gp.S1 = SgP;
+    b->grad.imgs.push_back(gi);
+    b->grad.imgs.push_back(gp);
+    Img go = d;          // inverse transform of the adjoint spectrum into the gradient
+    go.SI = Gs;
+    go.SP = Gz;
+    go.uI = gu;
+    go.uP = m.uP;
+    b->gout.imgs.push_back(go);
+    b->uR.push_back(uR);
+    b->gu.push_back(gu);
+  }
+  if (e != hipSuccess) return e;
+  b->bwd.st_base = b->st;
+  b->grad.st_base = b->st;
+  b->gout.st_base = b->st;
+  std::vector<int> all(n), all2(2 * n);
+  for (int i = 0; i < n; ++i) all[i] = i;
+  for (int i = 0; i < 2 * n; ++i) all2[i] = i;
+  plan_row_fwd(b->fwd_a, b->bwd, all);
+  plan_col_fwd(b->fwd_a, b->bwd, all, false);
+  plan_col_inv(b->fwd_b, b->bwd, all);
+  plan_row_inv(b->fwd_b, b->bwd, all);
+  plan_guided_filter(b->gf, b->bwd, all, false);
+  for (int st = 0; st < 3; ++st) plan_box_stage(b->box[st], b->bwd, all, st + 1);
+  plan_adj_spec(b->spec, b->bwd, all);
+  plan_adj_col(b->col, b->bwd, all);
+  plan_adj_inf(b->inf, b->bwd, all);
+  b->one = plan_one_per_image(b->bwd, all);
+  plan_row_fwd(b->grad_fft, b->grad, all2);
+  plan_col_fwd(b->grad_fft, b->grad, all2, false);
+  plan_row_inv(b->gout_inv, b->gout, all);
+  for (ImgSet *set : {&b->bwd, &b->grad, &b->gout}) {
+    if (e == hipSuccess) e = upload_table(*set);
+    if (e == hipSuccess) e = finalize_items(*set);
+  }
+  return e;
+}
+
+// Slots for checkpoints and for the pre-estimates of one segment.
+static hipError_t bwd_slots(gfd_ctx *c, int nck, int seg) {
+  Bwd *b = c->bwd;
+  b->ck.resize(c->count);
+  b->seg.resize(c->count);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < c->count && e == hipSuccess; ++i) {
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+    while ((int)b->ck[i].size() < nck && e == hipSuccess) {
+      float *p = nullptr;
+      e = balloc(b, &p, P);
+      b->ck[i].push_back(p);
+    }
+    while ((int)b->seg[i].size() < seg && e == hipSuccess) {
+      float *p = nullptr;
+      e = balloc(b, &p, P);
+      b->seg[i].push_back(p);
+    }
+  }
+  return e;
+}
+
+static hipError_t copy_images(gfd_ctx *c, const std::vector<float *> &dst, const std::vector<float *> &src,
+                              hipStream_t s) {
+  for (int i = 0; i < c->count; ++i) {
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+    hipError_t e = hipMemcpyAsync(dst[i], src[i], P * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static std::vector<float *> slot(const std::vector<std::vector<float *>> &v, int j) {
+  std::vector<float *> r;
+  for (const auto &x : v) r.push_back(x[j]);
+  return r;
+}
+
+// Iteration k of the forward run again, with its logged lambda: u_I, u_p (and U_E in S1);
+// with `filter` also the next pre-estimate, in place in uR.
+static hipError_t replay(Bwd *b, int k, bool filter, hipStream_t s) {
+  hipError_t e = b->fwd_a.enqueue(s);
+  if (e == hipSuccess) e = launch_lam_replay(b->bwd, b->one, k, s);
+  if (e == hipSuccess) e = b->fwd_b.enqueue(s);
+  if (e == hipSuccess && filter) e = b->gf.enqueue(s);
+  return e;
+}
+
+// Adjoint of iteration k; gu holds the gradient with respect to its output on entry and
+// with respect to its pre-estimate on exit.
+static hipError_t adjoint_step(Bwd *b, int k, hipStream_t s) {
+  hipError_t e = replay(b, k, false, s);
+  for (int st = 0; st < 3 && e == hipSuccess; ++st) e = b->box[st].enqueue(s);
+  if (e == hipSuccess) e = b->grad_fft.enqueue(s);
+  if (e == hipSuccess) e = b->spec.enqueue(s);
+  if (e == hipSuccess) e = launch_adj_fin(b->bwd, b->one, k, s);
+  if (e == hipSuccess) e = b->col.enqueue(s);
+  if (e == hipSuccess) e = b->gout_inv.enqueue(s);
+  if (e == hipSuccess) e = b->inf.enqueue(s);
+  return e;
 }
 
 extern "C" {
@@ -611,9 +831,11 @@ gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream) {
   for (int i = 0; i < ctx->count; ++i) {
     const size_t P = (size_t)ctx->meta[i].M * ctx->meta[i].N;
     HIPCHK(hipMemcpyAsync(ctx->main.imgs[i].uE, uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->u0[i], uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
     off += P;
   }
   HIPCHK(ctx->warm.enqueue(s));
+  ctx->k_start = ctx->iters;
   return GFD_OK;
 }
 
@@ -623,10 +845,12 @@ gfd_status deconv_reset(gfd_ctx *ctx, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   for (int i = 0; i < ctx->count; ++i) {
     HIPCHK(launch_fill_f(ctx->main.imgs[i].uE, (size_t)ctx->meta[i].M * ctx->meta[i].N, 0.0f, s));
+    HIPCHK(launch_fill_f(ctx->u0[i], (size_t)ctx->meta[i].M * ctx->meta[i].N, 0.0f, s));
     HIPCHK(launch_state_reset(ctx->st + i, s));
   }
   HIPCHK(ctx->warm.enqueue(s));
   ctx->iters = 0;
+  ctx->k_start = 0;
   return GFD_OK;
 }
 
@@ -671,6 +895,69 @@ gfd_status deconv_set_graph(gfd_ctx *ctx, int use_graph) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   ctx->use_graph = use_graph ? 1 : 0;
+  return GFD_OK;
+}
+
+gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_dev, float *grad_scales_dev,
+                           int checkpoint_every, void *stream) {
+  g_err.clear();
+  if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (!grad_u) return fail(GFD_ERR_ARG, "grad_u must be a device pointer");
+  if (checkpoint_every < 0) return fail(GFD_ERR_ARG, "checkpoint_every must be >= 0 (0: default 5)");
+  hipStream_t s = (hipStream_t)stream;
+  const int K = ctx->iters - ctx->k_start, k0 = ctx->k_start;
+  const int c = checkpoint_every == 0 ? 5 : checkpoint_every;
+  if (ctx->bwd && ctx->bwd->hist_cap != ctx->hist_cap) {
+    HIPCHK(hipDeviceSynchronize());
+    free_bwd(ctx->bwd);
+    ctx->bwd = nullptr;
+  }
+  if (!ctx->bwd) {
+    hipError_t e = build_bwd(ctx);
+    if (e != hipSuccess) {
+      free_bwd(ctx->bwd);
+      ctx->bwd = nullptr;
+      return fail(e == hipErrorOutOfMemory ? GFD_ERR_NOMEM : GFD_ERR_HIP, "reverse-mode set-up failed: %s",
+                  hipGetErrorString(e));
+    }
+  }
+  Bwd *b = ctx->bwd;
+  const int nck = K > 0 ? (K + c - 1) / c : 0;
+  {
+    hipError_t e = bwd_slots(ctx, nck, std::min(c, std::max(K, 1)));
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? GFD_ERR_NOMEM : GFD_ERR_HIP, "checkpoint allocation failed: %s",
+                  hipGetErrorString(e));
+  }
+  // incoming gradient (images one after another) and a private copy of the search constants
+  size_t off = 0;
+  for (int i = 0; i < ctx->count; ++i) {
+    const size_t P = (size_t)ctx->meta[i].M * ctx->meta[i].N;
+    HIPCHK(hipMemcpyAsync(b->gu[i], grad_u + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    off += P;
+  }
+  HIPCHK(hipMemcpyAsync(b->st, ctx->st, ctx->count * sizeof(LamState), hipMemcpyDeviceToDevice, s));
+  // forward replay from the starting estimate, keeping every c-th pre-estimate
+  HIPCHK(copy_images(ctx, b->uR, ctx->u0, s));
+  for (int k = 0; k < (nck - 1) * c; ++k) {
+    if (k % c == 0) HIPCHK(copy_images(ctx, slot(b->ck, k / c), b->uR, s));
+    HIPCHK(replay(b, k0 + k, true, s));
+  }
+  if (nck > 0) HIPCHK(copy_images(ctx, slot(b->ck, nck - 1), b->uR, s));
+  // segments in reverse: recompute the segment's pre-estimates, then differentiate it
+  for (int j = nck - 1; j >= 0; --j) {
+    const int a = j * c, z = std::min(a + c, K);
+    if (j != nck - 1) HIPCHK(copy_images(ctx, b->uR, slot(b->ck, j), s));
+    for (int k = a; k < z; ++k) {
+      HIPCHK(copy_images(ctx, slot(b->seg, k - a), b->uR, s));
+      if (k + 1 < z) HIPCHK(replay(b, k0 + k, true, s));
+    }
+    for (int k = z - 1; k >= a; --k) {
+      HIPCHK(copy_images(ctx, b->uR, slot(b->seg, k - a), s));
+      HIPCHK(adjoint_step(b, k0 + k, s));
+    }
+  }
+  HIPCHK(launch_adj_out(b->bwd, b->one, K, k0, grad_eps_dev, grad_scales_dev, s));
   return GFD_OK;
 }
 

@@ -60,6 +60,24 @@ struct Img {
   int w;
   float eps;
   int gfTX, gfTY, gfNBY;  // guided-filter strip geometry
+  float *lam_star_hist;   // lambda* of each iteration (before the scale)
+  // reverse mode (set only in the backward descriptor sets; null otherwise)
+  float *ga, *gmu, *gpb, *gve;  // stage 1 of the filter's adjoint: a, mean I, mean p, var + eps
+  float *gc, *gd;               // d/dc and the direct term g_u * mean(a)
+  float *gu;                    // incoming gradient with respect to the filter output
+  float *gI, *gP;               // outgoing gradients with respect to u_I and u_p
+  float *geps_part;             // per-strip partial sums of the eps gradient
+  cf *SgI, *SgP;                // half spectra of gI and gP
+  cf *G;                        // adjoint spectrum with respect to F(u_E)
+  struct AdjState *ad;
+  float *geps_hist, *gs_hist;   // per-iteration eps gradient and scale gradient
+  int bxTX, bxTY, bxNBY;        // strip geometry of the adjoint's box passes
+};
+
+// Per-image scalars of one reverse-mode iteration.
+struct AdjState {
+  float kappa;  // coefficient of the implicit-lambda term
+  int skip;     // 1: lambda = +inf on this iteration (no spectral adjoint)
 };
 
 struct Item {
@@ -89,6 +107,52 @@ struct ImgSet {
   Item *items_dev = nullptr;
 };
 
+template <class K>
+inline hipError_t set_lds(K kern, size_t lds) {
+  return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+// Append the work items of one image (blocks 0 .. nblk-1), padded to a multiple of 8 and
+// permuted so that every 8th item (one XCD's share: the hardware deals blocks to the 8 XCDs
+// in turn) covers a contiguous run of blocks, which then share that XCD's L2.
+inline void append_items(ImgSet &set, int img, int nblk) {
+  const int nx = 8;
+  const int padded = (nblk + nx - 1) / nx * nx;
+  const int per = padded / nx;
+  for (int i = 0; i < padded; ++i) {
+    const int xcd = i % nx, local = i / nx;
+    const int blk = xcd * per + local;
+    set.items_host.push_back(Item{img, blk < nblk ? blk : -1});
+  }
+}
+
+struct ItemRange {
+  size_t off, n;
+};
+
+inline ItemRange add_items(ImgSet &set, const std::vector<int> &imgs, const std::function<int(const Img &)> &nblk) {
+  ItemRange r{set.items_host.size(), 0};
+  for (int i : imgs) append_items(set, i, nblk(set.imgs[i]));
+  r.n = set.items_host.size() - r.off;
+  return r;
+}
+
+// One launch over an item range (grid = number of items, one item per block).  The set's
+// tables are read when the launch is enqueued, so it may be built before finalize_items().
+template <class K, class... A>
+inline Launch make_launch(ImgSet *setp, K kern, ItemRange r, int threads, size_t lds, A... extra) {
+  return [=](hipStream_t s) -> hipError_t {
+    if (r.n == 0) return hipSuccess;
+    if (lds > 48 * 1024) {
+      hipError_t e = set_lds(kern, lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)r.n), dim3(threads), lds, s, (const Img *)setp->dev,
+                       (const Item *)(setp->items_dev + r.off), (int)r.n, extra...);
+    return hipGetLastError();
+  };
+}
+
 // Plan builders.  `sel` picks images of the set; launches reference set.dev and offsets into
 // set.items_dev, so finalize_items() must run before a plan is enqueued.
 void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel);
@@ -100,6 +164,18 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool 
 hipError_t finalize_items(ImgSet &set);
 void gf_geometry(Img &d);
 bool guided_filter_supported(int w);
+
+// Reverse mode (kernels_adj.hip).
+void adj_geometry(Img &d);
+int adj_strips(const Img &d);
+void plan_box_stage(Plan &p, ImgSet &set, const std::vector<int> &sel, int stage);
+void plan_adj_spec(Plan &p, ImgSet &set, const std::vector<int> &sel);
+void plan_adj_col(Plan &p, ImgSet &set, const std::vector<int> &sel);
+void plan_adj_inf(Plan &p, ImgSet &set, const std::vector<int> &sel);
+ItemRange plan_one_per_image(ImgSet &set, const std::vector<int> &sel);
+hipError_t launch_lam_replay(ImgSet &set, ItemRange one, int k, hipStream_t s);
+hipError_t launch_adj_fin(ImgSet &set, ItemRange one, int k, hipStream_t s);
+hipError_t launch_adj_out(ImgSet &set, ItemRange one, int K, int k0, float *geps, float *gs, hipStream_t s);
 
 // Stand-alone guided filter on caller-provided images (context-free).
 hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,

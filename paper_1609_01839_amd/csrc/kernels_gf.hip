@@ -16,56 +16,10 @@
 // horizontal sums unroll into back-to-back LDS reads.
 #include <map>
 
+#include "box_sum.h"
 #include "gfd_internal.h"
 
 namespace gfd {
-
-constexpr int kGfThreads = 256;
-constexpr int kGfRmax = 8;
-constexpr int kGfRun = 4;  // columns per thread in the horizontal sums
-constexpr int kGfRB = 2;   // rows per round of barriers
-
-struct Kahan {
-  float s, c;
-};
-
-// s += (xn - xo), compensated
-__device__ __forceinline__ void kahan_slide(Kahan &k, float xn, float xo) {
-  const float d = __fsub_rn(xn, xo);
-  const float y = __fsub_rn(d, k.c);
-  const float t = __fadd_rn(k.s, y);
-  k.c = __fsub_rn(__fsub_rn(t, k.s), y);
-  k.s = t;
-}
-
-__device__ __forceinline__ int wrap(int v, int n) {
-  v %= n;
-  return v < 0 ? v + n : v;
-}
-
-// Horizontal window sums (half-width R) of `ntask` rows of kGfThreads values: task `t` covers
-// row t / runs and columns [run * kGfRun, run * kGfRun + kGfRun).  Columns outside [R, used - R)
-// produce don't-care values.
-template <int R>
-__device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *__restrict__ dst, int task) {
-  constexpr int runs = kGfThreads / kGfRun;
-  const int row = task / runs, run = task - row * runs;
-  const float *v = src + row * kGfThreads;
-  const int j0 = run * kGfRun;
-  float x[kGfRun + 2 * R];
-#pragma unroll
-  for (int i = 0; i < kGfRun + 2 * R; ++i) x[i] = v[min(max(j0 - R + i, 0), kGfThreads - 1)];
-  float s = 0.0f;
-#pragma unroll
-  for (int i = 0; i <= 2 * R; ++i) s += x[i];
-  float *o = dst + row * kGfThreads + j0;
-  o[0] = s;
-#pragma unroll
-  for (int i = 1; i < kGfRun; ++i) {
-    s += x[i + 2 * R] - x[i - 1];
-    o[i] = s;
-  }
-}
 
 // One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
 template <int R>
@@ -277,13 +231,7 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool 
     const size_t off = set.items_host.size();
     for (int i : kv.second) {
       const Img &d = set.imgs[i];
-      const int nblk = (d.L.N + d.gfTX - 1) / d.gfTX * d.gfNBY;
-      // every 8th item runs on one XCD: give each XCD a contiguous run of strips
-      const int padded = (nblk + 7) / 8 * 8, per = padded / 8;
-      for (int q = 0; q < padded; ++q) {
-        const int blk = (q % 8) * per + q / 8;
-        set.items_host.push_back(Item{i, blk < nblk ? blk : -1});
-      }
+      append_items(set, i, (d.L.N + d.gfTX - 1) / d.gfTX * d.gfNBY);
     }
     const size_t n = set.items_host.size() - off;
     ImgSet *setp = &set;

@@ -87,6 +87,7 @@ __device__ __forceinline__ void lam_commit(const Img &d, LamState &st) {
   if (d.lam_hist != nullptr && st.k < d.hist_cap) {
     d.lam_hist[st.k] = lam;
     d.flag_hist[st.k] = st.flags;
+    if (d.lam_star_hist != nullptr) d.lam_star_hist[st.k] = ls;
   }
 }
 
@@ -900,50 +901,6 @@ static int pick_E(size_t elems, int &threads) {
   if (e <= 4) return 4;
   if (e <= 8) return 8;
   return 16;  // elems <= 16 * 1024 by construction of the layout
-}
-
-template <class K>
-static hipError_t set_lds(K kern, size_t lds) {
-  return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
-// Append the work items of one image (blocks 0 .. nblk-1), padded to a multiple of 8 and
-// permuted so that every 8th item (one XCD's share) covers a contiguous run of blocks.
-static void append_items(ImgSet &set, int img, int nblk) {
-  const int nx = 8;
-  const int padded = (nblk + nx - 1) / nx * nx;
-  const int per = padded / nx;
-  for (int i = 0; i < padded; ++i) {
-    const int xcd = i % nx, local = i / nx;
-    const int blk = xcd * per + local;
-    set.items_host.push_back(Item{img, blk < nblk ? blk : -1});
-  }
-}
-
-struct ItemRange {
-  size_t off, n;
-};
-
-static ItemRange add_items(ImgSet &set, const std::vector<int> &imgs, const std::function<int(const Img &)> &nblk) {
-  ItemRange r{set.items_host.size(), 0};
-  for (int i : imgs) append_items(set, i, nblk(set.imgs[i]));
-  r.n = set.items_host.size() - r.off;
-  return r;
-}
-
-// One launch over an item range (grid = number of items, one item per block).
-template <class K, class... A>
-static Launch make_launch(ImgSet *setp, K kern, ItemRange r, int threads, size_t lds, A... extra) {
-  return [=](hipStream_t s) -> hipError_t {
-    if (r.n == 0) return hipSuccess;
-    if (lds > 48 * 1024) {
-      hipError_t e = set_lds(kern, lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(kern, dim3((unsigned)r.n), dim3(threads), lds, s, (const Img *)setp->dev,
-                       (const Item *)(setp->items_dev + r.off), (int)r.n, extra...);
-    return hipGetLastError();
-  };
 }
 
 // Group images by a key and call `emit` for each group.
