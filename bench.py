@@ -129,6 +129,37 @@ def batch_leg(steps: int, warmup: int, n_images: int = 64) -> dict:
             "speedup_vs_one_image_per_launch": round(ms_single / ms_batch, 2)}
 
 
+def fwd_bwd_leg(g, M: int, N: int, iters: int, repeats: int, u_ref) -> dict:
+    """Forward iterations followed by the reverse mode (gradient of an MSE loss with respect
+    to eps and the lambda scales, checkpoints every 5 iterations), on the same context."""
+    import torch
+
+    dev = u_ref.device
+    stream = torch.cuda.current_stream(dev)
+    out = torch.empty((M, N), device=dev, dtype=torch.float32)
+    lam = torch.empty((iters,), device=dev, dtype=torch.float32)
+    times = []
+    for r in range(repeats + 1):
+        g.reset()
+        torch.cuda.synchronize()
+        ev0, ev1, ev2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        ev0.record(stream)
+        g.iterate(iters, out, lam)
+        ev1.record(stream)
+        gu = (2.0 / out.numel()) * (out - u_ref)
+        g.backward(gu, 5)
+        ev2.record(stream)
+        torch.cuda.synchronize()
+        if r > 0:                      # the first pass allocates the reverse-mode buffers
+            times.append((ev0.elapsed_time(ev1), ev1.elapsed_time(ev2)))
+    fwd = sorted(t[0] for t in times)[len(times) // 2]
+    bwd = sorted(t[1] for t in times)[len(times) // 2]
+    P = M * N
+    return {"iterations": iters, "checkpoint_every": 5, "fwd_ms": round(fwd, 3), "bwd_ms": round(bwd, 3),
+            "value": round(P * iters / ((fwd + bwd) * 1e-3) / 1e6, 1), "unit": "Mpixel-iters/s",
+            "bwd_over_fwd": round(bwd / fwd, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +169,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-size batch leg")
+    ap.add_argument("--no-bwd", action="store_true", help="skip the forward+adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the deconvolution of one frame runs on a single device "
@@ -208,6 +240,10 @@ def main():
                       "stage_us": {k: round(v * 1e3, 2) for k, v in per_iter.items()},
                       "wall_s": round(wall, 4)},
     }
+    if not args.no_bwd:
+        u_ref = torch.from_numpy(case.u_orig.astype(np.float32)).to(dev)
+        line["fwd_bwd"] = fwd_bwd_leg(g, M, N, 10, 3, u_ref)
+        del u_ref
     g.close()
     del y, h, out
     if not args.no_batch:

@@ -576,7 +576,7 @@ static hipError_t build_bwd(gfd_ctx *c) {
     b->grad.imgs.push_back(gi);
     b->grad.imgs.push_back(gp);
     Img go = d;          // inverse transform of the adjoint spectrum into the gradient
-    go.SI = Gs;
+    go.SI = m.SI;
     go.SP = Gz;
     go.uI = gu;
     go.uP = m.uP;

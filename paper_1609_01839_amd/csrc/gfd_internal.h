@@ -13,14 +13,18 @@
 namespace gfd {
 
 // Geometry of one image and of its half spectrum.
-// The half spectrum (columns k = 0 .. N/2 of the row transforms) is stored tile-major:
-// tile t holds columns [t*C, t*C + C) for all M rows as a contiguous M x C block, element
-// (m, c) of tile t at ((t * M) + m) * C + c.  Columns at or beyond Wh are zero padding.
+// The half spectrum (columns k = 0 .. N/2 of the row transforms) is stored tile-major between
+// the forward row and column passes: tile t holds columns [t*C, t*C + C) for all M rows as a
+// contiguous M x C block, element (m, c) of tile t at ((t * M) + m) * C + c.  Columns at or
+// beyond Wh are zero padding.  The column pass of the inverse writes row-major instead
+// (element (m, k) at m * RP + k, RP = NT * C), so that every pass reads contiguous data and
+// the transposition happens on the write side.
 struct Layout {
   int M, N;
   int Wh;         // N / 2 + 1
   int C, logC;    // tile width (power of two)
   int NT;         // number of tiles = ceil(Wh / C)
+  int RP;         // pitch of the row-major half spectra, NT * C
   int R;          // image rows per block in the LDS-resident row passes (even)
   int Rf, Ri;     // rows per block of the register-resident row passes (forward even, inverse)
   FastDiv Ndiv;   // division by N

@@ -297,8 +297,9 @@ __global__ void __launch_bounds__(256) k_adj_fin(const Img *__restrict__ D, cons
   }
 }
 
-// Column pass of the adjoint spectrum: G += kappa g conj(H) R, then the unnormalised inverse
-// column transform, in place.
+// Column pass of the adjoint spectrum: G + kappa g conj(H) R, then the unnormalised inverse
+// column transform, written row-major to SI (free again once the replayed solves were
+// transformed) for the row pass.
 __device__ __forceinline__ cf adj_total(const Img &d, size_t i, int k, float kappa, float ls) {
   const cf h = G(d.H)[i];
   const cf Rr = cmul(h, G(d.S1)[i]) - G(d.Y)[i];
@@ -333,7 +334,7 @@ __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, c
     reg_fft<+1>(v, t, active, d.rm, lds + c, C, G(d.twM));
     if (active) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) G(d.G)[off + (t + T * m) * C + c] = v[m];
+      for (int m = 0; m < 16; ++m) G(d.SI)[(size_t)(t + T * m) * lay.RP + k] = v[m];
     }
     __syncthreads();
   }
@@ -358,7 +359,8 @@ __global__ void __launch_bounds__(1024) k_adjcol_g(const Img *__restrict__ D, co
     }
     __syncthreads();
     lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-    for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.G)[off + e] = buf[e];
+    for (int e = threadIdx.x; e < n; e += blockDim.x)
+      G(d.SI)[(size_t)(e >> lay.logC) * lay.RP + wi.blk * C + (e & (C - 1))] = buf[e];
     __syncthreads();
   }
 }

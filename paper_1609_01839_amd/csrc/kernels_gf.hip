@@ -14,6 +14,8 @@
 // (the image means when known) before products are formed; the filter commutes with such
 // shifts (u shifts by the input's constant).  The radius is a template parameter so that the
 // horizontal sums unroll into back-to-back LDS reads.
+#include <stdlib.h>
+
 #include <map>
 
 #include "box_sum.h"
@@ -200,6 +202,7 @@ static void gf_tiles(int M, int N, int R, int &TX, int &TY, int &nbx, int &nby) 
   TX = kGfThreads - 4 * R;
   if (TX > N) TX = N;
   TY = 64;
+  if (const char *e = getenv("GFD_TUNE_GFTY")) TY = atoi(e);
   if (TY > M) TY = M;
   nbx = (N + TX - 1) / TX;
   nby = (M + TY - 1) / TY;

@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SP)[off + e] = buf[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SP)[(size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1))] = buf[e];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < E; ++u) {
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SI)[off + e] = buf[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SI)[(size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1))] = buf[e];
   GFD_ITEM_END
 }
 
@@ -312,23 +312,22 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
   cf *buf = reinterpret_cast<cf *>(smem_raw);
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
-  const int M = lay.M, N = lay.N, R = lay.R, C = lay.C, Wh = lay.Wh, LP = N + 1;
+  const int M = lay.M, N = lay.N, R = lay.R, Wh = lay.Wh, LP = N + 1;
   const int r0 = wi.blk * R;
-  const int per_t = R * C, total = lay.NT * per_t;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int t = fdiv(e, lay.RCdiv), rem = e - t * per_t;
-    const int rho = rem >> lay.logC, c = rem & (C - 1);
-    const int m = r0 + rho, k = t * C + c;
-    if (m >= M || k >= Wh) continue;
-    const size_t g = ((size_t)t * M + m) * C + c;
-    cf A = G(d.SI)[g], B = G(d.SP)[g];
-    if (k == 0 || 2 * k == N) {
-      A.im = 0.0f;
-      B.im = 0.0f;
-    }
+  for (int rho = 0; rho < R; ++rho) {
+    const int m = r0 + rho;
+    if (m >= M) break;
     cf *z = buf + rho * LP;
-    z[k] = cf{A.re - B.im, A.im + B.re};
-    if (k > 0 && N - k >= Wh) z[N - k] = cf{A.re + B.im, B.re - A.im};
+    for (int k = threadIdx.x; k < Wh; k += blockDim.x) {
+      const size_t g = (size_t)m * lay.RP + k;
+      cf A = G(d.SI)[g], B = G(d.SP)[g];
+      if (k == 0 || 2 * k == N) {
+        A.im = 0.0f;
+        B.im = 0.0f;
+      }
+      z[k] = cf{A.re - B.im, A.im + B.re};
+      if (k > 0 && N - k >= Wh) z[N - k] = cf{A.re + B.im, B.re - A.im};
+    }
   }
   __syncthreads();
   lds_fft<float, E, +1, false>(buf, R, 0, 1, LP, d.pn, G(d.twN));
@@ -348,7 +347,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 // and last passes straight from / to global memory.  Threads beyond an image's need (blocks
 // sized for a larger image of the batch) only join the barriers.
 
-__global__ void __launch_bounds__(512) k_row_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+__global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
@@ -486,24 +485,24 @@ __global__ void __launch_bounds__(512) k_col_inv_r16(const Img *__restrict__ D, 
   reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
   if (active) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) G(d.SP)[off + (t + T * m) * C + c] = vp[m];
+    for (int m = 0; m < 16; ++m) G(d.SP)[(size_t)(t + T * m) * lay.RP + k] = vp[m];
   }
   reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
   if (active) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) G(d.SI)[off + (t + T * m) * C + c] = vi[m];
+    for (int m = 0; m < 16; ++m) G(d.SI)[(size_t)(t + T * m) * lay.RP + k] = vi[m];
   }
   GFD_ITEM_END
 }
 
 // Row pass, inverse; the Hermitian completion is gathered straight from the tile-major spectra.
-__global__ void __launch_bounds__(512) k_row_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+__global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
-  const int M = lay.M, N = lay.N, C = lay.C, Wh = lay.Wh, T = d.rn.T;
+  const int M = lay.M, N = lay.N, Wh = lay.Wh, T = d.rn.T;
   const int LP = N + (N >> 4);
   const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
   const bool active = seq < lay.Ri;
@@ -516,7 +515,7 @@ __global__ void __launch_bounds__(512) k_row_inv_r16(const Img *__restrict__ D, 
       const int n = t + T * m;
       const bool direct = n < Wh;
       const int kk = direct ? n : N - n;
-      const size_t g = ((size_t)(kk >> lay.logC) * M + rowc) * C + (kk & (C - 1));
+      const size_t g = (size_t)rowc * lay.RP + kk;
       cf A = G(d.SI)[g], B = G(d.SP)[g];
       if (kk == 0 || 2 * kk == N) {
         A.im = 0.0f;
@@ -835,6 +834,7 @@ Layout make_layout(int M, int N) {
   L.C = C;
   L.logC = ilog2(C);
   L.NT = (L.Wh + C - 1) / C;
+  L.RP = L.NT * C;
   // rows per block in the LDS-resident row passes: aim at >= 128-byte segments, LDS <= 64 KiB
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
