@@ -31,11 +31,17 @@
 namespace gfd {
 
 // ============================================================================ box passes
+// Each stage loads NR raw values per pixel (load) and derives its NF summed fields from them
+// (fields); the two steps are apart so that loads can be issued a round ahead.
 struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
-  static constexpr int NF = 4;
+  static constexpr int NF = 4, NR = 2;
   static constexpr bool kEps = false;
-  __device__ static void load(const Img &d, size_t g, float cI, float cP, float (&v)[NF]) {
-    const float I = __fsub_rn(G(d.uI)[g], cI), p = __fsub_rn(G(d.uP)[g], cP);
+  __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
+    r[0] = G(d.uI)[g];
+    r[1] = G(d.uP)[g];
+  }
+  __device__ static void fields(const float (&r)[NR], float cI, float cP, float (&v)[NF]) {
+    const float I = __fsub_rn(r[0], cI), p = __fsub_rn(r[1], cP);
     v[0] = I;
     v[1] = p;
     v[2] = I * I;
@@ -54,13 +60,17 @@ struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
 };
 
 struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c, g_u B(a)
-  static constexpr int NF = 3;
+  static constexpr int NF = 3, NR = 3;
   static constexpr bool kEps = true;
-  __device__ static void load(const Img &d, size_t g, float cI, float, float (&v)[NF]) {
-    const float gu = G(d.gu)[g];
-    v[0] = G(d.ga)[g];
-    v[1] = gu * __fsub_rn(G(d.uI)[g], cI);
-    v[2] = gu;
+  __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
+    r[0] = G(d.ga)[g];
+    r[1] = G(d.gu)[g];
+    r[2] = G(d.uI)[g];
+  }
+  __device__ static void fields(const float (&r)[NR], float cI, float, float (&v)[NF]) {
+    v[0] = r[0];
+    v[1] = r[1] * __fsub_rn(r[2], cI);
+    v[2] = r[1];
   }
   // Pointwise reads of mu, pbar, v + eps at the emitted pixel come before the writes that
   // replace them; no other pixel reads them.
@@ -84,13 +94,17 @@ struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c
 };
 
 struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
-  static constexpr int NF = 4;
+  static constexpr int NF = 4, NR = 4;
   static constexpr bool kEps = false;
-  __device__ static void load(const Img &d, size_t g, float, float, float (&v)[NF]) {
-    v[0] = G(d.gmu)[g];
-    v[1] = G(d.gc)[g];
-    v[2] = G(d.gve)[g];
-    v[3] = G(d.gpb)[g];
+  __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
+    r[0] = G(d.gmu)[g];
+    r[1] = G(d.gc)[g];
+    r[2] = G(d.gve)[g];
+    r[3] = G(d.gpb)[g];
+  }
+  __device__ static void fields(const float (&r)[NR], float, float, float (&v)[NF]) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = r[f];
   }
   __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], float cI, float cP, float &) {
     const float I = __fsub_rn(G(d.uI)[g], cI), p = __fsub_rn(G(d.uP)[g], cP);
@@ -108,8 +122,9 @@ template <int R, class Op>
 __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict__ D, const Item *__restrict__ W,
                                                           int nitems) {
   constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = kGfRB;
-  __shared__ float vbuf[RB * NF * kGfThreads];
-  __shared__ float hbuf[RB * NF * kGfThreads];
+  constexpr int VP = hs_pitch<R>();
+  __shared__ __align__(16) float vbuf[RB * NF * VP];
+  __shared__ __align__(16) float hbuf[RB * NF * kGfThreads];
   __shared__ float red[kGfThreads / 64];
   const float inv_w2 = 1.0f / (float)(Wn * Wn);
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
@@ -124,32 +139,50 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
     const int gx = wrap(x0 - R + j, N);
     const int nrows = TY + 2 * R, ybase = y0 - R;  // stream row it is image row ybase + it
     const float cI = d.st->meanI, cP = d.st->meanP;
+    hs_zero_pads<R>(vbuf, RB * NF);  // ordered before the first reads by the first barrier
     Kahan s[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) s[f] = Kahan{0.0f, 0.0f};
     float eacc = 0.0f;
+    constexpr int NR = Op::NR;
+    // raw values of the rows entering and leaving the windows, loaded one round ahead; every
+    // load is unconditional (wrapped, clamped rows) so that the compiler can keep the next
+    // round's loads in flight while this round is summed
+    float cn[RB][NR], co[RB][NR], nn[RB][NR], no[RB][NR];
+    auto fetch = [&](int it, float (&rn)[NR], float (&ro)[NR]) {
+      const int itc = min(it, nrows - 1);
+      Op::load(d, (size_t)wrap(ybase + itc, M) * N + gx, rn);
+      Op::load(d, (size_t)wrap(ybase + itc - Wn, M) * N + gx, ro);
+    };
+#pragma unroll
+    for (int q = 0; q < RB; ++q) fetch(q, nn[q], no[q]);
     for (int base = 0; base < nrows; base += RB) {
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          cn[q][r] = nn[q][r];
+          co[q][r] = no[q][r];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RB; ++q) fetch(base + RB + q, nn[q], no[q]);
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
         const int it = base + q;
-        float *vb = vbuf + q * NF * kGfThreads;
+        float *vb = vbuf + q * NF * VP + R;
         if (active && it < nrows) {
           float vn[NF], vo[NF];
-          Op::load(d, (size_t)wrap(ybase + it, M) * N + gx, cI, cP, vn);
-          if (it >= Wn) {
-            Op::load(d, (size_t)wrap(ybase + it - Wn, M) * N + gx, cI, cP, vo);
-          } else {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) vo[f] = 0.0f;
-          }
+          Op::fields(cn[q], cI, cP, vn);
+          Op::fields(co[q], cI, cP, vo);
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
-            kahan_slide(s[f], vn[f], vo[f]);
-            vb[f * kGfThreads + j] = s[f].s;
+            kahan_slide(s[f], vn[f], it >= Wn ? vo[f] : 0.0f);
+            vb[f * VP + j] = s[f].s;
           }
         } else {
 #pragma unroll
-          for (int f = 0; f < NF; ++f) vb[f * kGfThreads + j] = 0.0f;
+          for (int f = 0; f < NF; ++f) vb[f * VP + j] = 0.0f;
         }
       }
       __syncthreads();

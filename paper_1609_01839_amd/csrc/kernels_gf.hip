@@ -31,6 +31,8 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
                                          float *__restrict__ vbuf, float *__restrict__ hbuf) {
   constexpr int W = 2 * R + 1;
   constexpr int RB = kGfRB;
+  constexpr int VP = hs_pitch<R>();  // padded row of vertical sums
+  hs_zero_pads<R>(vbuf, RB * 4);     // ordered before the first reads by the first barrier
   const float inv_w2 = 1.0f / (float)(W * W);
   const int bx = lb / nby, by = lb - bx * nby;
   const int x0 = bx * TX, y0 = by * TY;
@@ -45,30 +47,36 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   struct RowIn {
     float I, p, Io, po, Ig;
   };
+  // Loads are issued unconditionally (rows clamped and wrapped, so every address is valid;
+  // unused values are discarded where they are consumed): with no branch around them the
+  // compiler can count the loads in flight and let the next round's loads overlap this
+  // round's arithmetic instead of draining the memory queue.
   auto fetch = [&](int it) -> RowIn {
-    RowIn v = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (!active || it >= nrows) return v;
-    const size_t g = (size_t)wrap(ybase + it, M) * N + gx;
+    const int itc = min(it, nrows - 1);
+    RowIn v;
+    const size_t g = (size_t)wrap(ybase + itc, M) * N + gx;
     v.I = uI[g];
     v.p = uP[g];
-    if (it >= W) {
-      const size_t go = (size_t)wrap(ybase + it - W, M) * N + gx;
-      v.Io = uI[go];
-      v.po = uP[go];
-    }
-    if (it >= 4 * R) v.Ig = uI[(size_t)wrap(ybase + it - 2 * R, M) * N + gx];  // guide of the output row
+    const size_t go = (size_t)wrap(ybase + itc - W, M) * N + gx;
+    v.Io = uI[go];
+    v.po = uP[go];
+    v.Ig = uI[(size_t)wrap(ybase + itc - 2 * R, M) * N + gx];  // guide of the output row
     return v;
   };
 
   Kahan sI = {0, 0}, sP = {0, 0}, sII = {0, 0}, sIP = {0, 0}, sA = {0, 0}, sB = {0, 0};
-  RowIn cur[RB], nxt[RB];
+  // Software pipelining: each round first consumes the rows loaded during the previous round
+  // (the vertical updates, and a copy of the guide values), then issues the loads of the next
+  // round into the same registers, and only then does the rest of its work.  The wait for a
+  // round's loads thus comes a whole round after they were issued, with no newer loads in
+  // flight that it would have to drain.
+  RowIn cur[RB];
 #pragma unroll
-  for (int q = 0; q < RB; ++q) nxt[q] = fetch(q);
+  for (int q = 0; q < RB; ++q) cur[q] = fetch(q);
   for (int base = 0; base < nrows; base += RB) {
+    float Ig[RB];
 #pragma unroll
-    for (int q = 0; q < RB; ++q) cur[q] = nxt[q];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) nxt[q] = fetch(base + RB + q);
+    for (int q = 0; q < RB; ++q) Ig[q] = cur[q].Ig;
     // ---- stage 1, vertical
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
@@ -80,16 +88,18 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         kahan_slide(sP, p, po);
         kahan_slide(sII, I * I, Io * Io);
         kahan_slide(sIP, I * p, Io * po);
-        float *vb = vbuf + q * 4 * kGfThreads;
+        float *vb = vbuf + q * 4 * VP + R;
         vb[j] = sI.s;
-        vb[kGfThreads + j] = sP.s;
-        vb[2 * kGfThreads + j] = sII.s;
-        vb[3 * kGfThreads + j] = sIP.s;
+        vb[VP + j] = sP.s;
+        vb[2 * VP + j] = sII.s;
+        vb[3 * VP + j] = sIP.s;
       } else {
-        float *vb = vbuf + q * 4 * kGfThreads;
-        vb[j] = vb[kGfThreads + j] = vb[2 * kGfThreads + j] = vb[3 * kGfThreads + j] = 0.0f;
+        float *vb = vbuf + q * 4 * VP + R;
+        vb[j] = vb[VP + j] = vb[2 * VP + j] = vb[3 * VP + j] = 0.0f;
       }
     }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) cur[q] = fetch(base + RB + q);
     __syncthreads();
     if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
     // ---- stage 1, horizontal: RB rows x 4 quantities
@@ -101,7 +111,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
     for (int q = 0; q < RB; ++q) {
       const int it = base + q;
       const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
-      float *vb = vbuf + q * 2 * kGfThreads;
+      float *vb = vbuf + q * 2 * VP + R;
       if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
         const float *hb = hbuf + q * 4 * kGfThreads;
         const float mu = hb[j] * inv_w2;
@@ -117,12 +127,12 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         kahan_slide(sA, a, old.x);
         kahan_slide(sB, b, old.y);
         vb[j] = sA.s;
-        vb[kGfThreads + j] = sB.s;
+        vb[VP + j] = sB.s;
       } else {
         // Columns without coefficients still enter the first window of a sliding run before
         // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
         vb[j] = 0.0f;
-        vb[kGfThreads + j] = 0.0f;
+        vb[VP + j] = 0.0f;
       }
     }
     __syncthreads();
@@ -140,7 +150,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
       if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
         const float *hb = hbuf + q * 2 * kGfThreads;
         const float abar = hb[j] * inv_w2, bbar = hb[kGfThreads + j] * inv_w2;
-        const float I = __fsub_rn(cur[q].Ig, cI);
+        const float I = __fsub_rn(Ig[q], cI);
         u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, I, bbar), cP);
       }
     }
@@ -157,8 +167,8 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, 
                                                      int nitems, int close_iteration) {
   constexpr int Wn = 2 * R + 1;
   __shared__ float2 ringAB[Wn * kGfThreads];
-  __shared__ float vbuf[kGfRB * 4 * kGfThreads];
-  __shared__ float hbuf[kGfRB * 4 * kGfThreads];
+  __shared__ __align__(16) float vbuf[kGfRB * 4 * hs_pitch<R>()];
+  __shared__ __align__(16) float hbuf[kGfRB * 4 * kGfThreads];
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
     const Item wi = W[ii];
     if (wi.blk < 0) continue;
@@ -190,8 +200,8 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict
                                                          int TY, int nby) {
   constexpr int Wn = 2 * R + 1;
   __shared__ float2 ringAB[Wn * kGfThreads];
-  __shared__ float vbuf[kGfRB * 4 * kGfThreads];
-  __shared__ float hbuf[kGfRB * 4 * kGfThreads];
+  __shared__ __align__(16) float vbuf[kGfRB * 4 * hs_pitch<R>()];
+  __shared__ __align__(16) float hbuf[kGfRB * 4 * kGfThreads];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   gf_strip<R>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], ringAB, vbuf, hbuf);
 }
