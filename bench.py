@@ -97,6 +97,7 @@ def batch_leg(steps: int, warmup: int, n_images: int = 64) -> dict:
         return ev0.elapsed_time(ev1) / n
 
     with gfd.GFDeconvBatch(probs) as gb:
+        gb.autotune(2)
         out = torch.empty((gb.total,), device=dev, dtype=torch.float32)
         lam = torch.empty((gb.count, 1), device=dev, dtype=torch.float32)
         for _ in range(warmup):
@@ -170,6 +171,7 @@ def main():
     ap.add_argument("--profile-iters", type=int, default=10)
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+adjoint leg")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the deconvolution of one frame runs on a single device "
@@ -190,6 +192,7 @@ def main():
     y = torch.from_numpy(case.y).to(dev)
     h = torch.from_numpy(case.h.astype(np.float32)).to(dev)
     g = gfd.GFDeconv(y, h, case.sigma2, case.w, case.eps)
+    tuning = None if args.no_autotune else g.autotune(4)
     stream = torch.cuda.current_stream(dev)
     out = torch.empty((M, N), device=dev, dtype=torch.float32)
     lam = torch.empty((1,), device=dev, dtype=torch.float32)
@@ -233,7 +236,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{M}x{N} piecewise-constant synthetic image, Gaussian PSF std 2.5 on 31x31, "
                                f"sigma^2=4, w=17, eps=650.25, forward iteration (one step = one iteration)",
-                   "M": M, "N": N, "iters_per_step": 1, "hip_graph": True},
+                   "M": M, "N": N, "iters_per_step": 1, "hip_graph": True, "autotune": tuning},
         "roofline": roofline,
         "iteration": {"alg_bytes_per_px": round((total_alg + 8 * Q) / P, 2),
                       "alg_frac_of_hbm_roofline": round((total_alg / P) * P / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

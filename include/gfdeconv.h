@@ -171,6 +171,20 @@ gfd_status deconv_set_graph(gfd_ctx *ctx, int use_graph);
 gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_stages, void *stream);
 
 /*
+ * deconv_autotune -- pick launch shapes for this context by timing: the guided filter's strip
+ * height and the rows per block of the power-of-two row transforms are tried one knob at a
+ * time (coordinate descent from the defaults), each candidate over `iters` replays of the
+ * captured iteration (0 selects 4; at most 64), and the fastest is kept.  The arithmetic is
+ * the same in every shape except where the filter's running sums restart (strip edges), so
+ * results agree to rounding.  Needs a context with no
+ * iterations run (after deconv_init or deconv_reset); the estimate and the search state are
+ * restored afterwards.  choice_host (3 ints, host, or NULL) receives the strip height, the
+ * forward row pairs per block and the inverse rows per block chosen for image 0.
+ * Synchronises `stream`.
+ */
+gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stream);
+
+/*
  * deconv_backward -- reverse mode of the iterations run since the estimate was last set
  * (deconv_init, deconv_reset or deconv_set_estimate): given g_u = dLoss/du for the current
  * estimate u^K, the gradient of the loss with respect to the guided-filter regulariser eps

@@ -45,6 +45,7 @@ EXPORTS = {
     "deconv_set_graph": (_i, [_vp, _i]),
     "deconv_profile": (_i, [_vp, _i, ctypes.POINTER(_f), _i, _vp]),
     "deconv_backward": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
+    "deconv_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), _vp]),
     "deconv_destroy": (None, [_vp]),
     "gfd_last_error": (ctypes.c_char_p, []),
 }
@@ -167,6 +168,12 @@ class GFDeconv:
     def reset(self):
         _check(load_library().deconv_reset(self.handle, _stream(self.device)))
         self._k_start = 0
+
+    def autotune(self, iters: int = 4) -> dict:
+        """Time candidate launch shapes and keep the fastest (needs no iterations run yet)."""
+        ch = (_i * 3)()
+        _check(load_library().deconv_autotune(self.handle, int(iters), ch, _stream(self.device)))
+        return {"gf_strip_rows": ch[0], "row_pairs_fwd": ch[1], "rows_inv": ch[2]}
 
     def set_graph(self, use_graph: bool):
         _check(load_library().deconv_set_graph(self.handle, 1 if use_graph else 0))

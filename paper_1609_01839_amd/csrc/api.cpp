@@ -59,6 +59,7 @@ struct gfd_ctx {
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
   struct Bwd *bwd = nullptr;   // reverse-mode buffers and plans, built on first use
+  Tuning tune;                 // launch shapes in use (deconv_autotune)
 };
 
 // Reverse mode: descriptor sets over the same images.
@@ -501,6 +502,40 @@ static gfd_status copy_estimates_out(gfd_ctx *c, float *u_out, hipStream_t s) {
   return GFD_OK;
 }
 
+// ---------------------------------------------------------------- launch-shape tuning
+// New launch shapes for every image: layouts and strip geometry are recomputed (buffer sizes
+// do not depend on them), and every plan, the captured graph and the reverse-mode sets are
+// rebuilt.
+static hipError_t apply_tuning(gfd_ctx *c, const Tuning &t) {
+  for (Img &d : c->main.imgs) {
+    d.L = make_layout(d.L.M, d.L.N, t);
+    gf_geometry(d, t.gf_ty);
+  }
+  if (c->count == 1) {
+    Img &a = c->aux.imgs[0];
+    const Img &m = c->main.imgs[0];
+    a.L = m.L;
+    a.gfTX = m.gfTX;
+    a.gfTY = m.gfTY;
+    a.gfNBY = m.gfNBY;
+  }
+  c->tune = t;
+  for (Plan *p : {&c->iter, &c->warm, &c->aux_solve, &c->aux_lam}) p->steps.clear();
+  for (Plan &p : c->stage) p.steps.clear();
+  c->main.items_host.clear();
+  c->aux.items_host.clear();
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  free_bwd(c->bwd);
+  c->bwd = nullptr;
+  hipError_t e = upload_table(c->main);
+  if (e == hipSuccess && c->count == 1) e = upload_table(c->aux);
+  if (e == hipSuccess) e = build_plans(c);
+  return e;
+}
+
 // ---------------------------------------------------------------- reverse mode
 template <class T>
 static hipError_t balloc(Bwd *b, T **p, size_t count) {
@@ -895,6 +930,97 @@ gfd_status deconv_set_graph(gfd_ctx *ctx, int use_graph) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   ctx->use_graph = use_graph ? 1 : 0;
+  return GFD_OK;
+}
+
+gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stream) {
+  g_err.clear();
+  if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (ctx->iters != 0) return fail(GFD_ERR_STATE, "deconv_autotune needs a context with no iterations run");
+  if (iters < 0 || iters > 64) return fail(GFD_ERR_ARG, "iters must be in [0, 64] (0: default 4)");
+  const int n = iters == 0 ? 4 : std::max(iters, 2);
+  hipStream_t s = (hipStream_t)stream;
+  gfd_ctx *c = ctx;
+  // the trial iterations advance the estimate and the search state: keep copies
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<LamState> st_save(c->count);
+  HIPCHK(hipMemcpy(st_save.data(), c->st, c->count * sizeof(LamState), hipMemcpyDeviceToHost));
+  std::vector<float *> ue_save(c->count, nullptr);
+  auto release = [&]() {
+    for (float *p : ue_save)
+      if (p) (void)hipFree(p);
+  };
+  for (int i = 0; i < c->count; ++i) {
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+    hipError_t e = hipMalloc((void **)&ue_save[i], P * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(ue_save[i], c->main.imgs[i].uE, P * sizeof(float), hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      release();
+      return fail(e == hipErrorOutOfMemory ? GFD_ERR_NOMEM : GFD_ERR_HIP, "autotune set-up failed: %s",
+                  hipGetErrorString(e));
+    }
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  gfd_status rc = GFD_OK;
+  auto trial = [&](const Tuning &t, float &ms) -> bool {
+    hipError_t e = apply_tuning(c, t);
+    if (e != hipSuccess) {
+      rc = fail(GFD_ERR_HIP, "autotune rebuild failed: %s", hipGetErrorString(e));
+      return false;
+    }
+    if ((rc = capture_graph(c)) != GFD_OK) return false;
+    e = hipGraphLaunch(c->gexec, s);  // warm-up replay
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int k = 0; k < n && e == hipSuccess; ++k) e = hipGraphLaunch(c->gexec, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      rc = fail(GFD_ERR_HIP, "autotune trial failed: %s", hipGetErrorString(e));
+      return false;
+    }
+    return true;
+  };
+  // coordinate descent over the knobs, starting from the defaults
+  Tuning best{};
+  float best_ms = 0.0f;
+  bool ok = trial(best, best_ms);
+  const int gf_ty[] = {32, 64, 96, 128}, seqs[] = {1, 2, 4};
+  for (int knob = 0; knob < 3 && ok; ++knob) {
+    const int *vals = knob == 0 ? gf_ty : seqs;
+    const int nv = knob == 0 ? 4 : 3;
+    for (int v = 0; v < nv && ok; ++v) {
+      Tuning t = best;
+      int &field = knob == 0 ? t.gf_ty : knob == 1 ? t.seq_fwd : t.seq_inv;
+      field = vals[v];
+      float ms = 0.0f;
+      ok = trial(t, ms);
+      if (ok && ms < 0.99f * best_ms) {
+        best = t;
+        best_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hipError_t e = ok ? apply_tuning(c, best) : hipSuccess;
+  // back to the state before the trials
+  for (int i = 0; i < c->count && e == hipSuccess; ++i) {
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+    e = hipMemcpy(c->main.imgs[i].uE, ue_save[i], P * sizeof(float), hipMemcpyDeviceToDevice);
+  }
+  if (e == hipSuccess) e = hipMemcpy(c->st, st_save.data(), c->count * sizeof(LamState), hipMemcpyHostToDevice);
+  release();
+  if (!ok) return rc;
+  if (e != hipSuccess) return fail(GFD_ERR_HIP, "autotune restore failed: %s", hipGetErrorString(e));
+  if (choice_host) {
+    const Img &d = c->main.imgs[0];
+    choice_host[0] = d.gfTY;
+    choice_host[1] = d.L.Rf / 2;
+    choice_host[2] = d.L.Ri;
+  }
   return GFD_OK;
 }
 

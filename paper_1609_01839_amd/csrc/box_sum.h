@@ -8,7 +8,7 @@ namespace gfd {
 
 constexpr int kGfThreads = 256;
 constexpr int kGfRmax = 8;
-constexpr int kGfRun = 4;  // columns per thread in the horizontal sums
+constexpr int kGfRun = 8;  // columns per thread in the horizontal sums (a multiple of 4)
 constexpr int kGfRB = 2;   // rows per round of barriers
 
 struct Kahan {
@@ -41,12 +41,11 @@ constexpr int hs_pitch() {
 // Horizontal window sums (half-width R) over rows of padded vertical sums: task `t` covers row
 // t / runs and output columns [j0, j0 + kGfRun), j0 = run * kGfRun.  Its inputs, columns
 // j0 - R .. j0 + kGfRun - 1 + R, start at the 16-byte aligned index j0 and are read as float4
-// (consecutive lanes read consecutive 16-byte words: no bank conflicts); the outputs go out as
-// one float4 into rows of kGfThreads floats.  Columns outside [R, used - R) produce don't-care
+// words; the outputs go out as float4 words into rows of kGfThreads floats.  Columns outside [R, used - R) produce don't-care
 // values.
 template <int R>
 __device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *__restrict__ dst, int task) {
-  static_assert(kGfRun == 4, "one float4 of outputs per task");
+  static_assert(kGfRun % 4 == 0, "outputs go out as float4");
   constexpr int runs = kGfThreads / kGfRun;
   constexpr int NX = kGfRun + 2 * R, NV = (NX + 3) / 4;
   const int row = task / runs, run = task - row * runs;
@@ -71,7 +70,9 @@ __device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *
     s += x[i + 2 * R] - x[i - 1];
     o[i] = s;
   }
-  *reinterpret_cast<float4 *>(dst + row * kGfThreads + j0) = make_float4(o[0], o[1], o[2], o[3]);
+  float4 *d4 = reinterpret_cast<float4 *>(dst + row * kGfThreads + j0);
+#pragma unroll
+  for (int k = 0; k < kGfRun / 4; ++k) d4[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
 }
 
 // Zero the padding columns of `nrows` padded rows (every thread of the block calls this).

@@ -33,7 +33,16 @@ struct Layout {
   __host__ __device__ size_t bins() const { return (size_t)NT * M * C; }
 };
 
-Layout make_layout(int M, int N);
+// Launch-shape choices that do not change results (the autotuner's knobs); 0 = default.
+struct Tuning {
+  int gf_ty = 0;    // rows per guided-filter strip
+  int seq_fwd = 0;  // row pairs per block of the register-resident forward row pass
+  int seq_inv = 0;  // rows per block of the register-resident inverse row pass
+};
+
+Layout make_layout(int M, int N, const Tuning &tune = Tuning{});
+size_t reg_seq_lds(int N);
+bool reg_seqs_ok(int N, int seqs);
 FftPlan make_plan(int L);
 
 constexpr int kLamAccFirst = 2 + 2 * kLamFirstCand;  // Einf, floor, f and slope per candidate
@@ -141,6 +150,14 @@ inline ItemRange add_items(ImgSet &set, const std::vector<int> &imgs, const std:
   return r;
 }
 
+// One block per image, without padding (kernels with a single block per image).
+inline ItemRange add_one_per_image(ImgSet &set, const std::vector<int> &imgs) {
+  ItemRange r{set.items_host.size(), 0};
+  for (int i : imgs) set.items_host.push_back(Item{i, 0});
+  r.n = set.items_host.size() - r.off;
+  return r;
+}
+
 // One launch over an item range (grid = number of items, one item per block).  The set's
 // tables are read when the launch is enqueued, so it may be built before finalize_items().
 template <class K, class... A>
@@ -166,7 +183,7 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool close_iteration);
 hipError_t finalize_items(ImgSet &set);
-void gf_geometry(Img &d);
+void gf_geometry(Img &d, int ty = 0);
 bool guided_filter_supported(int w);
 
 // Reverse mode (kernels_adj.hip).

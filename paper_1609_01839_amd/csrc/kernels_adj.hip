@@ -509,7 +509,7 @@ void plan_adj_inf(Plan &p, ImgSet &set, const std::vector<int> &sel) {
 }
 
 ItemRange plan_one_per_image(ImgSet &set, const std::vector<int> &sel) {
-  return add_items(set, sel, [](const Img &) { return 1; });
+  return add_one_per_image(set, sel);
 }
 
 hipError_t launch_lam_replay(ImgSet &set, ItemRange one, int k, hipStream_t s) {

@@ -14,8 +14,6 @@
 // (the image means when known) before products are formed; the filter commutes with such
 // shifts (u shifts by the input's constant).  The radius is a template parameter so that the
 // horizontal sums unroll into back-to-back LDS reads.
-#include <stdlib.h>
-
 #include <map>
 
 #include "box_sum.h"
@@ -118,7 +116,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         const float pb = hb[kGfThreads + j] * inv_w2;
         const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * inv_w2), 0.0f);
         const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * inv_w2);
-        const float a = cov / (var + eps);
+        const float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
         const float b = __fmaf_rn(-a, mu, pb);
         const int slot = it2 % W;
         float2 old = make_float2(0.0f, 0.0f);
@@ -208,19 +206,18 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict
 
 bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
 
-static void gf_tiles(int M, int N, int R, int &TX, int &TY, int &nbx, int &nby) {
+static void gf_tiles(int M, int N, int R, int ty, int &TX, int &TY, int &nbx, int &nby) {
   TX = kGfThreads - 4 * R;
   if (TX > N) TX = N;
-  TY = 64;
-  if (const char *e = getenv("GFD_TUNE_GFTY")) TY = atoi(e);
+  TY = ty > 0 ? ty : 64;
   if (TY > M) TY = M;
   nbx = (N + TX - 1) / TX;
   nby = (M + TY - 1) / TY;
 }
 
-void gf_geometry(Img &d) {
+void gf_geometry(Img &d, int ty) {
   int nbx;
-  gf_tiles(d.L.M, d.L.N, (d.w - 1) / 2, d.gfTX, d.gfTY, nbx, d.gfNBY);
+  gf_tiles(d.L.M, d.L.N, (d.w - 1) / 2, ty, d.gfTX, d.gfTY, nbx, d.gfNBY);
 }
 
 #define GFD_R_SWITCH(r, X)                                                                                  \
@@ -266,7 +263,7 @@ hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u
   const int r = (w - 1) / 2;
   if (!guided_filter_supported(w)) return hipErrorInvalidValue;
   int TX, TY, nbx, nby;
-  gf_tiles(M, N, r, TX, TY, nbx, nby);
+  gf_tiles(M, N, r, 0, TX, TY, nbx, nby);
 #define GFD_LAUNCH_GFP(RR) \
   hipLaunchKernelGGL(k_gf_plain<RR>, dim3(nbx * nby), dim3(kGfThreads), 0, s, uI, uP, u, M, N, eps, TX, TY, nby)
   GFD_R_SWITCH(r, GFD_LAUNCH_GFP)

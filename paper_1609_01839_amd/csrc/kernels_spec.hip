@@ -452,7 +452,7 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
   GFD_ITEM_END
 }
 
-__global__ void __launch_bounds__(512) k_col_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) k_col_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
@@ -822,7 +822,7 @@ static FastDiv mkdiv(int d) {
   return f;
 }
 
-Layout make_layout(int M, int N) {
+Layout make_layout(int M, int N, const Tuning &tune) {
   Layout L;
   L.M = M;
   L.N = N;
@@ -839,17 +839,18 @@ Layout make_layout(int M, int N) {
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
   L.R = R;
-  // register-resident row passes (power-of-two N): T = N / 16 threads per sequence
+  // register-resident row passes (power-of-two N): T = N / 16 threads per sequence, `seqs`
+  // sequences per block (forward: pairs of rows; inverse: rows)
   L.Rf = L.Ri = 2;
   if (reg_plan_ok(N)) {
     const int T = N / 16, target = N >= 2048 ? 512 : 256;
-    const size_t lds_seq = (size_t)(N + N / 16) * sizeof(cf);
     int seqs = target / T > 1 ? target / T : 1;
-    while (seqs > 1 && seqs * lds_seq > 80 * 1024) seqs /= 2;
-    L.Rf = 2 * seqs;
-    L.Ri = seqs;
-    if (const char *e = getenv("GFD_TUNE_RF")) L.Rf = atoi(e);
-    if (const char *e = getenv("GFD_TUNE_RI")) L.Ri = atoi(e);
+    while (seqs > 1 && seqs * reg_seq_lds(N) > 80 * 1024) seqs /= 2;
+    int sf = seqs, si = seqs;
+    if (tune.seq_fwd > 0 && reg_seqs_ok(N, tune.seq_fwd)) sf = tune.seq_fwd;
+    if (tune.seq_inv > 0 && reg_seqs_ok(N, tune.seq_inv)) si = tune.seq_inv;
+    L.Rf = 2 * sf;
+    L.Ri = si;
     while (L.Rf > 2 && L.Rf / 2 > (M + 1) / 2) L.Rf /= 2;
     while (L.Ri > 1 && L.Ri > M) L.Ri /= 2;
   }
@@ -857,6 +858,15 @@ Layout make_layout(int M, int N) {
   L.RCdiv = mkdiv(R * C);
   L.RfCdiv = mkdiv(L.Rf * C);
   return L;
+}
+
+size_t reg_seq_lds(int N) { return (size_t)(N + N / 16) * sizeof(cf); }
+
+// A block of `seqs` register-resident sequences of length N fits: at most 1024 threads and
+// 160 KiB of LDS, power-of-two count.
+bool reg_seqs_ok(int N, int seqs) {
+  return reg_plan_ok(N) && seqs >= 1 && (seqs & (seqs - 1)) == 0 && seqs * (N / 16) <= 1024 &&
+         seqs * reg_seq_lds(N) <= 160 * 1024;
 }
 
 FftPlan make_plan(int L) {
@@ -973,7 +983,7 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
 }
 
 void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds) {
-  ItemRange one = add_items(set, sel, [](const Img &) { return 1; });
+  ItemRange one = add_one_per_image(set, sel);
   p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0, set.st_base));
   ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
   for (int k = 0; k < rounds; ++k) {

@@ -111,3 +111,34 @@ def test_batch_rejects_single_image_calls():
         lam = torch.empty(1, device=DEV)
         u = torch.zeros(64 * 80, device=DEV)
         assert lib.discrepancy_lambda(g.handle, u.data_ptr(), lam.data_ptr(), None) == -5
+
+
+def test_autotune_keeps_state_and_results():
+    c = synth.make_case(1, size=(512, 512))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as ref:
+        u_ref, lam_ref = ref.iterate(5)
+        u_ref, lam_ref = u_ref.cpu().numpy(), lam_ref.cpu().numpy()
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+        choice = g.autotune(3)
+        print("autotune choice", choice)
+        assert g.info()["iterations"] == 0
+        u, lam = g.iterate(5)
+        u, lam = u.cpu().numpy(), lam.cpu().numpy()
+        with pytest.raises(gfd.GFDError):
+            g.autotune(3)              # iterations have run
+    e = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+    print(f"tuned vs default rel L2 {e:.2e}")
+    assert e < 1e-6 and np.allclose(lam, lam_ref, rtol=1e-5)
+
+
+def test_autotune_batch():
+    cases = synth.make_batch(4, sizes=SMALL_SIZES, config=19)
+    probs = problems(cases)
+    ref = single_runs(probs, [3])
+    with gfd.GFDeconvBatch(probs) as g:
+        g.autotune(2)
+        us, _ = g.iterate(3)
+        for b, (u_ref, _, _) in enumerate(ref):
+            e = float(np.linalg.norm(us[b].cpu().numpy() - u_ref) / np.linalg.norm(u_ref))
+            assert e < 1e-6, (b, e)
