@@ -41,118 +41,111 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const int nrows = TY + 4 * R;  // stream rows it = 0 .. nrows-1 are image rows y0 - 2R + it
   const int ybase = y0 - 2 * R;
 
-  // per stream row: (I, p) entering, (I, p) leaving the stage-1 window, guide I of the output row
-  struct RowIn {
-    float I, p, Io, po, Ig;
+  // Each thread keeps the mean-centred I and p of the last W stream rows of its column in a
+  // register ring (slot it % W), so the rows leaving the stage-1 windows and the guide value of
+  // the output row (stream row it - 2r, still in the ring) are never loaded twice.  The row loop
+  // is unrolled over 2W rows (W rounds of two), which makes every ring slot a compile-time index.
+  // Loads run one round ahead: a round first consumes the rows loaded during the previous round,
+  // then issues the next loads, and only then does its LDS work.
+  static_assert(kGfRB == 2, "rounds of two rows");
+  auto fetch = [&](int it, float &I, float &p) {
+    const size_t g = (size_t)wrap(ybase + min(it, nrows - 1), M) * N + gx;
+    I = uI[g];
+    p = uP[g];
   };
-  // Loads are issued unconditionally (rows clamped and wrapped, so every address is valid;
-  // unused values are discarded where they are consumed): with no branch around them the
-  // compiler can count the loads in flight and let the next round's loads overlap this
-  // round's arithmetic instead of draining the memory queue.
-  auto fetch = [&](int it) -> RowIn {
-    const int itc = min(it, nrows - 1);
-    RowIn v;
-    const size_t g = (size_t)wrap(ybase + itc, M) * N + gx;
-    v.I = uI[g];
-    v.p = uP[g];
-    const size_t go = (size_t)wrap(ybase + itc - W, M) * N + gx;
-    v.Io = uI[go];
-    v.po = uP[go];
-    v.Ig = uI[(size_t)wrap(ybase + itc - 2 * R, M) * N + gx];  // guide of the output row
-    return v;
-  };
-
   Kahan sI = {0, 0}, sP = {0, 0}, sII = {0, 0}, sIP = {0, 0}, sA = {0, 0}, sB = {0, 0};
-  // Software pipelining: each round first consumes the rows loaded during the previous round
-  // (the vertical updates, and a copy of the guide values), then issues the loads of the next
-  // round into the same registers, and only then does the rest of its work.  The wait for a
-  // round's loads thus comes a whole round after they were issued, with no newer loads in
-  // flight that it would have to drain.
-  RowIn cur[RB];
+  float rI[W], rP[W];
 #pragma unroll
-  for (int q = 0; q < RB; ++q) cur[q] = fetch(q);
-  for (int base = 0; base < nrows; base += RB) {
-    float Ig[RB];
+  for (int k = 0; k < W; ++k) rI[k] = rP[k] = 0.0f;
+  float nI[RB], nP[RB];
 #pragma unroll
-    for (int q = 0; q < RB; ++q) Ig[q] = cur[q].Ig;
-    // ---- stage 1, vertical
+  for (int q = 0; q < RB; ++q) fetch(q, nI[q], nP[q]);
+  for (int base0 = 0; base0 < nrows; base0 += RB * W) {
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      if (active && base + q < nrows) {
-        const float I = __fsub_rn(cur[q].I, cI), p = __fsub_rn(cur[q].p, cP);
-        const bool out = base + q >= W;
-        const float Io = out ? __fsub_rn(cur[q].Io, cI) : 0.0f, po = out ? __fsub_rn(cur[q].po, cP) : 0.0f;
-        kahan_slide(sI, I, Io);
-        kahan_slide(sP, p, po);
-        kahan_slide(sII, I * I, Io * Io);
-        kahan_slide(sIP, I * p, Io * po);
+    for (int r = 0; r < W; ++r) {
+      const int base = base0 + RB * r;
+      if (base >= nrows) break;  // uniform
+      float Ig[RB];
+      // ---- stage 1, vertical
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int s = (RB * r + q) % W, sg = (RB * r + q + 1) % W;
+        const float I = __fsub_rn(nI[q], cI), p = __fsub_rn(nP[q], cP);
+        const float Io = rI[s], po = rP[s];  // stream row it - W (zero while it < W)
+        rI[s] = I;
+        rP[s] = p;
+        Ig[q] = rI[sg];  // stream row it - 2r: the guide of this round's output row
         float *vb = vbuf + q * 4 * VP + R;
-        vb[j] = sI.s;
-        vb[VP + j] = sP.s;
-        vb[2 * VP + j] = sII.s;
-        vb[3 * VP + j] = sIP.s;
-      } else {
-        float *vb = vbuf + q * 4 * VP + R;
-        vb[j] = vb[VP + j] = vb[2 * VP + j] = vb[3 * VP + j] = 0.0f;
+        if (active && base + q < nrows) {
+          kahan_slide(sI, I, Io);
+          kahan_slide(sP, p, po);
+          kahan_slide(sII, I * I, Io * Io);
+          kahan_slide(sIP, I * p, Io * po);
+          vb[j] = sI.s;
+          vb[VP + j] = sP.s;
+          vb[2 * VP + j] = sII.s;
+          vb[3 * VP + j] = sIP.s;
+        } else {
+          vb[j] = vb[VP + j] = vb[2 * VP + j] = vb[3 * VP + j] = 0.0f;
+        }
       }
+#pragma unroll
+      for (int q = 0; q < RB; ++q) fetch(base + RB + q, nI[q], nP[q]);
+        __syncthreads();
+        if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
+        // ---- stage 1, horizontal: RB rows x 4 quantities
+#pragma unroll
+        for (int t = j; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+        __syncthreads();
+        // ---- a, b (Eqs. 3-4) and stage 2, vertical
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const int it = base + q;
+          const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
+          float *vb = vbuf + q * 2 * VP + R;
+          if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
+            const float *hb = hbuf + q * 4 * kGfThreads;
+            const float mu = hb[j] * inv_w2;
+            const float pb = hb[kGfThreads + j] * inv_w2;
+            const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * inv_w2), 0.0f);
+            const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * inv_w2);
+            const float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
+            const float b = __fmaf_rn(-a, mu, pb);
+            const int slot = (RB * r + q + 1) % W;  // it2 % W (base0 is a multiple of W)
+            float2 old = make_float2(0.0f, 0.0f);
+            if (it2 >= W) old = ringAB[slot * kGfThreads + j];
+            ringAB[slot * kGfThreads + j] = make_float2(a, b);
+            kahan_slide(sA, a, old.x);
+            kahan_slide(sB, b, old.y);
+            vb[j] = sA.s;
+            vb[VP + j] = sB.s;
+          } else {
+            // Columns without coefficients still enter the first window of a sliding run before
+            // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
+            vb[j] = 0.0f;
+            vb[VP + j] = 0.0f;
+          }
+        }
+        __syncthreads();
+        if (base + RB - 1 < 4 * R) continue;  // no complete stage-2 window yet (uniform)
+        // ---- stage 2, horizontal: RB rows x 2 quantities
+#pragma unroll
+        for (int t = j; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+        __syncthreads();
+        // ---- output rows
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const int it = base + q;
+          const int yo = ybase + it - 2 * R;  // output row
+          const int xo = x0 - 2 * R + j;      // output column
+          if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
+            const float *hb = hbuf + q * 2 * kGfThreads;
+            const float abar = hb[j] * inv_w2, bbar = hb[kGfThreads + j] * inv_w2;
+            u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
+          }
+        }
+      // the next round's first barrier orders these hbuf reads before hbuf is rewritten
     }
-#pragma unroll
-    for (int q = 0; q < RB; ++q) cur[q] = fetch(base + RB + q);
-    __syncthreads();
-    if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
-    // ---- stage 1, horizontal: RB rows x 4 quantities
-#pragma unroll
-    for (int t = j; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
-    __syncthreads();
-    // ---- a, b (Eqs. 3-4) and stage 2, vertical
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int it = base + q;
-      const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
-      float *vb = vbuf + q * 2 * VP + R;
-      if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
-        const float *hb = hbuf + q * 4 * kGfThreads;
-        const float mu = hb[j] * inv_w2;
-        const float pb = hb[kGfThreads + j] * inv_w2;
-        const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * inv_w2), 0.0f);
-        const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * inv_w2);
-        const float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
-        const float b = __fmaf_rn(-a, mu, pb);
-        const int slot = it2 % W;
-        float2 old = make_float2(0.0f, 0.0f);
-        if (it2 >= W) old = ringAB[slot * kGfThreads + j];
-        ringAB[slot * kGfThreads + j] = make_float2(a, b);
-        kahan_slide(sA, a, old.x);
-        kahan_slide(sB, b, old.y);
-        vb[j] = sA.s;
-        vb[VP + j] = sB.s;
-      } else {
-        // Columns without coefficients still enter the first window of a sliding run before
-        // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
-        vb[j] = 0.0f;
-        vb[VP + j] = 0.0f;
-      }
-    }
-    __syncthreads();
-    if (base + RB - 1 < 4 * R) continue;  // no complete stage-2 window yet (uniform)
-    // ---- stage 2, horizontal: RB rows x 2 quantities
-#pragma unroll
-    for (int t = j; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
-    __syncthreads();
-    // ---- output rows
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int it = base + q;
-      const int yo = ybase + it - 2 * R;  // output row
-      const int xo = x0 - 2 * R + j;      // output column
-      if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
-        const float *hb = hbuf + q * 2 * kGfThreads;
-        const float abar = hb[j] * inv_w2, bbar = hb[kGfThreads + j] * inv_w2;
-        const float I = __fsub_rn(Ig[q], cI);
-        u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, I, bbar), cP);
-      }
-    }
-    // the next round's first barrier orders these hbuf reads before hbuf is rewritten
   }
 }
 
