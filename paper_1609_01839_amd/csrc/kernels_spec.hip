@@ -430,19 +430,29 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
     const bool valid = active && k < lay.Wh;
     const float wgt = (k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f;
     if (active) {
+      // all loads first, stores last: no store between the loads that the compiler would have
+      // to order them against, so the 32 loads are in flight together
+      // (padding columns hold zeros in H and Y, so they are loaded like the others)
+      cf hv[16], yv[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int e = (t + T * m) * C + c;
+        hv[m] = G(d.H)[off + e];
+        yv[m] = G(d.Y)[off + e];
+      }
+      float qv[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const cf r = cmul(hv[m], v[m]) - yv[m];
+        const float qq = valid ? wgt * abs2f(r) : 0.0f;
+        qv[m] = qq;
+        first_round_terms<NC>(qq, abs2f(hv[m]), mu, acc);
+      }
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         const int e = (t + T * m) * C + c;
         tile[e] = v[m];
-        float qq = 0.0f, t2 = 0.0f;
-        if (valid) {
-          const cf h = G(d.H)[off + e], y = G(d.Y)[off + e];
-          const cf r = cmul(h, v[m]) - y;
-          qq = wgt * abs2f(r);
-          t2 = abs2f(h);
-        }
-        G(d.q)[off + e] = qq;
-        first_round_terms<NC>(qq, t2, mu, acc);
+        G(d.q)[off + e] = qv[m];
       }
     }
     float h, l;
@@ -466,21 +476,22 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   const int k = wi.blk * C + c;
   const bool valid = active && k < lay.Wh;
   const float dk = valid ? G(d.dN)[k] : 0.0f;
+  // all loads first (no store in between), then the solves
+  // no store inside the loop (the means are written after it), so the compiler may move the
+  // loads of later rows ahead of the arithmetic of earlier ones
   cf vp[16], vi[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int row = t + T * m;
+    const size_t e = off + (size_t)row * C + c;
     cf Up = {0.0f, 0.0f}, Ui = {0.0f, 0.0f};
-    if (valid) {
-      const int e = row * C + c;
-      solve_bin(sp, G(d.S1)[off + e], G(d.HY)[off + e], G(d.H2)[off + e], G(d.dM)[row] + dk, Up, Ui);
-      if (k == 0 && row == 0) {
-        d.st->meanP = Up.re;
-        d.st->meanI = Ui.re;
-      }
-    }
+    if (valid) solve_bin(sp, G(d.S1)[e], G(d.HY)[e], G(d.H2)[e], G(d.dM)[row] + dk, Up, Ui);
     vp[m] = Up;
     vi[m] = Ui;
+  }
+  if (valid && k == 0 && t == 0) {  // zero frequency (row 0, column 0): the means of u_p and u_I
+    d.st->meanP = vp[0].re;
+    d.st->meanI = vi[0].re;
   }
   reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
   if (active) {
