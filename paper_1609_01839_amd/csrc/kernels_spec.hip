@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <map>
 #include <tuple>
+#include <type_traits>
 
 #include "gfd_internal.h"
 
@@ -176,11 +177,14 @@ __device__ __forceinline__ SolveParams solve_params(const LamState *st) {
   s.mu = s.big ? 1.0f / s.lam : 0.0f;
   return s;
 }
-__device__ __forceinline__ void solve_bin(const SolveParams &sp, cf U, cf hy, float t2, float d2, cf &Up, cf &Ui) {
-  if (sp.inf_branch) {
+// MODE 0: lambda = +inf, 1: lambda >= 1 (written with mu = 1/lambda), 2: lambda < 1.
+template <int MODE>
+__device__ __forceinline__ void solve_bin_mode(const SolveParams &sp, cf U, cf hy, float t2, float d2, cf &Up,
+                                               cf &Ui) {
+  if constexpr (MODE == 0) {
     Up = cscale(U, sp.invP);
     Ui = Up;
-  } else if (sp.big) {
+  } else if constexpr (MODE == 1) {
     const float ip = sp.invP * __builtin_amdgcn_rcpf(__fmaf_rn(sp.mu, t2, 1.0f));
     const float ii = sp.invP * __builtin_amdgcn_rcpf(__fmaf_rn(sp.mu, t2, d2));
     Up = cf{(__fmaf_rn(sp.mu, hy.re, U.re)) * ip, (__fmaf_rn(sp.mu, hy.im, U.im)) * ip};
@@ -192,6 +196,12 @@ __device__ __forceinline__ void solve_bin(const SolveParams &sp, cf U, cf hy, fl
     Up = cf{__fmaf_rn(sp.lam, U.re, hy.re) * ip, __fmaf_rn(sp.lam, U.im, hy.im) * ip};
     Ui = cf{__fmaf_rn(ld, U.re, hy.re) * ii, __fmaf_rn(ld, U.im, hy.im) * ii};
   }
+}
+
+__device__ __forceinline__ void solve_bin(const SolveParams &sp, cf U, cf hy, float t2, float d2, cf &Up, cf &Ui) {
+  if (sp.inf_branch) solve_bin_mode<0>(sp, U, hy, t2, d2, Up, Ui);
+  else if (sp.big) solve_bin_mode<1>(sp, U, hy, t2, d2, Up, Ui);
+  else solve_bin_mode<2>(sp, U, hy, t2, d2, Up, Ui);
 }
 
 // ============================================================================ hot-path kernels, any length
@@ -477,17 +487,31 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   const bool valid = active && k < lay.Wh;
   const float dk = valid ? G(d.dN)[k] : 0.0f;
   // all loads first (no store in between), then the solves
-  // no store inside the loop (the means are written after it), so the compiler may move the
-  // loads of later rows ahead of the arithmetic of earlier ones
+  // Straight-line rows (the solve's case split is taken once, outside the loop; padding columns
+  // are computed and then zeroed; the means are written after the loop), so the compiler can
+  // issue the loads of later rows ahead of the arithmetic of earlier ones.
   cf vp[16], vi[16];
+  auto rows = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int row = t + T * m;
-    const size_t e = off + (size_t)row * C + c;
-    cf Up = {0.0f, 0.0f}, Ui = {0.0f, 0.0f};
-    if (valid) solve_bin(sp, G(d.S1)[e], G(d.HY)[e], G(d.H2)[e], G(d.dM)[row] + dk, Up, Ui);
-    vp[m] = Up;
-    vi[m] = Ui;
+    for (int m = 0; m < 16; ++m) {
+      const int row = t + T * m;
+      const size_t e = off + (size_t)row * C + c;
+      cf Up, Ui;
+      solve_bin_mode<MODE>(sp, G(d.S1)[e], G(d.HY)[e], G(d.H2)[e], G(d.dM)[row] + dk, Up, Ui);
+      vp[m] = valid ? Up : cf{0.0f, 0.0f};
+      vi[m] = valid ? Ui : cf{0.0f, 0.0f};
+    }
+  };
+  if (!active) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) vp[m] = vi[m] = cf{0.0f, 0.0f};
+  } else if (sp.inf_branch) {
+    rows(std::integral_constant<int, 0>{});
+  } else if (sp.big) {
+    rows(std::integral_constant<int, 1>{});
+  } else {
+    rows(std::integral_constant<int, 2>{});
   }
   if (valid && k == 0 && t == 0) {  // zero frequency (row 0, column 0): the means of u_p and u_I
     d.st->meanP = vp[0].re;
