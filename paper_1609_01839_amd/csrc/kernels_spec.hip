@@ -545,18 +545,24 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
   const int rowc = row < M ? row : M - 1;  // rows past the end compute a copy, never stored
   cf v[16];
   if (active) {
+    // every load of the row first, then the combination (keeps the 32 loads in flight together)
+    cf A[16], B[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int n = t + T * m;
+      const int kk = n < Wh ? n : N - n;
+      const size_t g = (size_t)rowc * lay.RP + kk;
+      A[m] = G(d.SI)[g];
+      B[m] = G(d.SP)[g];
+    }
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int n = t + T * m;
       const bool direct = n < Wh;
       const int kk = direct ? n : N - n;
-      const size_t g = (size_t)rowc * lay.RP + kk;
-      cf A = G(d.SI)[g], B = G(d.SP)[g];
-      if (kk == 0 || 2 * kk == N) {
-        A.im = 0.0f;
-        B.im = 0.0f;
-      }
-      v[m] = direct ? cf{A.re - B.im, A.im + B.re} : cf{A.re + B.im, B.re - A.im};
+      const bool real_col = kk == 0 || 2 * kk == N;
+      const float ai = real_col ? 0.0f : A[m].im, bi = real_col ? 0.0f : B[m].im;
+      v[m] = direct ? cf{A[m].re - bi, ai + B[m].re} : cf{A[m].re + bi, B[m].re - ai};
     }
   }
   reg_fft<+1>(v, t, active, d.rn, lds + seq * LP, 1, G(d.twN));
