@@ -121,6 +121,7 @@ __device__ __forceinline__ void row_fwd_body(XP x, const Layout &lay, const FftP
   const int M = lay.M, N = lay.N, R = lay.R, LP = N + 1;
   const int npair = R >> 1;
   const int r0 = blk * R;
+#pragma unroll 8
   for (int e = threadIdx.x; e < npair * N; e += blockDim.x) {
     const int b = fdiv(e, lay.Ndiv), n = e - b * N;
     const int ra = r0 + 2 * b, rb = ra + 1;
@@ -154,6 +155,7 @@ template <class T, int E, class TP>
 __device__ __forceinline__ void col_fwd_load_fft(TP tile, const Layout &lay, const FftPlan &pm,
                                                  const GFD_AS1 cpx<T> *__restrict__ tw, cpx<T> *buf) {
   const int n = lay.M * lay.C;
+#pragma unroll 8
   for (int e = threadIdx.x; e < n; e += blockDim.x) buf[e] = tile[e];
   __syncthreads();
   lds_fft<T, E, -1, true>(buf, lay.C, lay.logC, lay.C, 1, pm, tw);
@@ -234,6 +236,17 @@ __global__ void __launch_bounds__(1024) k_col_fwd_g(const Img *__restrict__ D, c
   const int n = lay.M * lay.C, C = lay.C;
   const size_t off = (size_t)wi.blk * n;
   GFD_AS1 cf *tile = G(d.S1) + off;
+  // F(h) and F(y) of this thread's bins do not depend on the transform: their loads are issued
+  // first so that they travel while the column transform runs
+  cf hv[RESID ? E : 1], yv[RESID ? E : 1];
+  if (RESID) {
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int e = min((int)threadIdx.x + u * (int)blockDim.x, n - 1);
+      hv[u] = G(d.H)[off + e];
+      yv[u] = G(d.Y)[off + e];
+    }
+  }
   col_fwd_load_fft<float, E>(tile, lay, d.pm, G(d.twM), buf);
   if (!RESID) {
     for (int e = threadIdx.x; e < n; e += blockDim.x) tile[e] = buf[e];
@@ -248,19 +261,22 @@ __global__ void __launch_bounds__(1024) k_col_fwd_g(const Img *__restrict__ D, c
 #pragma unroll
     for (int a = 0; a < 2 + 2 * NC; ++a) acc[a] = 0.0f;
     const int kbase = wi.blk * C;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-      const cf U = buf[e];
-      tile[e] = U;
-      const int k = kbase + (e & (C - 1));
-      float qq = 0.0f, t2 = 0.0f;
-      if (k < lay.Wh) {
-        const cf h = G(d.H)[off + e], y = G(d.Y)[off + e];
-        const cf r = cmul(h, U) - y;
-        qq = ((k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f) * abs2f(r);
-        t2 = abs2f(h);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int e = threadIdx.x + u * blockDim.x;
+      if (e < n) {
+        const cf U = buf[e];
+        tile[e] = U;
+        const int k = kbase + (e & (C - 1));
+        float qq = 0.0f, t2 = 0.0f;
+        if (k < lay.Wh) {  // padding columns hold zeros in H and Y
+          const cf r = cmul(hv[u], U) - yv[u];
+          qq = ((k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f) * abs2f(r);
+          t2 = abs2f(hv[u]);
+        }
+        G(d.q)[off + e] = qq;
+        first_round_terms<NC>(qq, t2, mu, acc);
       }
-      G(d.q)[off + e] = qq;
-      first_round_terms<NC>(qq, t2, mu, acc);
     }
     float h, l;
     block_sum_plain_then_df<2 + 2 * NC>(acc, h, l, scratch);
@@ -279,23 +295,34 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   const size_t off = (size_t)wi.blk * n;
   const SolveParams sp = solve_params(d.st);
   const int kbase = wi.blk * C;
-  cf ui[E];
+  // straight-line elements (case split outside the loop, clamped indices, padding columns
+  // zeroed by a select, the means written afterwards) so that their loads issue together
+  cf ui[E], up[E];
+  auto elems = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int e = min((int)threadIdx.x + u * (int)blockDim.x, n - 1);
+      const int k = kbase + (e & (C - 1)), m = e >> lay.logC;
+      cf Up, Ui;
+      solve_bin_mode<MODE>(sp, G(d.S1)[off + e], G(d.HY)[off + e], G(d.H2)[off + e],
+                           G(d.dM)[m] + G(d.dN)[min(k, lay.Wh - 1)], Up, Ui);
+      const bool ok = k < lay.Wh;
+      up[u] = ok ? Up : cf{0.0f, 0.0f};
+      ui[u] = ok ? Ui : cf{0.0f, 0.0f};
+    }
+  };
+  if (sp.inf_branch) elems(std::integral_constant<int, 0>{});
+  else if (sp.big) elems(std::integral_constant<int, 1>{});
+  else elems(std::integral_constant<int, 2>{});
+  if (threadIdx.x == 0 && wi.blk == 0) {  // zero frequency (row 0, column 0): the means
+    d.st->meanP = up[0].re;
+    d.st->meanI = ui[0].re;
+  }
 #pragma unroll
   for (int u = 0; u < E; ++u) {
     const int e = threadIdx.x + u * blockDim.x;
-    if (e < n) {
-      const int k = kbase + (e & (C - 1)), m = e >> lay.logC;
-      cf Up = {0.0f, 0.0f}, Ui = {0.0f, 0.0f};
-      if (k < lay.Wh) {
-        solve_bin(sp, G(d.S1)[off + e], G(d.HY)[off + e], G(d.H2)[off + e], G(d.dM)[m] + G(d.dN)[k], Up, Ui);
-        if (k == 0 && m == 0) {  // zero frequency: the means of u_p and u_I
-          d.st->meanP = Up.re;
-          d.st->meanI = Ui.re;
-        }
-      }
-      buf[e] = Up;
-      ui[u] = Ui;
-    }
+    if (e < n) buf[e] = up[u];
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
@@ -328,6 +355,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
     const int m = r0 + rho;
     if (m >= M) break;
     cf *z = buf + rho * LP;
+#pragma unroll 4
     for (int k = threadIdx.x; k < Wh; k += blockDim.x) {
       const size_t g = (size_t)m * lay.RP + k;
       cf A = G(d.SI)[g], B = G(d.SP)[g];
