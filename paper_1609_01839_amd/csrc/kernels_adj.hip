@@ -32,14 +32,16 @@ namespace gfd {
 
 // ============================================================================ box passes
 // Each stage loads NR raw values per pixel (load) and derives its NF summed fields from them
-// (fields); the two steps are apart so that loads can be issued a round ahead.
+// (fields).  Its epilogue receives, for the output pixel, the raw values (from the register ring)
+// and NE more values loaded a round ahead (eload).
 struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
-  static constexpr int NF = 4, NR = 2;
+  static constexpr int NF = 4, NR = 2, NE = 1;
   static constexpr bool kEps = false;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
     r[0] = G(d.uI)[g];
     r[1] = G(d.uP)[g];
   }
+  __device__ static void eload(const Img &, size_t, float (&e)[NE]) { e[0] = 0.0f; }
   __device__ static void fields(const float (&r)[NR], float cI, float cP, float (&v)[NF]) {
     const float I = __fsub_rn(r[0], cI), p = __fsub_rn(r[1], cP);
     v[0] = I;
@@ -47,7 +49,8 @@ struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
     v[2] = I * I;
     v[3] = I * p;
   }
-  __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], float, float, float &) {
+  __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], const float (&)[NR],
+                              const float (&)[NE], float, float, float &) {
     const float mu = B[0], pb = B[1];
     const float var = fmaxf(__fmaf_rn(-mu, mu, B[2]), 0.0f);
     const float cov = __fmaf_rn(-mu, pb, B[3]);
@@ -60,23 +63,29 @@ struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
 };
 
 struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c, g_u B(a)
-  static constexpr int NF = 3, NR = 3;
+  static constexpr int NF = 3, NR = 3, NE = 3;
   static constexpr bool kEps = true;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
     r[0] = G(d.ga)[g];
     r[1] = G(d.gu)[g];
     r[2] = G(d.uI)[g];
   }
+  __device__ static void eload(const Img &d, size_t g, float (&e)[NE]) {
+    e[0] = G(d.gmu)[g];
+    e[1] = G(d.gpb)[g];
+    e[2] = G(d.gve)[g];
+  }
   __device__ static void fields(const float (&r)[NR], float cI, float, float (&v)[NF]) {
     v[0] = r[0];
     v[1] = r[1] * __fsub_rn(r[2], cI);
     v[2] = r[1];
   }
-  // Pointwise reads of mu, pbar, v + eps at the emitted pixel come before the writes that
-  // replace them; no other pixel reads them.
-  __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], float, float, float &eacc) {
+  // mu, pbar and v + eps of the output pixel are read (a round ahead) before this epilogue
+  // replaces them; no other pixel reads them.
+  __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], const float (&r)[NR],
+                              const float (&e)[NE], float, float, float &eacc) {
     const float A = B[0], Ga = B[1], Gb = B[2];
-    const float a = G(d.ga)[g], mu = G(d.gmu)[g], pb = G(d.gpb)[g], ve = G(d.gve)[g];
+    const float a = r[0], gu = r[1], mu = e[0], pb = e[1], ve = e[2];
     float g_pbar = Gb;
     const float g_a = __fmaf_rn(-Gb, mu, Ga);
     float g_mu = -Gb * a;
@@ -89,12 +98,12 @@ struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c
     G(d.gpb)[g] = g_pbar;
     G(d.gve)[g] = g_v;
     G(d.gc)[g] = g_c;
-    G(d.gd)[g] = G(d.gu)[g] * A;
+    G(d.gd)[g] = gu * A;
   }
 };
 
 struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
-  static constexpr int NF = 4, NR = 4;
+  static constexpr int NF = 4, NR = 4, NE = 3;
   static constexpr bool kEps = false;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
     r[0] = G(d.gmu)[g];
@@ -102,13 +111,19 @@ struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
     r[2] = G(d.gve)[g];
     r[3] = G(d.gpb)[g];
   }
+  __device__ static void eload(const Img &d, size_t g, float (&e)[NE]) {
+    e[0] = G(d.uI)[g];
+    e[1] = G(d.uP)[g];
+    e[2] = G(d.gd)[g];
+  }
   __device__ static void fields(const float (&r)[NR], float, float, float (&v)[NF]) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) v[f] = r[f];
   }
-  __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], float cI, float cP, float &) {
-    const float I = __fsub_rn(G(d.uI)[g], cI), p = __fsub_rn(G(d.uP)[g], cP);
-    G(d.gI)[g] = G(d.gd)[g] + B[0] + p * B[1] + 2.0f * I * B[2];
+  __device__ static void emit(const Img &d, size_t g, const float (&B)[NF], const float (&)[NR],
+                              const float (&e)[NE], float cI, float cP, float &) {
+    const float I = __fsub_rn(e[0], cI), p = __fsub_rn(e[1], cP);
+    G(d.gI)[g] = e[2] + B[0] + p * B[1] + 2.0f * I * B[2];
     G(d.gP)[g] = __fmaf_rn(I, B[1], B[3]);
   }
 };
@@ -144,63 +159,80 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
 #pragma unroll
     for (int f = 0; f < NF; ++f) s[f] = Kahan{0.0f, 0.0f};
     float eacc = 0.0f;
-    constexpr int NR = Op::NR;
-    // raw values of the rows entering and leaving the windows, loaded one round ahead; every
-    // load is unconditional (wrapped, clamped rows) so that the compiler can keep the next
-    // round's loads in flight while this round is summed
-    float cn[RB][NR], co[RB][NR], nn[RB][NR], no[RB][NR];
-    auto fetch = [&](int it, float (&rn)[NR], float (&ro)[NR]) {
+    constexpr int NR = Op::NR, NE = Op::NE;
+    // Register ring of the raw values of the last Wn stream rows (slot it % Wn; the row loop is
+    // unrolled over RB * Wn rows so that slots are compile-time indices): rows leaving the
+    // windows are never loaded twice.  Loads run one round ahead: each round consumes the values
+    // loaded during the previous round before it issues the next loads.  The epilogue operands
+    // of the output row (stream row it - r) come from the ring and from NE loads, also issued a
+    // round ahead.
+    static_assert(RB == 2, "rounds of two rows");
+    float ring[Wn][NR];
+#pragma unroll
+    for (int k = 0; k < Wn; ++k)
+#pragma unroll
+      for (int x = 0; x < NR; ++x) ring[k][x] = 0.0f;
+    float nr[RB][NR], ne[RB][NE];
+    auto fetch = [&](int it, float (&rn)[NR], float (&en)[NE]) {
       const int itc = min(it, nrows - 1);
       Op::load(d, (size_t)wrap(ybase + itc, M) * N + gx, rn);
-      Op::load(d, (size_t)wrap(ybase + itc - Wn, M) * N + gx, ro);
+      // epilogue row: image row ybase + it - R, clamped into the strip's output rows
+      const int ye = min(max(ybase + itc - R, y0), min(y0 + TY, M) - 1);
+      const int xe = min(x0 - R + j, N - 1);
+      Op::eload(d, (size_t)ye * N + max(xe, 0), en);
     };
 #pragma unroll
-    for (int q = 0; q < RB; ++q) fetch(q, nn[q], no[q]);
-    for (int base = 0; base < nrows; base += RB) {
+    for (int q = 0; q < RB; ++q) fetch(q, nr[q], ne[q]);
+    for (int base0 = 0; base0 < nrows; base0 += RB * Wn) {
 #pragma unroll
-      for (int q = 0; q < RB; ++q) {
+      for (int rr = 0; rr < Wn; ++rr) {
+        const int base = base0 + RB * rr;
+        if (base >= nrows) break;  // uniform
+        float er[RB][NR], ee[RB][NE];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          cn[q][r] = nn[q][r];
-          co[q][r] = no[q][r];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < RB; ++q) fetch(base + RB + q, nn[q], no[q]);
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int it = base + q;
-        float *vb = vbuf + q * NF * VP + R;
-        if (active && it < nrows) {
+        for (int q = 0; q < RB; ++q) {
+          const int it = base + q;
+          const int sl = (RB * rr + q) % Wn, so = (RB * rr + q + Wn - R) % Wn;
           float vn[NF], vo[NF];
-          Op::fields(cn[q], cI, cP, vn);
-          Op::fields(co[q], cI, cP, vo);
+          Op::fields(nr[q], cI, cP, vn);
+          Op::fields(ring[sl], cI, cP, vo);  // stream row it - Wn (zeros while it < Wn)
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            kahan_slide(s[f], vn[f], it >= Wn ? vo[f] : 0.0f);
-            vb[f * VP + j] = s[f].s;
+          for (int x = 0; x < NR; ++x) ring[sl][x] = nr[q][x];
+#pragma unroll
+          for (int x = 0; x < NR; ++x) er[q][x] = ring[so][x];  // the output row's raw values
+#pragma unroll
+          for (int x = 0; x < NE; ++x) ee[q][x] = ne[q][x];
+          float *vb = vbuf + q * NF * VP + R;
+          if (active && it < nrows) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+              kahan_slide(s[f], vn[f], it >= Wn ? vo[f] : 0.0f);
+              vb[f * VP + j] = s[f].s;
+            }
+          } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) vb[f * VP + j] = 0.0f;
           }
-        } else {
-#pragma unroll
-          for (int f = 0; f < NF; ++f) vb[f * VP + j] = 0.0f;
         }
-      }
-      __syncthreads();
-      if (base + RB - 1 < Wn - 1) continue;  // no complete window in this round (uniform)
-      for (int t = j; t < RB * NF * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
-      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const int it = base + q;
-        const int y = ybase + it - R, x = x0 - R + j;
-        if (it < nrows && it >= 2 * R && j >= R && j < TX + R && x < N && y < M && y < y0 + TY) {
-          float B[NF];
+        for (int q = 0; q < RB; ++q) fetch(base + RB + q, nr[q], ne[q]);
+        __syncthreads();
+        if (base + RB - 1 < Wn - 1) continue;  // no complete window in this round (uniform)
+        for (int t = j; t < RB * NF * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+        __syncthreads();
 #pragma unroll
-          for (int f = 0; f < NF; ++f) B[f] = hbuf[(q * NF + f) * kGfThreads + j] * inv_w2;
-          Op::emit(d, (size_t)y * N + x, B, cI, cP, eacc);
+        for (int q = 0; q < RB; ++q) {
+          const int it = base + q;
+          const int y = ybase + it - R, x = x0 - R + j;
+          if (it < nrows && it >= 2 * R && j >= R && j < TX + R && x < N && y < M && y < y0 + TY) {
+            float B[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) B[f] = hbuf[(q * NF + f) * kGfThreads + j] * inv_w2;
+            Op::emit(d, (size_t)y * N + x, B, er[q], ee[q], cI, cP, eacc);
+          }
         }
+        // the next round's first barrier orders these hbuf reads before hbuf is rewritten
       }
-      // the next round's first barrier orders these hbuf reads before hbuf is rewritten
     }
     if (Op::kEps) {
 #pragma unroll
