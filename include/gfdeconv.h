@@ -199,7 +199,7 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
  *   checkpoint_every the forward iterations are replayed from their logged lambdas; every
  *                    c-th pre-estimate is kept and each segment of c iterations is recomputed
  *                    before it is differentiated (0 selects c = 5).  Memory: about
- *                    (K / c + c + 16) images per image.  The result does not depend on c.
+ *                    (K / c + 3 c + 16) images per image.  The result does not depend on c.
  * Stream-ordered; allocates device memory on first use.  The context's own estimate, search
  * state and histories are left unchanged.
  */

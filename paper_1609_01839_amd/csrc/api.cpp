@@ -74,7 +74,13 @@ struct Bwd {
   AdjState *ad = nullptr;
   std::vector<float *> uR, gu;
   std::vector<std::vector<float *>> ck;  // per image, checkpoint slots
-  std::vector<std::vector<float *>> seg; // per image, pre-estimates of one segment
+  // per image and segment position: what the adjoint of that iteration reads from its forward
+  // pass (u_I, u_p, U_E and the filter's centring constants), kept while the segment is replayed
+  struct Slot {
+    float *uI = nullptr, *uP = nullptr, *means = nullptr;
+    cf *S1 = nullptr;
+  };
+  std::vector<std::vector<Slot>> seg;
   std::vector<void *> allocs;
   int hist_cap = 0;
 };
@@ -653,19 +659,46 @@ static hipError_t bwd_slots(gfd_ctx *c, int nck, int seg) {
   b->seg.resize(c->count);
   hipError_t e = hipSuccess;
   for (int i = 0; i < c->count && e == hipSuccess; ++i) {
-    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N, nb = c->main.imgs[i].L.bins();
     while ((int)b->ck[i].size() < nck && e == hipSuccess) {
       float *p = nullptr;
       e = balloc(b, &p, P);
       b->ck[i].push_back(p);
     }
     while ((int)b->seg[i].size() < seg && e == hipSuccess) {
-      float *p = nullptr;
-      e = balloc(b, &p, P);
-      b->seg[i].push_back(p);
+      Bwd::Slot sl;
+      e = balloc(b, &sl.uI, P);
+      if (e == hipSuccess) e = balloc(b, &sl.uP, P);
+      if (e == hipSuccess) e = balloc(b, &sl.S1, nb);
+      if (e == hipSuccess) e = balloc(b, &sl.means, 2);
+      b->seg[i].push_back(sl);
     }
   }
   return e;
+}
+
+// Save (dir = +1) or restore (dir = -1) what the adjoint of one iteration needs from its forward
+// pass: u_I, u_p, U_E and the centring constants of every image.
+static hipError_t seg_copy(gfd_ctx *c, int pos, int dir, hipStream_t s) {
+  Bwd *b = c->bwd;
+  for (int i = 0; i < c->count; ++i) {
+    const Img &d = b->bwd.imgs[i];
+    const Bwd::Slot &sl = b->seg[i][pos];
+    const size_t P = (size_t)c->meta[i].M * c->meta[i].N, nb = d.L.bins();
+    float *means = (float *)((char *)(b->st + i) + offsetof(LamState, meanI));
+    static_assert(offsetof(LamState, meanP) == offsetof(LamState, meanI) + sizeof(float), "adjacent means");
+    struct {
+      void *dev, *slot;
+      size_t bytes;
+    } parts[] = {{d.uI, sl.uI, P * sizeof(float)}, {d.uP, sl.uP, P * sizeof(float)},
+                 {d.S1, sl.S1, nb * sizeof(cf)}, {means, sl.means, 2 * sizeof(float)}};
+    for (auto &x : parts) {
+      hipError_t e = dir > 0 ? hipMemcpyAsync(x.slot, x.dev, x.bytes, hipMemcpyDeviceToDevice, s)
+                             : hipMemcpyAsync(x.dev, x.slot, x.bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 static hipError_t copy_images(gfd_ctx *c, const std::vector<float *> &dst, const std::vector<float *> &src,
@@ -694,10 +727,11 @@ static hipError_t replay(Bwd *b, int k, bool filter, hipStream_t s) {
   return e;
 }
 
-// Adjoint of iteration k; gu holds the gradient with respect to its output on entry and
-// with respect to its pre-estimate on exit.
+// Adjoint of iteration k, whose forward quantities (u_I, u_p, U_E, centring constants) are in
+// place; gu holds the gradient with respect to its output on entry and with respect to its
+// pre-estimate on exit.
 static hipError_t adjoint_step(Bwd *b, int k, hipStream_t s) {
-  hipError_t e = replay(b, k, false, s);
+  hipError_t e = launch_lam_replay(b->bwd, b->one, k, s);
   for (int st = 0; st < 3 && e == hipSuccess; ++st) e = b->box[st].enqueue(s);
   if (e == hipSuccess) e = b->grad_fft.enqueue(s);
   if (e == hipSuccess) e = b->spec.enqueue(s);
@@ -1074,12 +1108,13 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
   for (int j = nck - 1; j >= 0; --j) {
     const int a = j * c, z = std::min(a + c, K);
     if (j != nck - 1) HIPCHK(copy_images(ctx, b->uR, slot(b->ck, j), s));
-    for (int k = a; k < z; ++k) {
-      HIPCHK(copy_images(ctx, slot(b->seg, k - a), b->uR, s));
-      if (k + 1 < z) HIPCHK(replay(b, k0 + k, true, s));
+    for (int k = a; k < z; ++k) {  // forward over the segment, keeping what the adjoint reads
+      HIPCHK(replay(b, k0 + k, false, s));
+      HIPCHK(seg_copy(ctx, k - a, +1, s));
+      if (k + 1 < z) HIPCHK(b->gf.enqueue(s));
     }
     for (int k = z - 1; k >= a; --k) {
-      HIPCHK(copy_images(ctx, b->uR, slot(b->seg, k - a), s));
+      HIPCHK(seg_copy(ctx, k - a, -1, s));
       HIPCHK(adjoint_step(b, k0 + k, s));
     }
   }
