@@ -23,7 +23,7 @@ independent float64 autograd of the same forward.
 """
 from .gfd import (  # noqa: F401
     dft2, idft2, embed_psf, grad_symbol, rho_eq12, Setup, setup, residual_energy,
-    discrepancy_lambda, spectral_solve, box_mean, guided_filter, StepResult, step,
+    discrepancy_lambda, spectral_solve, box_mean, guided_filter, guided_filter_color, StepResult, step,
     deconvolve, isnr, FLAG_INF_BRANCH, FLAG_NO_ROOT,
 )
 from . import adjoint  # noqa: F401,E402

@@ -220,6 +220,31 @@ def guided_filter(uI, up, w, eps):
     return box_mean(a, w) * uI + box_mean(b, w)
 
 
+def guided_filter_color(I3, up, w, eps):
+    """Guided filter with a three-channel guide (the colour case of Sec. 3.1's complexity remark).
+
+    Reading: the paper states that the filter has an exact linear-time algorithm for colour
+    guidance images without writing it out; the multichannel generalisation of Eqs. (3)-(5) is
+    taken: per window k, with the guide's channel means mu_k (3-vector) and window covariance
+    Sigma_k (3x3, population), a_k = (Sigma_k + eps U)^-1 (mean(I p) - mu_k pbar_k),
+    b_k = pbar_k - a_k . mu_k, and u(i) = abar_i . I(i) + bbar_i.  Each 3x3 system is solved by
+    numpy.linalg.solve.
+    """
+    I3 = np.asarray(I3, dtype=np.float64)
+    p = np.asarray(up, dtype=np.float64)
+    mu = np.stack([box_mean(I3[c], w) for c in range(3)])
+    pbar = box_mean(p, w)
+    S = np.empty(p.shape + (3, 3))
+    for c in range(3):
+        for d in range(3):
+            S[..., c, d] = box_mean(I3[c] * I3[d], w) - mu[c] * mu[d]
+    S = S + eps * np.eye(3)
+    cov = np.stack([box_mean(I3[c] * p, w) - mu[c] * pbar for c in range(3)], axis=-1)
+    a = np.linalg.solve(S, cov[..., None])[..., 0]            # M x N x 3
+    b = pbar - np.sum(a * np.moveaxis(mu, 0, -1), axis=-1)
+    return sum(box_mean(a[..., c], w) * I3[c] for c in range(3)) + box_mean(b, w)
+
+
 # ----------------------------------------------------------------------------- iteration
 
 @dataclasses.dataclass
