@@ -119,6 +119,19 @@ gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int 
                          void *stream);
 
 /*
+ * guided_filter_color -- the guided filter with a three-channel guide, the colour case of the
+ * Sec. 3.1 complexity remark, taken as the multichannel form of Eqs.(3)-(5): per window,
+ * a = (Sigma + eps U)^-1 (mean(I p) - mu pbar) with Sigma the guide's 3 x 3 window covariance
+ * and U the identity, b = pbar - a . mu, and u = mean(a) . I + mean(b); context-free.
+ *   I3 (guidance): device 3 x M x N float32, channel planes one after the other;
+ *   up (filtering input) and u (output): device M x N float32; u must not alias I3 or up.
+ *   Windows, w, M and N as for guided_filter; eps > 0 and finite.  The 3 x 3 systems are
+ *   solved in FP64, everything else in FP32.
+ */
+gfd_status guided_filter_color(const float *I3, const float *up, float *u, int M, int N, int w, float eps,
+                               void *stream);
+
+/*
  * spectral_solve -- the two regularised least-squares solves, Eqs.(8)-(9), for a given
  * pre-estimate and lambda, using the context's F(h), F(y) and gradient symbol.
  *   uE device M x N (input), uI and up device M x N (outputs: gradient- and identity-

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "spectral_solve", "discrepancy_lambda",
+__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
            "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -35,6 +35,7 @@ EXPORTS = {
     "deconv_image_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "deconv_iterate": (_i, [_vp, _i, _vp, _vp, _vp]),
     "guided_filter": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
+    "guided_filter_color": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
     "spectral_solve": (_i, [_vp, _vp, _f, _vp, _vp, _vp]),
     "discrepancy_lambda": (_i, [_vp, _vp, _vp, _vp]),
     "deconv_set_scales": (_i, [_vp, _vp, _i]),
@@ -345,6 +346,17 @@ def guided_filter(uI: torch.Tensor, up: torch.Tensor, w: int, eps: float, out: t
     out = torch.empty_like(uI) if out is None else out
     _check(load_library().guided_filter(_dev(uI, "uI"), _dev(up, "up", (M, N)), _dev(out, "out", (M, N)), M, N,
                                         int(w), float(eps), _stream(uI.device)))
+    return out
+
+
+def guided_filter_color(I3: torch.Tensor, up: torch.Tensor, w: int, eps: float, out: torch.Tensor | None = None):
+    """Guided filter with a (3, M, N) colour guide: per window (Sigma + eps U)^-1 in place of 1 / (var + eps)."""
+    if I3.dim() != 3 or int(I3.shape[0]) != 3:
+        raise GFDError(f"I3 must have shape (3, M, N), got {tuple(I3.shape)}")
+    M, N = (int(s) for s in I3.shape[1:])
+    out = torch.empty_like(up) if out is None else out
+    _check(load_library().guided_filter_color(_dev(I3, "I3", (3, M, N)), _dev(up, "up", (M, N)),
+                                              _dev(out, "out", (M, N)), M, N, int(w), float(eps), _stream(up.device)))
     return out
 
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgfdeconv.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["kernels_spec.hip", "kernels_gf.hip", "kernels_adj.hip", "api.cpp"]
+SOURCES = ["kernels_spec.hip", "kernels_gf.hip", "kernels_gfc.hip", "kernels_adj.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -844,6 +844,22 @@ gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int 
   return GFD_OK;
 }
 
+gfd_status guided_filter_color(const float *I3, const float *up, float *u, int M, int N, int w, float eps,
+                               void *stream) {
+  g_err.clear();
+  if (!I3 || !up || !u) return fail(GFD_ERR_ARG, "I3, up and u must be device pointers");
+  if (M < 1 || N < 1 || M > 65536 || N > 65536) return fail(GFD_ERR_SIZE, "M=%d, N=%d out of [1, 65536]", M, N);
+  if (w < 1 || w % 2 == 0 || w > M || w > N) return fail(GFD_ERR_ARG, "w=%d must be odd, 1 <= w <= min(M, N)", w);
+  if (!(eps > 0.0f) || !isfinite(eps)) return fail(GFD_ERR_ARG, "eps must be finite and > 0");
+  const size_t bytes = (size_t)M * N * sizeof(float);
+  const char *pu = (const char *)u, *pi = (const char *)I3, *pp = (const char *)up;
+  if ((pu < pi + 3 * bytes && pi < pu + bytes) || (pu < pp + bytes && pp < pu + bytes))
+    return fail(GFD_ERR_ARG, "u must not overlap I3 or up");
+  if (!guided_filter_supported(w)) return fail(GFD_ERR_UNIMPLEMENTED, "w=%d: windows wider than 17 are not built", w);
+  HIPCHK(launch_guided_filter_color(I3, up, u, M, N, w, eps, (hipStream_t)stream));
+  return GFD_OK;
+}
+
 gfd_status spectral_solve(gfd_ctx *ctx, const float *uE, float lambda, float *uI, float *up, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");

@@ -201,6 +201,8 @@ hipError_t launch_adj_out(ImgSet &set, ItemRange one, int K, int k0, float *geps
 // Stand-alone guided filter on caller-provided images (context-free).
 hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
                                       hipStream_t s);
+hipError_t launch_guided_filter_color(const float *I3, const float *up, float *u, int M, int N, int w, float eps,
+                                      hipStream_t s);
 
 // Per-image set-up (FP64 transforms of h and y, constants, rho and the target).
 hipError_t launch_embed_psf(const float *h, int kh, int kw, int M, int N, double *hp, hipStream_t st);

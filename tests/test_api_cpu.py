@@ -68,6 +68,21 @@ def test_guided_filter_argument_checks():
     assert lib.guided_filter(a, b, ctypes.c_void_p(0x10000 + 64), 16, 16, 3, 1.0, None) == -1  # u overlaps uI
 
 
+def test_guided_filter_color_argument_checks():
+    lib = gfd.load_library()
+    a, b, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    assert lib.guided_filter_color(None, b, c, 16, 16, 3, 1.0, None) == -1
+    assert lib.guided_filter_color(a, b, c, 16, 16, 4, 1.0, None) == -1
+    assert lib.guided_filter_color(a, b, c, 16, 16, 17, 1.0, None) == -1
+    assert lib.guided_filter_color(a, b, c, 16, 0, 1, 1.0, None) == -2
+    assert lib.guided_filter_color(a, b, c, 16, 16, 3, 0.0, None) == -1
+    assert lib.guided_filter_color(a, b, c, 64, 64, 19, 1.0, None) == -6
+    # u inside the third channel plane of I3 (planes of 16 * 16 floats)
+    assert lib.guided_filter_color(a, b, ctypes.c_void_p(0x100000 + 2 * 1024 + 8), 16, 16, 3, 1.0, None) == -1
+    assert lib.guided_filter_color(a, b, ctypes.c_void_p(0x200000 - 4), 16, 16, 3, 1.0, None) == -1  # overlaps up
+    assert lib.gfd_last_error()
+
+
 def test_foreign_and_null_contexts():
     lib = gfd.load_library()
     bogus = ctypes.c_void_p(0xDEAD0)
