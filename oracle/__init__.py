@@ -13,7 +13,9 @@ discretised gradient, Parseval normalisation, the lambda bracket, the tie at the
 infinite-lambda branch, ...) are stated next to the code that takes them.
 
 The hand-written reverse mode of the unrolled iteration (gradients with respect to
-eps and the per-iteration lambda scales) is in ``oracle.adjoint``.
+eps and the per-iteration lambda scales) is in ``oracle.adjoint``; the boundary variants
+(clipped guided-filter windows, padded non-circular observations) and their reverse mode
+are in ``oracle.boundary``.
 
 Parity status: every function here is pinned by CPU tests against closed forms,
 brute force or invariants, except the multi-iteration trajectory, which has no
@@ -27,3 +29,4 @@ from .gfd import (  # noqa: F401
     deconvolve, isnr, FLAG_INF_BRANCH, FLAG_NO_ROOT,
 )
 from . import adjoint  # noqa: F401,E402
+from . import boundary  # noqa: F401,E402

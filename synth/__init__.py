@@ -111,6 +111,20 @@ def blur_periodic(u: np.ndarray, h: np.ndarray) -> np.ndarray:
     return np.real(np.fft.ifft2(np.fft.fft2(u) * np.fft.fft2(hp)))
 
 
+def nonperiodic_case(M: int, N: int, h: np.ndarray, bsnr_db: float, seed: int, n_shapes: int = 12):
+    """A scene larger than the frame, blurred, then cropped: y (float32, M x N) is a blurred
+    view of u (M x N) whose blur reaches pixels outside the frame, i.e. not circular.
+    Returns (u, y, sigma2)."""
+    rng = np.random.default_rng(seed)
+    kh, kw = h.shape
+    mh, mw = kh, kw  # scene margin: at least the PSF's half-size on every side
+    scene = piecewise_image(M + 2 * mh, N + 2 * mw, rng, n_shapes=n_shapes)
+    b = blur_periodic(scene, h)[mh:mh + M, mw:mw + N]
+    sigma2 = sigma2_for_bsnr(b, bsnr_db)
+    y = (b + math.sqrt(sigma2) * rng.standard_normal((M, N))).astype(np.float32)
+    return scene[mh:mh + M, mw:mw + N].copy(), y, float(sigma2)
+
+
 def sigma2_for_bsnr(blurred: np.ndarray, bsnr_db: float) -> float:
     """Noise variance giving BSNR = 10 log10(var(h*u) / sigma^2) (population variance)."""
     return float(np.var(blurred) / (10.0 ** (bsnr_db / 10.0)))
