@@ -65,8 +65,29 @@ enum {
 gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float *h, int kh, int kw,
                        double sigma2, int w, float eps, double rho, void *stream);
 
+/* Boundary handling of an image (gfd_image.boundary, flags that combine). */
+enum {
+  GFD_BOUNDARY_PERIODIC = 0, /* the paper's model: circular blur, periodic filter windows */
+  GFD_BOUNDARY_CLIP = 1,     /* filter windows clipped to the image, means over the pixels inside */
+  GFD_BOUNDARY_PAD = 2       /* y is a non-circular blur: solved on a padded domain, then cropped */
+};
+
 /*
- * gfd_image -- one image of a batch: the arguments of deconv_init, same meaning and rules.
+ * gfd_image -- one image of a batch: the arguments of deconv_init, same meaning and rules,
+ * plus `boundary` (0 = GFD_BOUNDARY_PERIODIC gives exactly deconv_init's problem).  Both
+ * variants are readings for non-periodic images; the paper's solves (Eqs.(8)-(9)) assume a
+ * circular blur and its filter (Eqs.(3)-(5)) full windows.
+ *   GFD_BOUNDARY_CLIP: every window mean of the guided filter averages over the window's pixels
+ *     inside the (transform-domain) image and divides by their count; windows centred outside
+ *     do not exist.  The reverse mode uses the transposed means this implies.
+ *   GFD_BOUNDARY_PAD: y (M x N, any sizes in [2, 4096]) sits in the top-left corner of an
+ *     M' x N' domain, M' >= M + kh - 1 and N' >= N + kw - 1 the smallest 2^a 3^b 5^c sizes
+ *     (<= 4096), filled so that its periodic extension is continuous (each row ramps linearly
+ *     from its last value towards its first, then each column likewise).  rho of Eq.(12) is
+ *     computed from y, the target counts the observed pixels only (T = rho M N sigma^2), the
+ *     iteration runs on the domain, and the caller's arrays (u_out, deconv_set_estimate's uE,
+ *     deconv_backward's grad_u) stay M x N: estimates are cropped, a set estimate is extended
+ *     like y, a gradient by zeros.  spectral_solve and discrepancy_lambda work on the domain.
  */
 typedef struct gfd_image {
   const float *y; /* device, M x N */
@@ -77,6 +98,7 @@ typedef struct gfd_image {
   int w;
   float eps;
   double rho;
+  int boundary; /* GFD_BOUNDARY_* flags */
 } gfd_image;
 
 /*
@@ -99,6 +121,10 @@ gfd_status deconv_init_batch(gfd_ctx **out, const gfd_image *images, int count, 
 /* deconv_image_info -- size, rho and target rho*P*sigma^2 of image `index` of the context. */
 gfd_status deconv_image_info(gfd_ctx *ctx, int index, int *M, int *N, double *rho, double *target);
 
+/* deconv_image_domain -- transform-domain size (the padded size under GFD_BOUNDARY_PAD, else
+ * the image size) and boundary flags of image `index`; NULL outputs are skipped. */
+gfd_status deconv_image_domain(gfd_ctx *ctx, int index, int *M, int *N, int *boundary);
+
 /*
  * deconv_iterate -- run n_iter iterations of Steps 1-3 (Sec. 3.1) from the current estimate.
  *   u_out       device M x N or NULL: receives the estimate after the last iteration.
@@ -117,6 +143,15 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
  */
 gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
                          void *stream);
+
+/*
+ * guided_filter_clipped -- guided_filter with windows clipped to the image: every window mean of
+ * Eqs.(3)-(5) averages over the window's pixels inside the M x N image and divides by their
+ * count, and only windows centred inside the image carry coefficients (a boundary reading for
+ * non-periodic images; the paper's model is periodic).  Arguments and errors as guided_filter.
+ */
+gfd_status guided_filter_clipped(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
+                                 void *stream);
 
 /*
  * guided_filter_color -- the guided filter with a three-channel guide, the colour case of the

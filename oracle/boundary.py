@@ -174,12 +174,21 @@ def boundary_step(S, uE, w, eps, clip, scale=1.0):
     return u, uI, up, lam, lam_star, flags
 
 
+def start_estimate(S, shape, u0, pad):
+    """u_E^0: zeros, or u0 (y's shape) extended over the padding like y."""
+    if u0 is None:
+        return np.zeros((S.M, S.N))
+    u0 = np.asarray(u0, np.float64)
+    return pad_observation(u0, S.M, S.N) if pad else u0.copy()
+
+
 def deconvolve_boundary(y, h, sigma2, w, eps, iters, rho=None, clip=False, pad=False, scales=None,
-                        keep_iterates=False):
-    """The iteration from u_E = 0 with clipped filter windows and/or a padded observation.
-    Returns (u cropped to y's shape, info with the lambda history and the iterates, uncropped)."""
+                        keep_iterates=False, u0=None):
+    """The iteration from u_E = 0 (or u0) with clipped filter windows and/or a padded
+    observation.  Returns (u cropped to y's shape, info with the lambda history and the
+    iterates, uncropped)."""
     S, (M, N) = boundary_setup(y, h, sigma2, rho, pad)
-    uE = np.zeros((S.M, S.N))
+    uE = start_estimate(S, (M, N), u0, pad)
     lams, flags_all, iterates = [], [], []
     for k in range(iters):
         s = 1.0 if scales is None else float(scales[k])
@@ -193,13 +202,14 @@ def deconvolve_boundary(y, h, sigma2, w, eps, iters, rho=None, clip=False, pad=F
     return uE[:M, :N].copy(), info
 
 
-def deconvolve_boundary_adjoint(y, h, sigma2, w, eps, iters, g_u, rho=None, clip=False, pad=False, scales=None):
+def deconvolve_boundary_adjoint(y, h, sigma2, w, eps, iters, g_u, rho=None, clip=False, pad=False, scales=None,
+                                u0=None):
     """Gradient of a loss through deconvolve_boundary given g_u = dLoss/du (observed shape):
     returns (g_eps, g_scales).  The crop's adjoint extends g_u by zeros; T and rho do not depend
     on eps or the scales, so the solves' adjoint is that of the periodic iteration."""
     S, (M, N) = boundary_setup(y, h, sigma2, rho, pad)
     s = np.ones(iters) if scales is None else np.asarray(scales, np.float64)
-    pre = [np.zeros((S.M, S.N))]
+    pre = [start_estimate(S, (M, N), u0, pad)]
     steps = []
     for k in range(iters):
         r = boundary_step(S, pre[-1], w, eps, clip, float(s[k]))

@@ -16,7 +16,7 @@ import os
 
 import torch
 
-__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
+__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "guided_filter_clipped", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
            "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,6 +24,7 @@ _LIBNAME = "libgfdeconv.so"
 _lib = None
 
 FLAG_INF_BRANCH, FLAG_NO_ROOT, FLAG_NONFINITE = 1, 2, 4
+BOUNDARY_PERIODIC, BOUNDARY_CLIP, BOUNDARY_PAD = 0, 1, 2
 _ERRNAMES = {-1: "GFD_ERR_ARG", -2: "GFD_ERR_SIZE", -3: "GFD_ERR_HIP", -4: "GFD_ERR_NOMEM", -5: "GFD_ERR_STATE",
              -6: "GFD_ERR_UNIMPLEMENTED"}
 
@@ -33,9 +34,11 @@ EXPORTS = {
     "deconv_init": (_i, [ctypes.POINTER(_vp), _vp, _i, _i, _vp, _i, _i, _d, _i, _f, _d, _vp]),
     "deconv_init_batch": (_i, [ctypes.POINTER(_vp), _vp, _i, _vp]),
     "deconv_image_info": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "deconv_image_domain": (_i, [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "deconv_iterate": (_i, [_vp, _i, _vp, _vp, _vp]),
     "guided_filter": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
     "guided_filter_color": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
+    "guided_filter_clipped": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
     "spectral_solve": (_i, [_vp, _vp, _f, _vp, _vp, _vp]),
     "discrepancy_lambda": (_i, [_vp, _vp, _vp, _vp]),
     "deconv_set_scales": (_i, [_vp, _vp, _i]),
@@ -55,7 +58,7 @@ EXPORTS = {
 class GfdImage(ctypes.Structure):
     """``gfd_image`` of the C ABI: one image of a batch."""
     _fields_ = [("y", _vp), ("M", _i), ("N", _i), ("h", _vp), ("kh", _i), ("kw", _i), ("sigma2", _d), ("w", _i),
-                ("eps", _f), ("rho", _d)]
+                ("eps", _f), ("rho", _d), ("boundary", _i)]
 
 
 class GFDError(RuntimeError):
@@ -106,10 +109,13 @@ class GFDeconv:
 
     ``y`` (M x N) and ``h`` (kh x kw, odd sides) are float32 GPU tensors; ``sigma2`` the noise
     variance; ``w``, ``eps`` the guided-filter window and regulariser; ``rho=None`` takes
-    Eq.(12), otherwise 0 < rho <= 1.
+    Eq.(12), otherwise 0 < rho <= 1.  ``clip`` clips the guided filter's windows to the image;
+    ``pad`` treats y as a non-circular blur and solves on a padded domain (``domain``), returning
+    estimates of y's size (GFD_BOUNDARY_* of the C ABI).
     """
 
-    def __init__(self, y: torch.Tensor, h: torch.Tensor, sigma2: float, w: int, eps: float, rho=None):
+    def __init__(self, y: torch.Tensor, h: torch.Tensor, sigma2: float, w: int, eps: float, rho=None,
+                 clip: bool = False, pad: bool = False):
         lib = load_library()
         if y.dim() != 2 or h.dim() != 2:
             raise ValueError("y and h must be 2-D")
@@ -117,11 +123,24 @@ class GFDeconv:
         self.device = y.device
         self._y, self._h = y, h
         ctx = _vp()
-        rc = lib.deconv_init(ctypes.byref(ctx), _dev(y, "y"), self.M, self.N, _dev(h, "h"), int(h.shape[0]),
-                             int(h.shape[1]), float(sigma2), int(w), float(eps), -1.0 if rho is None else float(rho),
-                             _stream(self.device))
+        boundary = (BOUNDARY_CLIP if clip else 0) | (BOUNDARY_PAD if pad else 0)
+        if boundary == 0:
+            rc = lib.deconv_init(ctypes.byref(ctx), _dev(y, "y"), self.M, self.N, _dev(h, "h"), int(h.shape[0]),
+                                 int(h.shape[1]), float(sigma2), int(w), float(eps),
+                                 -1.0 if rho is None else float(rho), _stream(self.device))
+        else:
+            img = GfdImage(_dev(y, "y"), self.M, self.N, _dev(h, "h"), int(h.shape[0]), int(h.shape[1]),
+                           float(sigma2), int(w), float(eps), -1.0 if rho is None else float(rho), boundary)
+            rc = lib.deconv_init_batch(ctypes.byref(ctx), ctypes.byref(img), 1, _stream(self.device))
         _check(rc)
         self._ctx = ctx
+        self.domain = self._domain(0)
+
+    def _domain(self, b: int):
+        M, N, fl = _i(), _i(), _i()
+        _check(load_library().deconv_image_domain(self.handle, int(b), ctypes.byref(M), ctypes.byref(N),
+                                                  ctypes.byref(fl)))
+        return M.value, N.value
 
     # -- lifetime
     def close(self):
@@ -225,8 +244,8 @@ class GFDeconv:
 class GFDeconvBatch(GFDeconv):
     """Independent problems in one context: every pass of an iteration is one launch for all.
 
-    ``problems`` is a sequence of dicts with keys y, h, sigma2, w, eps and optionally rho (the
-    arguments of :class:`GFDeconv`).  Estimates are returned as a list of M_b x N_b views of
+    ``problems`` is a sequence of dicts with keys y, h, sigma2, w, eps and optionally rho, clip
+    and pad (the arguments of :class:`GFDeconv`).  Estimates are returned as a list of M_b x N_b views of
     one flat tensor, lambdas as a (count, n) tensor.
     """
 
@@ -244,8 +263,10 @@ class GFDeconvBatch(GFDeconv):
                 raise ValueError("y and h must be 2-D")
             M, N = (int(v) for v in y.shape)
             rho = pr.get("rho")
+            boundary = (BOUNDARY_CLIP if pr.get("clip") else 0) | (BOUNDARY_PAD if pr.get("pad") else 0)
             arr[b] = GfdImage(_dev(y, f"y[{b}]"), M, N, _dev(h, f"h[{b}]"), int(h.shape[0]), int(h.shape[1]),
-                              float(pr["sigma2"]), int(pr["w"]), float(pr["eps"]), -1.0 if rho is None else float(rho))
+                              float(pr["sigma2"]), int(pr["w"]), float(pr["eps"]), -1.0 if rho is None else float(rho),
+                              boundary)
             self._keep += [y, h]
             self.shapes.append((M, N))
         self.count = len(problems)
@@ -255,6 +276,7 @@ class GFDeconvBatch(GFDeconv):
         ctx = _vp()
         _check(lib.deconv_init_batch(ctypes.byref(ctx), ctypes.cast(arr, _vp), self.count, _stream(self.device)))
         self._ctx = ctx
+        self.domain = self._domain(0)
 
     def split(self, flat: torch.Tensor):
         out, off = [], 0
@@ -340,12 +362,15 @@ def deconvolve(y, h, sigma2, w, eps, iters, rho=None, scales=None):
         return g.iterate(iters)
 
 
-def guided_filter(uI: torch.Tensor, up: torch.Tensor, w: int, eps: float, out: torch.Tensor | None = None):
-    """u = guidfilter(u_I, u_p, w, eps) with periodic windows (Sec. 2, Eqs.(3)-(5))."""
+def guided_filter(uI: torch.Tensor, up: torch.Tensor, w: int, eps: float, out: torch.Tensor | None = None,
+                  clip: bool = False):
+    """u = guidfilter(u_I, u_p, w, eps) (Sec. 2, Eqs.(3)-(5)): periodic windows, or windows
+    clipped to the image with count-normalised means when ``clip``."""
     M, N = (int(s) for s in uI.shape)
     out = torch.empty_like(uI) if out is None else out
-    _check(load_library().guided_filter(_dev(uI, "uI"), _dev(up, "up", (M, N)), _dev(out, "out", (M, N)), M, N,
-                                        int(w), float(eps), _stream(uI.device)))
+    fn = load_library().guided_filter_clipped if clip else load_library().guided_filter
+    _check(fn(_dev(uI, "uI"), _dev(up, "up", (M, N)), _dev(out, "out", (M, N)), M, N, int(w), float(eps),
+              _stream(uI.device)))
     return out
 
 
@@ -362,9 +387,9 @@ def guided_filter_color(I3: torch.Tensor, up: torch.Tensor, w: int, eps: float, 
 
 def spectral_solve(g: GFDeconv, uE: torch.Tensor, lam: float):
     """(u_I, u_p) from Eqs.(8)-(9) for pre-estimate uE and a given lambda (+inf allowed)."""
-    uI = torch.empty((g.M, g.N), device=g.device, dtype=torch.float32)
+    uI = torch.empty(g.domain, device=g.device, dtype=torch.float32)
     up = torch.empty_like(uI)
-    _check(load_library().spectral_solve(g.handle, _dev(uE, "uE", (g.M, g.N)), float(lam), uI.data_ptr(),
+    _check(load_library().spectral_solve(g.handle, _dev(uE, "uE", g.domain), float(lam), uI.data_ptr(),
                                          up.data_ptr(), _stream(g.device)))
     return uI, up
 
@@ -372,6 +397,6 @@ def spectral_solve(g: GFDeconv, uE: torch.Tensor, lam: float):
 def discrepancy_lambda(g: GFDeconv, uE: torch.Tensor):
     """lambda_star for pre-estimate uE by the discrepancy principle (Sec. 3.2); 1-element GPU tensor."""
     lam = torch.empty((1,), device=g.device, dtype=torch.float32)
-    _check(load_library().discrepancy_lambda(g.handle, _dev(uE, "uE", (g.M, g.N)), lam.data_ptr(),
+    _check(load_library().discrepancy_lambda(g.handle, _dev(uE, "uE", g.domain), lam.data_ptr(),
                                              _stream(g.device)))
     return lam

@@ -29,7 +29,9 @@ static const int kMaxImages = 4096;
 static const int kStages = 6;
 
 struct ImgMeta {
-  int M, N, w;
+  int M, N, w;    // M x N: the transform domain (the padded size for a padded observation)
+  int Mo, No;     // the observed size (the caller's arrays)
+  int pad, clip;  // GFD_BOUNDARY_PAD / GFD_BOUNDARY_CLIP
   float eps;
   double sigma2, rho, T;
 };
@@ -121,6 +123,24 @@ static bool size_ok(int n) {
   for (int p : {2, 3, 5})
     while (n % p == 0) n /= p;
   return n == 1;
+}
+
+// The smallest m >= n whose only prime factors are 2, 3 and 5.
+static int good_size(int n) {
+  for (int m = std::max(n, 1);; ++m) {
+    int k = m;
+    for (int p : {2, 3, 5})
+      while (k % p == 0) k /= p;
+    if (k == 1) return m;
+  }
+}
+
+// Transform domain of an image: its own size, or the padded size (room for the PSF's support
+// on every side of a non-circular observation).
+static void domain_dims(const gfd_image &d, int &M, int &N) {
+  const bool pad = (d.boundary & GFD_BOUNDARY_PAD) != 0;
+  M = pad ? good_size(d.M + d.kh - 1) : d.M;
+  N = pad ? good_size(d.N + d.kw - 1) : d.N;
 }
 
 static bool live(gfd_ctx *c) {
@@ -231,8 +251,20 @@ static gfd_status capture_graph(gfd_ctx *c) {
 static gfd_status check_image(const gfd_image &d, int idx) {
   const int M = d.M, N = d.N;
   if (!d.y || !d.h) return fail(GFD_ERR_ARG, "image %d: y and h must be device pointers", idx);
-  if (!size_ok(M) || !size_ok(N))
+  if (d.boundary < 0 || d.boundary > (GFD_BOUNDARY_CLIP | GFD_BOUNDARY_PAD))
+    return fail(GFD_ERR_ARG, "image %d: unknown boundary flags %d", idx, d.boundary);
+  if (d.boundary & GFD_BOUNDARY_PAD) {
+    if (M < 2 || N < 2 || M > 4096 || N > 4096)
+      return fail(GFD_ERR_SIZE, "image %d: M=%d, N=%d out of [2, 4096]", idx, M, N);
+    if (d.kh >= 1 && d.kw >= 1 && d.kh <= M && d.kw <= N) {
+      int Md, Nd;
+      domain_dims(d, Md, Nd);
+      if (Md > 4096 || Nd > 4096)
+        return fail(GFD_ERR_SIZE, "image %d: padded domain %dx%d exceeds 4096", idx, Md, Nd);
+    }
+  } else if (!size_ok(M) || !size_ok(N)) {
     return fail(GFD_ERR_SIZE, "image %d: M=%d, N=%d: each must be 2^a 3^b 5^c in [2, 4096]", idx, M, N);
+  }
   if (d.kh < 1 || d.kw < 1 || d.kh % 2 == 0 || d.kw % 2 == 0 || d.kh > M || d.kw > N)
     return fail(GFD_ERR_SIZE, "image %d: PSF %dx%d: sides must be odd and at most the image sides", idx, d.kh, d.kw);
   if (!(d.sigma2 >= 0.0) || !isfinite(d.sigma2)) return fail(GFD_ERR_ARG, "image %d: sigma2 must be finite and >= 0", idx);
@@ -248,8 +280,10 @@ static gfd_status check_image(const gfd_image &d, int idx) {
 
 // Device buffers and FP64 set-up of image i (F(h), F(y), constants, rho and the target).
 static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream_t s, double *hp, cd *Hd, cd *Yd,
-                              double *work) {
-  const int M = src.M, N = src.N;
+                              double *work, float *ypad) {
+  const bool pad = (src.boundary & GFD_BOUNDARY_PAD) != 0;
+  int M, N;
+  domain_dims(src, M, N);
   Img d;
   memset(&d, 0, sizeof(d));
   d.L = make_layout(M, N);
@@ -259,6 +293,7 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   d.rn = make_reg_plan(reg_plan_ok(N) ? N : 256);
   d.w = src.w;
   d.eps = src.eps;
+  d.clip = (src.boundary & GFD_BOUNDARY_CLIP) ? 1 : 0;
   const Layout &L = d.L;
   const size_t P = (size_t)M * N, nb = L.bins();
   d.nchunk = lam_sweep_chunks(nb);
@@ -324,12 +359,18 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   if (e == hipSuccess) e = launch_embed_psf(src.h, src.kh, src.kw, M, N, hp, s);
   if (e == hipSuccess) e = launch_row_fwd_d(hp, L, d.pn, twNd, Hd, s);
   if (e == hipSuccess) e = launch_col_fwd_d(Hd, L, d.pm, twMd, s);
-  if (e == hipSuccess) e = launch_row_fwd_fd(src.y, L, d.pn, twNd, Yd, s);
+  const float *ydom = src.y;
+  if (pad) {
+    if (e == hipSuccess) e = launch_pad_ramp(src.y, src.M, src.N, ypad, M, N, s);
+    ydom = ypad;
+  }
+  if (e == hipSuccess) e = launch_row_fwd_fd(ydom, L, d.pn, twNd, Yd, s);
   if (e == hipSuccess) e = launch_col_fwd_d(Yd, L, d.pm, twMd, s);
   if (e == hipSuccess) e = launch_init_consts(Hd, Yd, L, H, Y, HY, H2, s);
   if (e == hipSuccess) e = launch_d2_tables(M, N, L.Wh, dM, dN, s);
   if (e == hipSuccess)
-    e = launch_rho_target(src.y, M, N, src.h, src.kh, src.kw, src.sigma2, src.rho, work, c->rho_out + 2 * i, d.st, s);
+    e = launch_rho_target(src.y, src.M, src.N, P, src.h, src.kh, src.kw, src.sigma2, src.rho, work, c->rho_out + 2 * i,
+                          d.st, s);
   if (e == hipSuccess) e = launch_state_reset(d.st, s);
   if (e == hipSuccess) e = launch_fill_f(uE, P, 0.0f, s);
   if (e == hipSuccess) e = launch_fill_f(u0, P, 0.0f, s);
@@ -340,6 +381,10 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   ImgMeta m;
   m.M = M;
   m.N = N;
+  m.Mo = src.M;
+  m.No = src.N;
+  m.pad = pad ? 1 : 0;
+  m.clip = d.clip;
   m.w = src.w;
   m.eps = src.eps;
   m.sigma2 = src.sigma2;
@@ -382,10 +427,13 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
   if (e != hipSuccess) return bail(e, "hipGetDevice");
   size_t maxP = 0, maxB = 0;
   for (int i = 0; i < count; ++i) {
-    maxP = std::max(maxP, (size_t)imgs[i].M * imgs[i].N);
-    maxB = std::max(maxB, make_layout(imgs[i].M, imgs[i].N).bins());
+    int Md, Nd;
+    domain_dims(imgs[i], Md, Nd);
+    maxP = std::max(maxP, (size_t)Md * Nd);
+    maxB = std::max(maxB, make_layout(Md, Nd).bins());
   }
   double *hp = nullptr, *work = nullptr;
+  float *ypad = nullptr;
   cd *Hd = nullptr, *Yd = nullptr;
   if (e == hipSuccess) e = dalloc(c, &c->st, count);
   c->main.st_base = c->st;
@@ -398,12 +446,13 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
   if (e == hipSuccess) e = dalloc(c, &work, 4 * 256);
   if (e == hipSuccess) e = dalloc(c, &Hd, maxB);
   if (e == hipSuccess) e = dalloc(c, &Yd, maxB);
+  if (e == hipSuccess) e = dalloc(c, &ypad, maxP);
   if (e == hipSuccess) e = launch_fill_f(c->scales, c->hist_cap, 1.0f, s);
   if (e != hipSuccess) return bail(e, "allocation failed");
-  for (int i = 0; i < count && e == hipSuccess; ++i) e = setup_image(c, i, imgs[i], s, hp, Hd, Yd, work);
+  for (int i = 0; i < count && e == hipSuccess; ++i) e = setup_image(c, i, imgs[i], s, hp, Hd, Yd, work, ypad);
   if (e != hipSuccess) return bail(e, "set-up failed");
   // the shared FP64 temporaries are no longer needed
-  for (void *p : {(void *)hp, (void *)work, (void *)Hd, (void *)Yd}) {
+  for (void *p : {(void *)hp, (void *)work, (void *)Hd, (void *)Yd, (void *)ypad}) {
     c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), p));
     (void)hipFree(p);
   }
@@ -498,11 +547,18 @@ static gfd_status grow_history(gfd_ctx *c, int need) {
   return GFD_OK;
 }
 
+// The estimates, images one after another at their observed sizes (a padded image's estimate is
+// cropped to its top-left M x N corner, where the observation sits).
 static gfd_status copy_estimates_out(gfd_ctx *c, float *u_out, hipStream_t s) {
   size_t off = 0;
   for (int i = 0; i < c->count; ++i) {
-    const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
-    HIPCHK(hipMemcpyAsync(u_out + off, c->main.imgs[i].uE, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    const ImgMeta &m = c->meta[i];
+    const size_t P = (size_t)m.Mo * m.No;
+    if (m.pad)
+      HIPCHK(hipMemcpy2DAsync(u_out + off, m.No * sizeof(float), c->main.imgs[i].uE, m.N * sizeof(float),
+                              m.No * sizeof(float), m.Mo, hipMemcpyDeviceToDevice, s));
+    else
+      HIPCHK(hipMemcpyAsync(u_out + off, c->main.imgs[i].uE, P * sizeof(float), hipMemcpyDeviceToDevice, s));
     off += P;
   }
   return GFD_OK;
@@ -760,6 +816,7 @@ gfd_status deconv_init(gfd_ctx **out, const float *y, int M, int N, const float 
   d.w = w;
   d.eps = eps;
   d.rho = rho;
+  d.boundary = GFD_BOUNDARY_PERIODIC;
   return init_common(out, &d, 1, (hipStream_t)stream);
 }
 
@@ -827,7 +884,8 @@ gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_
   return GFD_OK;
 }
 
-gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int N, int w, float eps, void *stream) {
+static gfd_status guided_filter_any(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
+                                    bool clip, void *stream) {
   g_err.clear();
   if (!uI || !up || !u) return fail(GFD_ERR_ARG, "uI, up and u must be device pointers");
   if (M < 1 || N < 1 || M > 65536 || N > 65536) return fail(GFD_ERR_SIZE, "M=%d, N=%d out of [1, 65536]", M, N);
@@ -840,8 +898,17 @@ gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int 
   };
   if (overlap(u, uI) || overlap(u, up)) return fail(GFD_ERR_ARG, "u must not overlap uI or up");
   if (!guided_filter_supported(w)) return fail(GFD_ERR_UNIMPLEMENTED, "w=%d: windows wider than 17 are not built", w);
-  HIPCHK(launch_guided_filter_plain(uI, up, u, M, N, w, eps, (hipStream_t)stream));
+  HIPCHK(launch_guided_filter_plain(uI, up, u, M, N, w, eps, clip, (hipStream_t)stream));
   return GFD_OK;
+}
+
+gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int N, int w, float eps, void *stream) {
+  return guided_filter_any(uI, up, u, M, N, w, eps, false, stream);
+}
+
+gfd_status guided_filter_clipped(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
+                                 void *stream) {
+  return guided_filter_any(uI, up, u, M, N, w, eps, true, stream);
 }
 
 gfd_status guided_filter_color(const float *I3, const float *up, float *u, int M, int N, int w, float eps,
@@ -914,9 +981,15 @@ gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   size_t off = 0;
   for (int i = 0; i < ctx->count; ++i) {
-    const size_t P = (size_t)ctx->meta[i].M * ctx->meta[i].N;
-    HIPCHK(hipMemcpyAsync(ctx->main.imgs[i].uE, uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(ctx->u0[i], uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    const ImgMeta &m = ctx->meta[i];
+    const size_t P = (size_t)m.Mo * m.No;
+    if (m.pad) {  // extended over the padding like the observation
+      HIPCHK(launch_pad_ramp(uE + off, m.Mo, m.No, ctx->main.imgs[i].uE, m.M, m.N, s));
+      HIPCHK(launch_pad_ramp(uE + off, m.Mo, m.No, ctx->u0[i], m.M, m.N, s));
+    } else {
+      HIPCHK(hipMemcpyAsync(ctx->main.imgs[i].uE, uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(ctx->u0[i], uE + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
     off += P;
   }
   HIPCHK(ctx->warm.enqueue(s));
@@ -953,10 +1026,21 @@ gfd_status deconv_image_info(gfd_ctx *ctx, int index, int *M, int *N, double *rh
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (index < 0 || index >= ctx->count) return fail(GFD_ERR_ARG, "index %d outside [0, %d)", index, ctx->count);
   const ImgMeta &m = ctx->meta[index];
-  if (M) *M = m.M;
-  if (N) *N = m.N;
+  if (M) *M = m.Mo;
+  if (N) *N = m.No;
   if (rho) *rho = m.rho;
   if (target) *target = m.T;
+  return GFD_OK;
+}
+
+gfd_status deconv_image_domain(gfd_ctx *ctx, int index, int *M, int *N, int *boundary) {
+  g_err.clear();
+  if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (index < 0 || index >= ctx->count) return fail(GFD_ERR_ARG, "index %d outside [0, %d)", index, ctx->count);
+  const ImgMeta &m = ctx->meta[index];
+  if (M) *M = m.M;
+  if (N) *N = m.N;
+  if (boundary) *boundary = (m.pad ? GFD_BOUNDARY_PAD : 0) | (m.clip ? GFD_BOUNDARY_CLIP : 0);
   return GFD_OK;
 }
 
@@ -1108,8 +1192,15 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
   // incoming gradient (images one after another) and a private copy of the search constants
   size_t off = 0;
   for (int i = 0; i < ctx->count; ++i) {
-    const size_t P = (size_t)ctx->meta[i].M * ctx->meta[i].N;
-    HIPCHK(hipMemcpyAsync(b->gu[i], grad_u + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    const ImgMeta &m = ctx->meta[i];
+    const size_t P = (size_t)m.Mo * m.No;
+    if (m.pad) {  // the crop's adjoint: zeros over the padding
+      HIPCHK(launch_fill_f(b->gu[i], (size_t)m.M * m.N, 0.0f, s));
+      HIPCHK(hipMemcpy2DAsync(b->gu[i], m.N * sizeof(float), grad_u + off, m.No * sizeof(float), m.No * sizeof(float),
+                              m.Mo, hipMemcpyDeviceToDevice, s));
+    } else {
+      HIPCHK(hipMemcpyAsync(b->gu[i], grad_u + off, P * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
     off += P;
   }
   HIPCHK(hipMemcpyAsync(b->st, ctx->st, ctx->count * sizeof(LamState), hipMemcpyDeviceToDevice, s));

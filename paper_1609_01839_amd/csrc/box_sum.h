@@ -24,6 +24,12 @@ __device__ __forceinline__ void kahan_slide(Kahan &k, float xn, float xo) {
   k.s = t;
 }
 
+// Pixels of the window of half-width R centred at c (a row or column index) inside [0, n).
+template <int R>
+__device__ __forceinline__ int clip_count(int c, int n) {
+  return min(c + R, n - 1) - max(c - R, 0) + 1;
+}
+
 __device__ __forceinline__ int wrap(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;

@@ -73,6 +73,7 @@ struct Img {
   int w;
   float eps;
   int gfTX, gfTY, gfNBY;  // guided-filter strip geometry
+  int clip;               // 1: filter windows clipped to the image (count-normalised means)
   float *lam_star_hist;   // lambda* of each iteration (before the scale)
   // reverse mode (set only in the backward descriptor sets; null otherwise)
   float *ga, *gmu, *gpb, *gve;  // stage 1 of the filter's adjoint: a, mean I, mean p, var + eps
@@ -200,7 +201,7 @@ hipError_t launch_adj_out(ImgSet &set, ItemRange one, int K, int k0, float *geps
 
 // Stand-alone guided filter on caller-provided images (context-free).
 hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
-                                      hipStream_t s);
+                                      bool clip, hipStream_t s);
 hipError_t launch_guided_filter_color(const float *I3, const float *up, float *u, int M, int N, int w, float eps,
                                       hipStream_t s);
 
@@ -214,8 +215,10 @@ hipError_t launch_col_fwd_d(cd *S, const Layout &L, const FftPlan &pm, const cd 
 hipError_t launch_init_consts(const cd *Hd, const cd *Yd, const Layout &L, cf *H, cf *Y, cf *HY, float *H2,
                               hipStream_t st);
 hipError_t launch_d2_tables(int M, int N, int Wh, float *dM, float *dN, hipStream_t st);
-hipError_t launch_rho_target(const float *y, int M, int N, const float *h, int kh, int kw, double sigma2,
-                             double rho_fixed, double *work, double *out2, LamState *st, hipStream_t st_);
+hipError_t launch_rho_target(const float *y, int M, int N, size_t ndom, const float *h, int kh, int kw,
+                             double sigma2, double rho_fixed, double *work, double *out2, LamState *st,
+                             hipStream_t s);
+hipError_t launch_pad_ramp(const float *y, int M, int N, float *out, int Mp, int Np, hipStream_t st);
 hipError_t launch_fill_f(float *p, size_t n, float v, hipStream_t st);
 hipError_t launch_state_reset(LamState *st, hipStream_t s);
 hipError_t launch_state_set_lam(LamState *st, float lam, hipStream_t s);

@@ -11,7 +11,10 @@
 //   g_I = g_u B(a) + B(g_mu) + p B(g_c) + 2 I B(g_v),  g_p = B(g_pbar) + I B(g_c).
 // Three streaming box passes compute it (k_box_stage with three epilogues), in the same
 // mean-centred variables as the forward filter (the filter commutes with constant shifts, so
-// the gradient is the same).
+// the gradient is the same).  With windows clipped to the image, B = D^-1 S (S the clipped
+// window sum, symmetric; D the counts) and the box sums that carry gradients backwards are
+// B^T = S D^-1: their fields are divided by the count of the input pixel's window before they
+// are summed, and their sums are used as they are.
 //
 // Solves.  For lambda = s lambda*, R = H U_E - Y, dp = |H|^2 + lambda, dI = |H|^2 + lambda D2:
 //   G_UE = (lambda / dp) G_p + (lambda D2 / dI) G_I  with  G_x = F(g_x) / P,
@@ -34,8 +37,10 @@ namespace gfd {
 // Each stage loads NR raw values per pixel (load) and derives its NF summed fields from them
 // (fields).  Its epilogue receives, for the output pixel, the raw values (from the register ring)
 // and NE more values loaded a round ahead (eload).
+// kT marks the fields whose sums are transposed means (gradients flowing back through B).
 struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
   static constexpr int NF = 4, NR = 2, NE = 1;
+  static constexpr unsigned kT = 0u;
   static constexpr bool kEps = false;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
     r[0] = G(d.uI)[g];
@@ -64,6 +69,7 @@ struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
 
 struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c, g_u B(a)
   static constexpr int NF = 3, NR = 3, NE = 3;
+  static constexpr unsigned kT = 6u;  // B^T(g_u I), B^T(g_u)
   static constexpr bool kEps = true;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
     r[0] = G(d.ga)[g];
@@ -104,6 +110,7 @@ struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c
 
 struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
   static constexpr int NF = 4, NR = 4, NE = 3;
+  static constexpr unsigned kT = 15u;  // all four are transposed means
   static constexpr bool kEps = false;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
     r[0] = G(d.gmu)[g];
@@ -132,8 +139,9 @@ struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
 // thread owns a column of the strip extended by r on both sides, keeps compensated vertical
 // running sums of the stage's NF fields and the block forms the horizontal window sums in
 // LDS; the stage's epilogue consumes the window means of each output pixel.  Images whose
-// lambda was +inf skip nothing here (the filter is applied on that branch too).
-template <int R, class Op>
+// lambda was +inf skip nothing here (the filter is applied on that branch too).  With CLIP,
+// pixels outside the image enter the sums as zeros and the means are normalised by counts.
+template <int R, class Op, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict__ D, const Item *__restrict__ W,
                                                           int nitems) {
   constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = kGfRB;
@@ -154,6 +162,16 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
     const int gx = wrap(x0 - R + j, N);
     const int nrows = TY + 2 * R, ybase = y0 - R;  // stream row it is image row ybase + it
     const float cI = d.st->meanI, cP = d.st->meanP;
+    const int xcol = x0 - R + j;
+    const bool colin = !CLIP || (xcol >= 0 && xcol < N);
+    const int ncol = CLIP && colin ? clip_count<R>(xcol, N) : 1;
+    // CLIP: factor of the fields of stream row `row` (0 outside the image; the reciprocal count
+    // of the pixel's window for transposed fields)
+    auto in_scale = [&](int row, int f) -> float {
+      const int y = ybase + row;
+      if (!(colin && y >= 0 && y < M)) return 0.0f;
+      return ((Op::kT >> f) & 1u) ? __builtin_amdgcn_rcpf((float)(clip_count<R>(y, M) * ncol)) : 1.0f;
+    };
     hs_zero_pads<R>(vbuf, RB * NF);  // ordered before the first reads by the first barrier
     Kahan s[NF];
 #pragma unroll
@@ -196,6 +214,13 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
           float vn[NF], vo[NF];
           Op::fields(nr[q], cI, cP, vn);
           Op::fields(ring[sl], cI, cP, vo);  // stream row it - Wn (zeros while it < Wn)
+          if (CLIP) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+              vn[f] *= in_scale(it, f);
+              vo[f] *= in_scale(it - Wn, f);
+            }
+          }
 #pragma unroll
           for (int x = 0; x < NR; ++x) ring[sl][x] = nr[q][x];
 #pragma unroll
@@ -226,8 +251,11 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
           const int y = ybase + it - R, x = x0 - R + j;
           if (it < nrows && it >= 2 * R && j >= R && j < TX + R && x < N && y < M && y < y0 + TY) {
             float B[NF];
+            float nrm = inv_w2;
+            if (CLIP) nrm = __builtin_amdgcn_rcpf((float)(clip_count<R>(y, M) * ncol));
 #pragma unroll
-            for (int f = 0; f < NF; ++f) B[f] = hbuf[(q * NF + f) * kGfThreads + j] * inv_w2;
+            for (int f = 0; f < NF; ++f)
+              B[f] = hbuf[(q * NF + f) * kGfThreads + j] * (CLIP && ((Op::kT >> f) & 1u) ? 1.0f : nrm);
             Op::emit(d, (size_t)y * N + x, B, er[q], ee[q], cI, cP, eacc);
           }
         }
@@ -475,19 +503,23 @@ int adj_strips(const Img &d) { return (d.L.N + d.bxTX - 1) / d.bxTX * d.bxNBY; }
   X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 
 void plan_box_stage(Plan &p, ImgSet &set, const std::vector<int> &sel, int stage) {
-  std::map<int, std::vector<int>> byR;
-  for (int i : sel) byR[(set.imgs[i].w - 1) / 2].push_back(i);
+  std::map<int, std::vector<int>> byR;  // key 2 r + clip
+  for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
     ItemRange r = add_items(set, kv.second, [](const Img &d) { return adj_strips(d); });
-    const int R = kv.first;
-#define GFD_BOX_CASE(RR)                                                                              \
-  if (R == RR) {                                                                                      \
-    if (stage == 1) p.steps.push_back(make_launch(&set, k_box_stage<RR, BoxStage1>, r, kGfThreads, 0)); \
-    if (stage == 2) p.steps.push_back(make_launch(&set, k_box_stage<RR, BoxStage2>, r, kGfThreads, 0)); \
-    if (stage == 3) p.steps.push_back(make_launch(&set, k_box_stage<RR, BoxStage3>, r, kGfThreads, 0)); \
+    const int R = kv.first / 2;
+    const bool clip = (kv.first & 1) != 0;
+#define GFD_BOX_ONE(RR, OP) \
+  p.steps.push_back(make_launch(&set, clip ? k_box_stage<RR, OP, true> : k_box_stage<RR, OP, false>, r, kGfThreads, 0))
+#define GFD_BOX_CASE(RR)                      \
+  if (R == RR) {                              \
+    if (stage == 1) GFD_BOX_ONE(RR, BoxStage1); \
+    if (stage == 2) GFD_BOX_ONE(RR, BoxStage2); \
+    if (stage == 3) GFD_BOX_ONE(RR, BoxStage3); \
   }
     GFD_R_CASES(GFD_BOX_CASE)
 #undef GFD_BOX_CASE
+#undef GFD_BOX_ONE
   }
 }
 

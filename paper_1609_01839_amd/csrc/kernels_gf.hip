@@ -14,6 +14,10 @@
 // (the image means when known) before products are formed; the filter commutes with such
 // shifts (u shifts by the input's constant).  The radius is a template parameter so that the
 // horizontal sums unroll into back-to-back LDS reads.
+//
+// With CLIP, windows are clipped to the image instead of wrapping: pixels outside the image
+// enter the sums as zeros, every mean divides by the number of the window's pixels inside the
+// image, and windows centred outside the image contribute no coefficients.
 #include <map>
 
 #include "box_sum.h"
@@ -22,7 +26,7 @@
 namespace gfd {
 
 // One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
-template <int R>
+template <int R, bool CLIP>
 __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, const GFD_AS1 float *__restrict__ uP,
                                          GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY, int nby,
                                          int lb, float cI, float cP, float2 *__restrict__ ringAB,
@@ -40,6 +44,11 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const int gx = wrap(x0 - 2 * R + j, N);
   const int nrows = TY + 4 * R;  // stream rows it = 0 .. nrows-1 are image rows y0 - 2R + it
   const int ybase = y0 - 2 * R;
+  // CLIP: whether this thread's column lies in the image, and the reciprocal column count of
+  // the windows centred on it (stage-1 coefficients and stage-2 outputs share the column)
+  const int xcol = x0 - 2 * R + j;
+  const bool colin = !CLIP || (xcol >= 0 && xcol < N);
+  const int ncol = CLIP && colin ? clip_count<R>(xcol, N) : 1;
 
   // Each thread keeps the mean-centred I and p of the last W stream rows of its column in a
   // register ring (slot it % W), so the rows leaving the stage-1 windows and the guide value of
@@ -70,7 +79,11 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
         const int s = (RB * r + q) % W, sg = (RB * r + q + 1) % W;
-        const float I = __fsub_rn(nI[q], cI), p = __fsub_rn(nP[q], cP);
+        float I = __fsub_rn(nI[q], cI), p = __fsub_rn(nP[q], cP);
+        if (CLIP) {
+          const int y = ybase + base + q;
+          if (!(colin && y >= 0 && y < M)) I = p = 0.0f;  // outside the image: no contribution
+        }
         const float Io = rI[s], po = rP[s];  // stream row it - W (zero while it < W)
         rI[s] = I;
         rP[s] = p;
@@ -105,12 +118,20 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           float *vb = vbuf + q * 2 * VP + R;
           if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
             const float *hb = hbuf + q * 4 * kGfThreads;
-            const float mu = hb[j] * inv_w2;
-            const float pb = hb[kGfThreads + j] * inv_w2;
-            const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * inv_w2), 0.0f);
-            const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * inv_w2);
-            const float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
-            const float b = __fmaf_rn(-a, mu, pb);
+            float nrm = inv_w2;
+            bool cin = true;
+            if (CLIP) {  // window centred at image row ybase + it - R, column xcol
+              const int yc = ybase + it - R;
+              cin = colin && yc >= 0 && yc < M;
+              nrm = cin ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yc, M) * ncol)) : 0.0f;
+            }
+            const float mu = hb[j] * nrm;
+            const float pb = hb[kGfThreads + j] * nrm;
+            const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * nrm), 0.0f);
+            const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * nrm);
+            float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
+            float b = __fmaf_rn(-a, mu, pb);
+            if (CLIP && !cin) a = b = 0.0f;  // windows centred outside the image do not exist
             const int slot = (RB * r + q + 1) % W;  // it2 % W (base0 is a multiple of W)
             float2 old = make_float2(0.0f, 0.0f);
             if (it2 >= W) old = ringAB[slot * kGfThreads + j];
@@ -140,7 +161,8 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           const int xo = x0 - 2 * R + j;      // output column
           if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
             const float *hb = hbuf + q * 2 * kGfThreads;
-            const float abar = hb[j] * inv_w2, bbar = hb[kGfThreads + j] * inv_w2;
+            const float nrm = CLIP ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yo, M) * ncol)) : inv_w2;
+            const float abar = hb[j] * nrm, bbar = hb[kGfThreads + j] * nrm;
             u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
           }
         }
@@ -153,7 +175,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
 // The item of block 0 of each image also closes that image's iteration: the counter advances
 // and the first lambda candidates of the next search are seeded.  Nothing else in this launch
 // reads those fields, and the means used as offsets are left untouched.
-template <int R>
+template <int R, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems, int close_iteration) {
   constexpr int Wn = 2 * R + 1;
@@ -179,13 +201,14 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, 
       st->k += 1;
       st->phase = 0;
     }
-    gf_strip<R>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, ringAB, vbuf, hbuf);
+    gf_strip<R, CLIP>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, ringAB,
+                      vbuf, hbuf);
     __syncthreads();
   }
 }
 
 // Stand-alone filter: the offsets are the first pixels of the inputs.
-template <int R>
+template <int R, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
                                                          float *__restrict__ u, int M, int N, float eps, int TX,
                                                          int TY, int nby) {
@@ -194,7 +217,7 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict
   __shared__ __align__(16) float vbuf[kGfRB * 4 * hs_pitch<R>()];
   __shared__ __align__(16) float hbuf[kGfRB * 4 * kGfThreads];
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  gf_strip<R>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], ringAB, vbuf, hbuf);
+  gf_strip<R, CLIP>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], ringAB, vbuf, hbuf);
 }
 
 bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
@@ -228,8 +251,8 @@ void gf_geometry(Img &d, int ty) {
   }
 
 void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool close_iteration) {
-  std::map<int, std::vector<int>> byR;
-  for (int i : sel) byR[(set.imgs[i].w - 1) / 2].push_back(i);
+  std::map<int, std::vector<int>> byR;  // key 2 r + clip
+  for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
     const size_t off = set.items_host.size();
     for (int i : kv.second) {
@@ -237,28 +260,27 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool 
       append_items(set, i, (d.L.N + d.gfTX - 1) / d.gfTX * d.gfNBY);
     }
     const size_t n = set.items_host.size() - off;
-    ImgSet *setp = &set;
-    const int r = kv.first, close = close_iteration ? 1 : 0;
-    p.steps.push_back([=](hipStream_t s) -> hipError_t {
-      if (n == 0) return hipSuccess;
-#define GFD_LAUNCH_GF(RR)                                                                                    \
-  hipLaunchKernelGGL(k_gf_g<RR>, dim3((unsigned)n), dim3(kGfThreads), 0, s, (const Img *)setp->dev,          \
-                     (const Item *)(setp->items_dev + off), (int)n, close)
-      GFD_R_SWITCH(r, GFD_LAUNCH_GF)
-#undef GFD_LAUNCH_GF
-      return hipGetLastError();
-    });
+    const int r = kv.first / 2, close = close_iteration ? 1 : 0;
+    const bool clip = (kv.first & 1) != 0;
+    const ItemRange range{off, n};
+#define GFD_PLAN_GF(RR) \
+  p.steps.push_back(make_launch(&set, clip ? k_gf_g<RR, true> : k_gf_g<RR, false>, range, kGfThreads, 0, close))
+    GFD_R_SWITCH(r, GFD_PLAN_GF)
+#undef GFD_PLAN_GF
   }
 }
 
 hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u, int M, int N, int w, float eps,
-                                      hipStream_t s) {
+                                      bool clip, hipStream_t s) {
   const int r = (w - 1) / 2;
   if (!guided_filter_supported(w)) return hipErrorInvalidValue;
   int TX, TY, nbx, nby;
   gf_tiles(M, N, r, 0, TX, TY, nbx, nby);
-#define GFD_LAUNCH_GFP(RR) \
-  hipLaunchKernelGGL(k_gf_plain<RR>, dim3(nbx * nby), dim3(kGfThreads), 0, s, uI, uP, u, M, N, eps, TX, TY, nby)
+#define GFD_LAUNCH_GFP(RR)                                                                          \
+  {                                                                                                 \
+    auto kern = clip ? k_gf_plain<RR, true> : k_gf_plain<RR, false>;                                \
+    hipLaunchKernelGGL(kern, dim3(nbx * nby), dim3(kGfThreads), 0, s, uI, uP, u, M, N, eps, TX, TY, nby); \
+  }
   GFD_R_SWITCH(r, GFD_LAUNCH_GFP)
 #undef GFD_LAUNCH_GFP
   return hipGetLastError();

@@ -819,11 +819,12 @@ __global__ void k_ycentred(const float *__restrict__ y, size_t n, const double *
   if (threadIdx.x == 0) part2[blockIdx.x] = sh[0];
 }
 
-// rho of Eq.(12) (radicand clipped to [1e-12, 1]) unless fixed, target T = rho P sigma^2, and
-// the constants of the search state.
+// rho of Eq.(12) (radicand clipped to [1e-12, 1]) unless fixed, target T = rho P sigma^2 over
+// the n observed pixels, and the constants of the search state, whose Parseval factors use the
+// ndom pixels of the transform domain (ndom = n unless the observation was padded).
 __global__ void k_rho_final(const double *__restrict__ part, const double *__restrict__ part2, int nparts,
-                            const float *__restrict__ h, int nh, size_t n, double sigma2, double rho_fixed,
-                            double *out2, LamState *st) {
+                            const float *__restrict__ h, int nh, size_t n, size_t ndom, double sigma2,
+                            double rho_fixed, double *out2, LamState *st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double sy2 = 0.0, sc = 0.0, h1 = 0.0;
   for (int p = 0; p < nparts; ++p) {
@@ -841,8 +842,8 @@ __global__ void k_rho_final(const double *__restrict__ part, const double *__res
   const double T = rho * P * sigma2;
   out2[0] = rho;
   out2[1] = T;
-  st->TP = (float)(T * P);
-  st->invP = (float)(1.0 / P);
+  st->TP = (float)(T * (double)ndom);
+  st->invP = (float)(1.0 / (double)ndom);
 }
 
 __global__ void k_fill_f(float *p, size_t n, float v) {
@@ -1182,14 +1183,48 @@ hipError_t launch_d2_tables(int M, int N, int Wh, float *dM, float *dN, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_rho_target(const float *y, int M, int N, const float *h, int kh, int kw, double sigma2,
-                             double rho_fixed, double *work, double *out2, LamState *st, hipStream_t s) {
+hipError_t launch_rho_target(const float *y, int M, int N, size_t ndom, const float *h, int kh, int kw,
+                             double sigma2, double rho_fixed, double *work, double *out2, LamState *st,
+                             hipStream_t s) {
   size_t n = (size_t)M * N;
   const int nb = 256;
   hipLaunchKernelGGL(k_ysums, dim3(nb), dim3(256), 0, s, y, n, work);
   hipLaunchKernelGGL(k_ycentred, dim3(nb), dim3(256), 0, s, y, n, work, nb, work + 2 * nb);
-  hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(64), 0, s, work, work + 2 * nb, nb, h, kh * kw, n, sigma2, rho_fixed,
-                     out2, st);
+  hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(64), 0, s, work, work + 2 * nb, nb, h, kh * kw, n, ndom, sigma2,
+                     rho_fixed, out2, st);
+  return hipGetLastError();
+}
+
+// The observation (or an estimate) y, M x N, in the top-left corner of an Mp x Np image whose
+// periodic extension is continuous: columns N.. of each row ramp linearly from its last value
+// towards its first (t / (Np - N + 1) of the way at column N - 1 + t), then rows M.. ramp the
+// same way between rows M - 1 and 0 of the widened image.  FP64 arithmetic, one rounding.
+__global__ void k_pad_ramp(const float *__restrict__ y, int M, int N, float *__restrict__ out, int Mp, int Np) {
+  const size_t total = (size_t)Mp * Np;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int m = (int)(i / Np), n = (int)(i - (size_t)m * Np);
+    auto row = [&](int r) -> double {
+      const float *yr = y + (size_t)r * N;
+      if (n < N) return (double)yr[n];
+      const double a = yr[N - 1], b = yr[0];
+      return a + (b - a) * (double)(n - N + 1) / (double)(Np - N + 1);
+    };
+    double v;
+    if (m < M) {
+      v = row(m);
+    } else {
+      const double a = row(M - 1), b = row(0);
+      v = a + (b - a) * (double)(m - M + 1) / (double)(Mp - M + 1);
+    }
+    out[i] = (float)v;
+  }
+}
+
+hipError_t launch_pad_ramp(const float *y, int M, int N, float *out, int Mp, int Np, hipStream_t st) {
+  const size_t n = (size_t)Mp * Np;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_pad_ramp, dim3(blocks), dim3(256), 0, st, y, M, N, out, Mp, Np);
   return hipGetLastError();
 }
 

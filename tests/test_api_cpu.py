@@ -68,6 +68,16 @@ def test_guided_filter_argument_checks():
     assert lib.guided_filter(a, b, ctypes.c_void_p(0x10000 + 64), 16, 16, 3, 1.0, None) == -1  # u overlaps uI
 
 
+def test_guided_filter_clipped_argument_checks():
+    lib = gfd.load_library()
+    a, b, c = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000), ctypes.c_void_p(0x30000)
+    assert lib.guided_filter_clipped(None, b, c, 16, 16, 3, 1.0, None) == -1
+    assert lib.guided_filter_clipped(a, b, c, 16, 16, 2, 1.0, None) == -1
+    assert lib.guided_filter_clipped(a, b, c, 16, 16, 3, 0.0, None) == -1
+    assert lib.guided_filter_clipped(a, b, c, 64, 64, 19, 1.0, None) == -6
+    assert lib.guided_filter_clipped(a, ctypes.c_void_p(0x30000 - 8), c, 16, 16, 3, 1.0, None) == -1
+
+
 def test_guided_filter_color_argument_checks():
     lib = gfd.load_library()
     a, b, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
@@ -111,4 +121,23 @@ def test_batch_descriptors_are_checked_without_gpu():
     assert lib.deconv_init_batch(ctypes.byref(ctx), None, 1, None) == -1
     assert lib.deconv_init_batch(ctypes.byref(ctx), ctypes.cast(arr, ctypes.c_void_p), 5000, None) == -1
     assert lib.deconv_image_info(None, 0, None, None, None, None) == -5
-    assert ctypes.sizeof(gfd.GfdImage) == 56
+    assert lib.deconv_image_domain(None, 0, None, None, None) == -5
+    assert ctypes.sizeof(gfd.GfdImage) == 64
+
+
+def test_boundary_flags_are_checked_without_gpu():
+    lib = gfd.load_library()
+    ctx = ctypes.c_void_p()
+    fake = 0x1000
+
+    def init(M, N, kh, boundary):
+        img = gfd.GfdImage(fake, M, N, fake, kh, kh, 1.0, 3, 1.0, -1.0, boundary)
+        return lib.deconv_init_batch(ctypes.byref(ctx), ctypes.byref(img), 1, None)
+
+    assert init(64, 64, 3, 4) == -1                      # unknown flag
+    assert init(64, 64, 3, -1) == -1
+    assert init(4096, 64, 3, gfd.BOUNDARY_PAD) == -2     # padded domain 4098 -> 4320 > 4096
+    assert init(7 * 16, 64, 3, gfd.BOUNDARY_CLIP) == -2  # unpadded sizes must be 2^a 3^b 5^c
+    assert init(1, 64, 1, gfd.BOUNDARY_PAD) == -2        # observed sides of at least 2
+    assert init(64, 64, 65, gfd.BOUNDARY_PAD) == -2      # PSF larger than the observation
+    assert ctx.value is None
