@@ -8,9 +8,9 @@
 //            sums -> a_k, b_k (Eqs.(3)-(4)) for one row of windows;
 //   stage 2: the same two-direction sums over a and b -> abar, bbar (Eq.(5)), then
 //            u = abar * I + bbar.
-// The rows leaving the stage-1 windows and the guide row of the output are re-read from global
-// memory (they were read w rows earlier and are still cached); the last w rows of (a, b) sit in
-// an LDS ring.  Windows wrap periodically in both directions.  Inputs are shifted by constants
+// The inputs of the last w rows and the coefficients of the last w rows of windows stay in
+// per-thread register rings, so nothing is loaded twice.  Windows wrap periodically in both
+// directions.  Inputs are shifted by constants
 // (the image means when known) before products are formed; the filter commutes with such
 // shifts (u shifts by the input's constant).  The radius is a template parameter so that the
 // horizontal sums unroll into back-to-back LDS reads.
@@ -25,16 +25,27 @@
 
 namespace gfd {
 
+// Rows per round of barriers of the filter's streaming strip.
+constexpr int kGfRows = 2;
+
+// LDS of one strip: RB rows x 4 fields of padded vertical sums and of horizontal sums.
+template <int R>
+struct GfLds {
+  float vbuf[kGfRows * 4 * hs_pitch<R>()];
+  float hbuf[kGfRows * 4 * kGfThreads];
+};
+
 // One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
 template <int R, bool CLIP>
 __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, const GFD_AS1 float *__restrict__ uP,
                                          GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY, int nby,
-                                         int lb, float cI, float cP, float2 *__restrict__ ringAB,
-                                         float *__restrict__ vbuf, float *__restrict__ hbuf) {
+                                         int lb, float cI, float cP, GfLds<R> &sh) {
   constexpr int W = 2 * R + 1;
-  constexpr int RB = kGfRB;
+  constexpr int RB = kGfRows;
   constexpr int VP = hs_pitch<R>();  // padded row of vertical sums
-  hs_zero_pads<R>(vbuf, RB * 4);     // ordered before the first reads by the first barrier
+  float *__restrict__ vbuf = sh.vbuf;
+  float *__restrict__ hbuf = sh.hbuf;
+  hs_zero_pads<R>(vbuf, RB * 4);  // ordered before the first reads by the first barrier
   const float inv_w2 = 1.0f / (float)(W * W);
   const int bx = lb / nby, by = lb - bx * nby;
   const int x0 = bx * TX, y0 = by * TY;
@@ -50,22 +61,22 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const bool colin = !CLIP || (xcol >= 0 && xcol < N);
   const int ncol = CLIP && colin ? clip_count<R>(xcol, N) : 1;
 
-  // Each thread keeps the mean-centred I and p of the last W stream rows of its column in a
-  // register ring (slot it % W), so the rows leaving the stage-1 windows and the guide value of
-  // the output row (stream row it - 2r, still in the ring) are never loaded twice.  The row loop
-  // is unrolled over 2W rows (W rounds of two), which makes every ring slot a compile-time index.
-  // Loads run one round ahead: a round first consumes the rows loaded during the previous round,
-  // then issues the next loads, and only then does its LDS work.
-  static_assert(kGfRB == 2, "rounds of two rows");
+  // Each thread keeps, in registers, the mean-centred I and p of the last W stream rows of its
+  // column (slot it % W) and the coefficients (a, b) of the last W rows of windows centred on it
+  // (slot it2 % W), so rows leaving the windows and the guide value of the output row (stream
+  // row it - 2r, still in the ring) are never loaded or recomputed.  The row loop is unrolled
+  // over RB W rows (W rounds of RB), which makes every ring slot a compile-time index.  Loads run
+  // one round ahead: a round first consumes the rows loaded during the previous round, then
+  // issues the next loads, and only then does its LDS work.
   auto fetch = [&](int it, float &I, float &p) {
     const size_t g = (size_t)wrap(ybase + min(it, nrows - 1), M) * N + gx;
     I = uI[g];
     p = uP[g];
   };
   Kahan sI = {0, 0}, sP = {0, 0}, sII = {0, 0}, sIP = {0, 0}, sA = {0, 0}, sB = {0, 0};
-  float rI[W], rP[W];
+  float rI[W], rP[W], rA[W], rB[W];
 #pragma unroll
-  for (int k = 0; k < W; ++k) rI[k] = rP[k] = 0.0f;
+  for (int k = 0; k < W; ++k) rI[k] = rP[k] = rA[k] = rB[k] = 0.0f;
   float nI[RB], nP[RB];
 #pragma unroll
   for (int q = 0; q < RB; ++q) fetch(q, nI[q], nP[q]);
@@ -104,84 +115,83 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
       }
 #pragma unroll
       for (int q = 0; q < RB; ++q) fetch(base + RB + q, nI[q], nP[q]);
-        __syncthreads();
-        if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
-        // ---- stage 1, horizontal: RB rows x 4 quantities
+      __syncthreads();
+      if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
+      // ---- stage 1, horizontal: RB rows x 4 quantities
 #pragma unroll
-        for (int t = j; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
-        __syncthreads();
-        // ---- a, b (Eqs. 3-4) and stage 2, vertical
+      for (int t = j; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+      __syncthreads();
+      // ---- a, b (Eqs. 3-4) and stage 2, vertical
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-          const int it = base + q;
-          const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
-          float *vb = vbuf + q * 2 * VP + R;
-          if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
-            const float *hb = hbuf + q * 4 * kGfThreads;
-            float nrm = inv_w2;
-            bool cin = true;
-            if (CLIP) {  // window centred at image row ybase + it - R, column xcol
-              const int yc = ybase + it - R;
-              cin = colin && yc >= 0 && yc < M;
-              nrm = cin ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yc, M) * ncol)) : 0.0f;
-            }
-            const float mu = hb[j] * nrm;
-            const float pb = hb[kGfThreads + j] * nrm;
-            const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * nrm), 0.0f);
-            const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * nrm);
-            float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
-            float b = __fmaf_rn(-a, mu, pb);
-            if (CLIP && !cin) a = b = 0.0f;  // windows centred outside the image do not exist
-            const int slot = (RB * r + q + 1) % W;  // it2 % W (base0 is a multiple of W)
-            float2 old = make_float2(0.0f, 0.0f);
-            if (it2 >= W) old = ringAB[slot * kGfThreads + j];
-            ringAB[slot * kGfThreads + j] = make_float2(a, b);
-            kahan_slide(sA, a, old.x);
-            kahan_slide(sB, b, old.y);
-            vb[j] = sA.s;
-            vb[VP + j] = sB.s;
-          } else {
-            // Columns without coefficients still enter the first window of a sliding run before
-            // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
-            vb[j] = 0.0f;
-            vb[VP + j] = 0.0f;
+      for (int q = 0; q < RB; ++q) {
+        const int it = base + q;
+        const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
+        float *vb = vbuf + q * 2 * VP + R;
+        if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
+          const float *hb = hbuf + q * 4 * kGfThreads;
+          float nrm = inv_w2;
+          bool cin = true;
+          if (CLIP) {  // window centred at image row ybase + it - R, column xcol
+            const int yc = ybase + it - R;
+            cin = colin && yc >= 0 && yc < M;
+            nrm = cin ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yc, M) * ncol)) : 0.0f;
           }
+          const float mu = hb[j] * nrm;
+          const float pb = hb[kGfThreads + j] * nrm;
+          const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * nrm), 0.0f);
+          const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * nrm);
+          float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
+          float b = __fmaf_rn(-a, mu, pb);
+          if (CLIP && !cin) a = b = 0.0f;  // windows centred outside the image do not exist
+          const int slot = (RB * r + q + 1) % W;  // it2 % W (base0 is a multiple of W)
+          const float ao = it2 >= W ? rA[slot] : 0.0f, bo = it2 >= W ? rB[slot] : 0.0f;
+          rA[slot] = a;
+          rB[slot] = b;
+          kahan_slide(sA, a, ao);
+          kahan_slide(sB, b, bo);
+          vb[j] = sA.s;
+          vb[VP + j] = sB.s;
+        } else {
+          // Columns without coefficients still enter the first window of a sliding run before
+          // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
+          vb[j] = 0.0f;
+          vb[VP + j] = 0.0f;
         }
-        __syncthreads();
-        if (base + RB - 1 < 4 * R) continue;  // no complete stage-2 window yet (uniform)
-        // ---- stage 2, horizontal: RB rows x 2 quantities
+      }
+      __syncthreads();
+      if (base + RB - 1 < 4 * R) continue;  // no complete stage-2 window yet (uniform)
+      // ---- stage 2, horizontal: RB rows x 2 quantities
 #pragma unroll
-        for (int t = j; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
-        __syncthreads();
-        // ---- output rows
+      for (int t = j; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+      __syncthreads();
+      // ---- output rows
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-          const int it = base + q;
-          const int yo = ybase + it - 2 * R;  // output row
-          const int xo = x0 - 2 * R + j;      // output column
-          if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
-            const float *hb = hbuf + q * 2 * kGfThreads;
-            const float nrm = CLIP ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yo, M) * ncol)) : inv_w2;
-            const float abar = hb[j] * nrm, bbar = hb[kGfThreads + j] * nrm;
-            u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
-          }
+      for (int q = 0; q < RB; ++q) {
+        const int it = base + q;
+        const int yo = ybase + it - 2 * R;  // output row
+        const int xo = x0 - 2 * R + j;      // output column
+        if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
+          const float *hb = hbuf + q * 2 * kGfThreads;
+          const float nrm = CLIP ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yo, M) * ncol)) : inv_w2;
+          const float abar = hb[j] * nrm, bbar = hb[kGfThreads + j] * nrm;
+          u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
         }
+      }
       // the next round's first barrier orders these hbuf reads before hbuf is rewritten
     }
   }
 }
 
 // Inside the iteration: one launch filters every image of the group (images of one radius).
+// Four waves per SIMD (at most 128 VGPRs): the widest radius spills a few registers, which
+// costs less than the lost occupancy.
 // The item of block 0 of each image also closes that image's iteration: the counter advances
 // and the first lambda candidates of the next search are seeded.  Nothing else in this launch
 // reads those fields, and the means used as offsets are left untouched.
 template <int R, bool CLIP>
-__global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
+__global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems, int close_iteration) {
-  constexpr int Wn = 2 * R + 1;
-  __shared__ float2 ringAB[Wn * kGfThreads];
-  __shared__ __align__(16) float vbuf[kGfRB * 4 * hs_pitch<R>()];
-  __shared__ __align__(16) float hbuf[kGfRB * 4 * kGfThreads];
+  __shared__ __align__(16) GfLds<R> sh;
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
     const Item wi = W[ii];
     if (wi.blk < 0) continue;
@@ -201,8 +211,7 @@ __global__ void __launch_bounds__(kGfThreads) k_gf_g(const Img *__restrict__ D, 
       st->k += 1;
       st->phase = 0;
     }
-    gf_strip<R, CLIP>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, ringAB,
-                      vbuf, hbuf);
+    gf_strip<R, CLIP>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
     __syncthreads();
   }
 }
@@ -212,12 +221,9 @@ template <int R, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
                                                          float *__restrict__ u, int M, int N, float eps, int TX,
                                                          int TY, int nby) {
-  constexpr int Wn = 2 * R + 1;
-  __shared__ float2 ringAB[Wn * kGfThreads];
-  __shared__ __align__(16) float vbuf[kGfRB * 4 * hs_pitch<R>()];
-  __shared__ __align__(16) float hbuf[kGfRB * 4 * kGfThreads];
+  __shared__ __align__(16) GfLds<R> sh;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  gf_strip<R, CLIP>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], ringAB, vbuf, hbuf);
+  gf_strip<R, CLIP>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
 }
 
 bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
