@@ -55,19 +55,51 @@ __device__ __forceinline__ void store_partial(GFD_AS1 float *part, int npart, in
   }
 }
 
-// Compensated sum of the partials of `nparts` blocks with every thread of the block;
-// deterministic order; result in thread 0.
+// Compensated sums of the NV values of the partials of `nparts` blocks.  Wave w takes values
+// w, w + nwaves, ...: each lane accumulates the partials lane, lane + 64, ... in order (loaded
+// 32 at a time, so that up to 2048 partials cost one memory round trip), then the
+// wave combines its lanes by shuffles, so no lane carries more than one value through the
+// shuffle tree (the tree is the expensive part).  Deterministic order; thread 0 receives all NV
+// sums.  `scratch` must hold 2 NV floats.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict__ part, int npart, int nparts, float (&hi)[NV],
                                 float (&lo)[NV], float *scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int v = wid; v < NV; v += nw) {
+    const GFD_AS1 float *ph = part + (size_t)(2 * v) * npart, *pl = part + (size_t)(2 * v + 1) * npart;
+    float h = 0.0f, l = 0.0f;
+    // U partials per lane per pass, loaded together before they are added in order
+    constexpr int U = 32;
+    for (int p0 = lane; p0 < nparts; p0 += 64 * U) {
+      float xh[U], xl[U];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) hi[v] = lo[v] = 0.0f;
-  for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+      for (int u = 0; u < U; ++u) {
+        const int p = p0 + 64 * u;
+        xh[u] = p < nparts ? ph[p] : 0.0f;
+        xl[u] = p < nparts ? pl[p] : 0.0f;
+      }
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      df_add(hi[v], lo[v], part[(size_t)(2 * v) * npart + p], part[(size_t)(2 * v + 1) * npart + p]);
+      for (int u = 0; u < U; ++u) df_add(h, l, xh[u], xl[u]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const float oh = __shfl_down(h, off, 64), ol = __shfl_down(l, off, 64);
+      df_add(h, l, oh, ol);
+    }
+    if (lane == 0) {
+      scratch[2 * v] = h;
+      scratch[2 * v + 1] = l;
+    }
   }
-  block_reduce_df<NV>(hi, lo, scratch);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      hi[v] = scratch[2 * v];
+      lo[v] = scratch[2 * v + 1];
+    }
+  }
+  __syncthreads();
 }
 
 // Commit the lambda of this iteration (one thread, once the search is finished).  The search

@@ -20,6 +20,17 @@
 #define GFD_HD
 #endif
 
+// Quotients and exponentials whose last bits do not matter (candidate placement, bracket
+// bookkeeping, Newton steps) use the hardware approximations on the device: this code runs on
+// one thread, where every accurately rounded division or exponential is a long dependent chain.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GFD_QDIV(a, b) __fdividef((a), (b))
+#define GFD_QEXP(x) __expf(x)
+#else
+#define GFD_QDIV(a, b) ((a) / (b))
+#define GFD_QEXP(x) expf(x)
+#endif
+
 namespace gfd {
 
 constexpr int kLamMaxCand = 8;     // candidates per evaluation round
@@ -56,7 +67,7 @@ struct LamState {
 
 GFD_HD inline float lam_relF(float hi, float lo, float TP) {
   // f / T - 1 with the subtraction done exactly when hi is close to TP
-  return ((hi - TP) + lo) / TP;
+  return GFD_QDIV((hi - TP) + lo, TP);
 }
 
 GFD_HD inline void lam_set_cand(LamState &s, int n, const float *c) {
@@ -64,7 +75,7 @@ GFD_HD inline void lam_set_cand(LamState &s, int n, const float *c) {
   for (int j = 0; j < n; ++j) {
     float v = fminf(fmaxf(c[j], kLamFloor), kLamCeil);
     s.cand[j] = v;
-    s.mu[j] = 1.0f / v;
+    s.mu[j] = GFD_QDIV(1.0f, v);
   }
 }
 
@@ -77,7 +88,7 @@ GFD_HD inline void lam_first_candidates(LamState &s) {
     float sp = 1.0f;
     if (s.lam_prev2 > 0.0f) sp = fminf(fmaxf(1.5f * fabsf(logf(s.lam_prev / s.lam_prev2)), 0.02f), 1.0f);
     for (int j = 0; j < kLamFirstCand; ++j)
-      c[j] = s.lam_prev * expf(sp * ((float)j - 0.5f * (kLamFirstCand - 1)));
+      c[j] = s.lam_prev * GFD_QEXP(sp * ((float)j - 0.5f * (kLamFirstCand - 1)));
   } else {
     const float x0 = logf(kLamFloor), x1 = logf(kLamCeil);
     for (int j = 0; j < kLamFirstCand; ++j)
@@ -92,7 +103,7 @@ GFD_HD inline void lam_absorb(LamState &s, int n, const float *cand, const float
   for (int j = 0; j < n; ++j) {
     float F = lam_relF(Shi[j], Slo[j], s.TP);
     float S = Shi[j] + Slo[j];
-    float D = S > 0.0f ? 2.0f * Dsum[j] / S : 0.0f;
+    float D = S > 0.0f ? GFD_QDIV(2.0f * Dsum[j], S) : 0.0f;
     if (F < 0.0f) {
       if (!s.haslo || cand[j] > s.llo) { s.haslo = 1; s.llo = cand[j]; s.Flo = F; s.Dlo = D; }
     } else {
@@ -105,14 +116,15 @@ GFD_HD inline void lam_absorb(LamState &s, int n, const float *cand, const float
 // d0, d1 (already multiplied by the interval length).
 GFD_HD inline float hermite_root(float G0, float G1, float d0, float d1, float tau_guess) {
   float lo = 0.0f, hi = 1.0f, t = fminf(fmaxf(tau_guess, 0.0f), 1.0f);
-  for (int it = 0; it < 40; ++it) {
+  for (int it = 0; it < 30; ++it) {
     float t2 = t * t, t3 = t2 * t;
     float p = (2 * t3 - 3 * t2 + 1) * G0 + (t3 - 2 * t2 + t) * d0 + (-2 * t3 + 3 * t2) * G1 + (t3 - t2) * d1;
     float dp = (6 * t2 - 6 * t) * G0 + (3 * t2 - 4 * t + 1) * d0 + (-6 * t2 + 6 * t) * G1 + (3 * t2 - 2 * t) * d1;
     if (p < 0.0f) lo = t; else hi = t;
-    float tn = (dp > 0.0f) ? t - p / dp : -1.0f;
+    float tn = (dp > 0.0f) ? t - GFD_QDIV(p, dp) : -1.0f;
     if (!(tn > lo && tn < hi)) tn = 0.5f * (lo + hi);
-    if (fabsf(tn - t) <= 1e-9f) { t = tn; break; }
+    // converged to FP32 resolution (Newton may then alternate between neighbouring floats)
+    if (fabsf(tn - t) <= 4.0f * 1.1920929e-7f * fmaxf(t, 1e-3f)) { t = tn; break; }
     t = tn;
   }
   return t;
@@ -150,16 +162,16 @@ GFD_HD inline int lam_decide(LamState &s, bool last) {
     }
     const int n = kLamMaxCand;
     if (width > 1.0f || !(err > 0.0f)) {
-      for (int j = 0; j < n; ++j) next[j] = s.llo * expf(width * (float)(j + 1) / (float)(n + 1));
+      for (int j = 0; j < n; ++j) next[j] = s.llo * GFD_QEXP(width * (float)(j + 1) / (float)(n + 1));
     } else {
       float h = fmaxf(4.0f * err, 1e-7f);
       if (h * (float)(n + 1) >= width) {
-        for (int j = 0; j < n; ++j) next[j] = s.llo * expf(width * (float)(j + 1) / (float)(n + 1));
+        for (int j = 0; j < n; ++j) next[j] = s.llo * GFD_QEXP(width * (float)(j + 1) / (float)(n + 1));
       } else {
         // clustered around the estimate, kept strictly inside the bracket
         float xe = logf(est / s.llo);
         xe = fminf(fmaxf(xe, 0.5f * h * (float)(n + 1)), width - 0.5f * h * (float)(n + 1));
-        for (int j = 0; j < n; ++j) next[j] = s.llo * expf(xe + h * ((float)j - 0.5f * (float)(n - 1)));
+        for (int j = 0; j < n; ++j) next[j] = s.llo * GFD_QEXP(xe + h * ((float)j - 0.5f * (float)(n - 1)));
       }
     }
     lam_set_cand(s, n, next);
@@ -169,10 +181,10 @@ GFD_HD inline int lam_decide(LamState &s, bool last) {
   const float step = 6.0f;
   if (s.haslo) {
     if (last || s.llo >= kLamCeil) { s.lam_star = s.llo; s.phase = 1; return 1; }
-    for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.llo * expf(step * (float)(j + 1));
+    for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.llo * GFD_QEXP(step * (float)(j + 1));
   } else {
     if (last || s.lhi <= kLamFloor) { s.lam_star = s.lhi; s.phase = 1; return 1; }
-    for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.lhi * expf(-step * (float)(j + 1));
+    for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.lhi * GFD_QEXP(-step * (float)(j + 1));
   }
   lam_set_cand(s, kLamMaxCand, next);
   return 0;
