@@ -33,7 +33,7 @@ ALG_BYTES = {
 }
 KERNEL_SYMBOL = {
     "row_fwd": "k_row_fwd_r16", "col_fwd_resid": "k_col_fwd_r16<true>", "lambda_sweeps": "k_lam_sweep",
-    "col_inv_solve": "k_col_inv_r16", "row_inv": "k_row_inv_r16", "guided_filter": "k_gf_g<8>",
+    "col_inv_solve": "k_col_inv_r16", "row_inv": "k_row_inv_r16", "guided_filter": "k_gf_g<8, false>",
 }
 
 

@@ -35,32 +35,51 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return v < 0 ? v + n : v;
 }
 
-// Rows of vertical sums are kept in LDS with R zero columns on each side: column c of a
-// row is at index c + R of a row of hs_pitch<R>() floats (a multiple of 4).  The padding
-// columns are zeroed once and never written, so that runs at the strip's edges read finite
-// values without clamped indices.
+// LDS layout of the rows that the horizontal sums read and write: column c of a row sits at
+// hs_col(c) = c + 4 (c / 8), i.e. every run of 8 columns is followed by 4 unused floats.  A
+// horizontal-sum task reads and writes whole runs as float4 words; with runs 48 bytes apart the
+// eight lanes that one LDS cycle serves hit eight different groups of four banks (runs 32 bytes
+// apart would put two lanes on every group), and every float4 offset inside a task is a
+// compile-time constant.
+__host__ __device__ constexpr int hs_col(int c) { return c + 4 * (c >> 3); }
+
+// Rows of horizontal sums (outputs): kGfThreads columns.
+constexpr int kHsOut = hs_col(kGfThreads - 1) + 1;
+static_assert(kHsOut % 4 == 0, "float4 rows");
+
+// Rows of vertical sums are kept with R zero columns on each side: column c of the block is
+// padded column c + R, at hs_col(c + R) of a row of hs_pitch<R>() floats.  The padding columns
+// are zeroed once and never written, so that runs at the strip's edges read finite values
+// without clamped indices.
+template <int R>
+constexpr int hs_nv() {
+  return (kGfRun + 2 * R + 3) / 4;  // float4 words a task reads
+}
+template <int R>
+constexpr int hs_last_col() {
+  return kGfThreads - kGfRun + 4 * hs_nv<R>() - 1;  // last padded column a task reads
+}
 template <int R>
 constexpr int hs_pitch() {
-  return (kGfThreads + 2 * R + 3) & ~3;
+  return (hs_col(hs_last_col<R>()) + 1 + 3) & ~3;
 }
 
 // Horizontal window sums (half-width R) over rows of padded vertical sums: task `t` covers row
-// t / runs and output columns [j0, j0 + kGfRun), j0 = run * kGfRun.  Its inputs, columns
-// j0 - R .. j0 + kGfRun - 1 + R, start at the 16-byte aligned index j0 and are read as float4
-// words; the outputs go out as float4 words into rows of kGfThreads floats.  Columns outside [R, used - R) produce don't-care
-// values.
+// t / runs and output columns [j0, j0 + kGfRun), j0 = run * kGfRun.  Its inputs, padded columns
+// j0 .. j0 + kGfRun - 1 + 2R, are read as float4 words; the outputs go out as float4 words into
+// rows of kHsOut floats.  Columns outside [R, used - R) produce don't-care values.
 template <int R>
 __device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *__restrict__ dst, int task) {
-  static_assert(kGfRun % 4 == 0, "outputs go out as float4");
+  static_assert(kGfRun == 8, "runs of 8 columns (the LDS layout)");
   constexpr int runs = kGfThreads / kGfRun;
-  constexpr int NX = kGfRun + 2 * R, NV = (NX + 3) / 4;
+  constexpr int NV = hs_nv<R>();
   const int row = task / runs, run = task - row * runs;
   const int j0 = run * kGfRun;
-  const float4 *v4 = reinterpret_cast<const float4 *>(src + row * hs_pitch<R>() + j0);
+  const float *in = src + row * hs_pitch<R>() + hs_col(j0);
   float x[4 * NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    const float4 q = v4[k];
+    const float4 q = *reinterpret_cast<const float4 *>(in + 4 * k + 4 * (k >> 1));
     x[4 * k] = q.x;
     x[4 * k + 1] = q.y;
     x[4 * k + 2] = q.z;
@@ -76,19 +95,19 @@ __device__ __forceinline__ void hsum_task(const float *__restrict__ src, float *
     s += x[i + 2 * R] - x[i - 1];
     o[i] = s;
   }
-  float4 *d4 = reinterpret_cast<float4 *>(dst + row * kGfThreads + j0);
-#pragma unroll
-  for (int k = 0; k < kGfRun / 4; ++k) d4[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+  float *out = dst + row * kHsOut + hs_col(j0);
+  *reinterpret_cast<float4 *>(out) = make_float4(o[0], o[1], o[2], o[3]);
+  *reinterpret_cast<float4 *>(out + 4) = make_float4(o[4], o[5], o[6], o[7]);
 }
 
 // Zero the padding columns of `nrows` padded rows (every thread of the block calls this).
 template <int R>
 __device__ __forceinline__ void hs_zero_pads(float *buf, int nrows) {
-  constexpr int P = hs_pitch<R>(), npad = P - kGfThreads;
+  constexpr int P = hs_pitch<R>(), lo = R, hi = hs_last_col<R>() - (kGfThreads + R) + 1, npad = lo + hi;
   if constexpr (npad > 0) {
     for (int i = threadIdx.x; i < nrows * npad; i += blockDim.x) {
       const int r = i / npad, c = i - r * npad;
-      buf[r * P + (c < R ? c : kGfThreads + c)] = 0.0f;
+      buf[r * P + hs_col(c < lo ? c : kGfThreads + R + (c - lo))] = 0.0f;
     }
   }
 }

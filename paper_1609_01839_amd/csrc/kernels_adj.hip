@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
   constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = kGfRB;
   constexpr int VP = hs_pitch<R>();
   __shared__ __align__(16) float vbuf[RB * NF * VP];
-  __shared__ __align__(16) float hbuf[RB * NF * kGfThreads];
+  __shared__ __align__(16) float hbuf[RB * NF * kHsOut];
   __shared__ float red[kGfThreads / 64];
   const float inv_w2 = 1.0f / (float)(Wn * Wn);
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
@@ -227,16 +227,16 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
           for (int x = 0; x < NR; ++x) er[q][x] = ring[so][x];  // the output row's raw values
 #pragma unroll
           for (int x = 0; x < NE; ++x) ee[q][x] = ne[q][x];
-          float *vb = vbuf + q * NF * VP + R;
+          float *vb = vbuf + q * NF * VP + hs_col(j + R);
           if (active && it < nrows) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
               kahan_slide(s[f], vn[f], it >= Wn ? vo[f] : 0.0f);
-              vb[f * VP + j] = s[f].s;
+              vb[f * VP] = s[f].s;
             }
           } else {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) vb[f * VP + j] = 0.0f;
+            for (int f = 0; f < NF; ++f) vb[f * VP] = 0.0f;
           }
         }
 #pragma unroll
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
             if (CLIP) nrm = __builtin_amdgcn_rcpf((float)(clip_count<R>(y, M) * ncol));
 #pragma unroll
             for (int f = 0; f < NF; ++f)
-              B[f] = hbuf[(q * NF + f) * kGfThreads + j] * (CLIP && ((Op::kT >> f) & 1u) ? 1.0f : nrm);
+              B[f] = hbuf[(q * NF + f) * kHsOut + hs_col(j)] * (CLIP && ((Op::kT >> f) & 1u) ? 1.0f : nrm);
             Op::emit(d, (size_t)y * N + x, B, er[q], ee[q], cI, cP, eacc);
           }
         }

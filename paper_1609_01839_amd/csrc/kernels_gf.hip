@@ -32,7 +32,7 @@ constexpr int kGfRows = 2;
 template <int R>
 struct GfLds {
   float vbuf[kGfRows * 4 * hs_pitch<R>()];
-  float hbuf[kGfRows * 4 * kGfThreads];
+  float hbuf[kGfRows * 4 * kHsOut];
 };
 
 // One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
@@ -60,6 +60,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const int xcol = x0 - 2 * R + j;
   const bool colin = !CLIP || (xcol >= 0 && xcol < N);
   const int ncol = CLIP && colin ? clip_count<R>(xcol, N) : 1;
+  const int cj = hs_col(j + R), hj = hs_col(j);  // this column in the rows of vertical / horizontal sums
 
   // Each thread keeps, in registers, the mean-centred I and p of the last W stream rows of its
   // column (slot it % W) and the coefficients (a, b) of the last W rows of windows centred on it
@@ -99,18 +100,18 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         rI[s] = I;
         rP[s] = p;
         Ig[q] = rI[sg];  // stream row it - 2r: the guide of this round's output row
-        float *vb = vbuf + q * 4 * VP + R;
+        float *vb = vbuf + q * 4 * VP + cj;
         if (active && base + q < nrows) {
           kahan_slide(sI, I, Io);
           kahan_slide(sP, p, po);
           kahan_slide(sII, I * I, Io * Io);
           kahan_slide(sIP, I * p, Io * po);
-          vb[j] = sI.s;
-          vb[VP + j] = sP.s;
-          vb[2 * VP + j] = sII.s;
-          vb[3 * VP + j] = sIP.s;
+          vb[0] = sI.s;
+          vb[VP] = sP.s;
+          vb[2 * VP] = sII.s;
+          vb[3 * VP] = sIP.s;
         } else {
-          vb[j] = vb[VP + j] = vb[2 * VP + j] = vb[3 * VP + j] = 0.0f;
+          vb[0] = vb[VP] = vb[2 * VP] = vb[3 * VP] = 0.0f;
         }
       }
 #pragma unroll
@@ -126,9 +127,9 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
       for (int q = 0; q < RB; ++q) {
         const int it = base + q;
         const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
-        float *vb = vbuf + q * 2 * VP + R;
+        float *vb = vbuf + q * 2 * VP + cj;
         if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
-          const float *hb = hbuf + q * 4 * kGfThreads;
+          const float *hb = hbuf + q * 4 * kHsOut + hj;
           float nrm = inv_w2;
           bool cin = true;
           if (CLIP) {  // window centred at image row ybase + it - R, column xcol
@@ -136,10 +137,10 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
             cin = colin && yc >= 0 && yc < M;
             nrm = cin ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yc, M) * ncol)) : 0.0f;
           }
-          const float mu = hb[j] * nrm;
-          const float pb = hb[kGfThreads + j] * nrm;
-          const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kGfThreads + j] * nrm), 0.0f);
-          const float cov = __fmaf_rn(-mu, pb, hb[3 * kGfThreads + j] * nrm);
+          const float mu = hb[0] * nrm;
+          const float pb = hb[kHsOut] * nrm;
+          const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kHsOut] * nrm), 0.0f);
+          const float cov = __fmaf_rn(-mu, pb, hb[3 * kHsOut] * nrm);
           float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
           float b = __fmaf_rn(-a, mu, pb);
           if (CLIP && !cin) a = b = 0.0f;  // windows centred outside the image do not exist
@@ -149,13 +150,13 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           rB[slot] = b;
           kahan_slide(sA, a, ao);
           kahan_slide(sB, b, bo);
-          vb[j] = sA.s;
-          vb[VP + j] = sB.s;
+          vb[0] = sA.s;
+          vb[VP] = sB.s;
         } else {
           // Columns without coefficients still enter the first window of a sliding run before
           // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
-          vb[j] = 0.0f;
-          vb[VP + j] = 0.0f;
+          vb[0] = 0.0f;
+          vb[VP] = 0.0f;
         }
       }
       __syncthreads();
@@ -171,9 +172,9 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         const int yo = ybase + it - 2 * R;  // output row
         const int xo = x0 - 2 * R + j;      // output column
         if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
-          const float *hb = hbuf + q * 2 * kGfThreads;
+          const float *hb = hbuf + q * 2 * kHsOut + hj;
           const float nrm = CLIP ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yo, M) * ncol)) : inv_w2;
-          const float abar = hb[j] * nrm, bbar = hb[kGfThreads + j] * nrm;
+          const float abar = hb[0] * nrm, bbar = hb[kHsOut] * nrm;
           u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
         }
       }

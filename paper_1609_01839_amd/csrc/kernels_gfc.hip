@@ -23,6 +23,12 @@ namespace {
 
 constexpr int kC1 = 13;  // stage-1 fields
 constexpr int kC2 = 4;   // stage-2 fields: a_r, a_g, a_b, b
+// Rows per round: one for small radii (13 LDS rows per stream row: less LDS, more blocks per CU),
+// two for wide windows, where the halo work dominates.
+template <int R>
+constexpr int gfc_rows() {
+  return R <= 4 ? 1 : 2;
+}
 
 __device__ __forceinline__ void gfc_fields(const float (&x)[4], float (&v)[kC1]) {
   const float r = x[0], g = x[1], b = x[2], p = x[3];
@@ -71,8 +77,7 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
                                           GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY,
                                           int nby, int lb, const float (&cen)[4], float *__restrict__ vbuf,
                                           float *__restrict__ hbuf) {
-  constexpr int W = 2 * R + 1, RB = kGfRB, VP = hs_pitch<R>();
-  static_assert(RB == 2, "rounds of two rows");
+  constexpr int W = 2 * R + 1, RB = gfc_rows<R>(), VP = hs_pitch<R>();
   hs_zero_pads<R>(vbuf, RB * kC1);  // ordered before the first reads by the first barrier
   const float inv_w2 = 1.0f / (float)(W * W);
   const size_t plane = (size_t)M * N;
@@ -128,16 +133,16 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
         for (int x = 0; x < 3; ++x) guide[q][x] = rx[sg][x];  // stream row it - 2r
         gfc_fields(rx[s], vn);
         gfc_fields(xo, vo);
-        float *vb = vbuf + q * kC1 * VP + R;
+        float *vb = vbuf + q * kC1 * VP + hs_col(j + R);
         if (active && base + q < nrows) {
 #pragma unroll
           for (int f = 0; f < kC1; ++f) {
             kahan_slide(s1[f], vn[f], vo[f]);
-            vb[f * VP + j] = s1[f].s;
+            vb[f * VP] = s1[f].s;
           }
         } else {
 #pragma unroll
-          for (int f = 0; f < kC1; ++f) vb[f * VP + j] = 0.0f;
+          for (int f = 0; f < kC1; ++f) vb[f * VP] = 0.0f;
         }
       }
 #pragma unroll
@@ -152,23 +157,23 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
         const int it = base + q, it2 = it - (W - 1);  // row of (a, b) in the stage-2 stream
-        float *vb = vbuf + q * kC2 * VP + R;
+        float *vb = vbuf + q * kC2 * VP + hs_col(j + R);
         if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
           const int slot = (RB * r + q + 1) % W;  // it2 mod W
           float m[kC1], ab[kC2];
 #pragma unroll
-          for (int f = 0; f < kC1; ++f) m[f] = hbuf[(q * kC1 + f) * kGfThreads + j] * inv_w2;
+          for (int f = 0; f < kC1; ++f) m[f] = hbuf[(q * kC1 + f) * kHsOut + hs_col(j)] * inv_w2;
           gfc_coeffs(m, eps, ab);
 #pragma unroll
           for (int f = 0; f < kC2; ++f) {
             kahan_slide(s2[f], ab[f], it2 >= W ? rab[slot][f] : 0.0f);
             rab[slot][f] = ab[f];
-            vb[f * VP + j] = s2[f].s;
+            vb[f * VP] = s2[f].s;
           }
         } else {
           // columns without coefficients enter the first window of a sliding run: keep them zero
 #pragma unroll
-          for (int f = 0; f < kC2; ++f) vb[f * VP + j] = 0.0f;
+          for (int f = 0; f < kC2; ++f) vb[f * VP] = 0.0f;
         }
       }
       __syncthreads();
@@ -182,10 +187,10 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
         const int it = base + q;
         const int yo = ybase + it - 2 * R, xo = x0 - 2 * R + j;
         if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
-          const float *hb = hbuf + q * kC2 * kGfThreads + j;
-          float acc = hb[3 * kGfThreads] * inv_w2;
+          const float *hb = hbuf + q * kC2 * kHsOut + hs_col(j);
+          float acc = hb[3 * kHsOut] * inv_w2;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) acc = __fmaf_rn(hb[c * kGfThreads] * inv_w2, guide[q][c], acc);
+          for (int c = 0; c < 3; ++c) acc = __fmaf_rn(hb[c * kHsOut] * inv_w2, guide[q][c], acc);
           u[(size_t)yo * N + xo] = __fadd_rn(acc, cen[3]);
         }
       }
@@ -198,8 +203,8 @@ template <int R>
 __global__ void __launch_bounds__(kGfThreads) k_gfc_plain(const float *__restrict__ I3, const float *__restrict__ up,
                                                           float *__restrict__ u, int M, int N, float eps, int TX,
                                                           int TY, int nby) {
-  __shared__ __align__(16) float vbuf[kGfRB * kC1 * hs_pitch<R>()];
-  __shared__ __align__(16) float hbuf[kGfRB * kC1 * kGfThreads];
+  __shared__ __align__(16) float vbuf[gfc_rows<R>() * kC1 * hs_pitch<R>()];
+  __shared__ __align__(16) float hbuf[gfc_rows<R>() * kC1 * kHsOut];
   const size_t plane = (size_t)M * N;
   const float cen[4] = {I3[0], I3[plane], I3[2 * plane], up[0]};
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
