@@ -192,7 +192,7 @@ def main():
     y = torch.from_numpy(case.y).to(dev)
     h = torch.from_numpy(case.h.astype(np.float32)).to(dev)
     g = gfd.GFDeconv(y, h, case.sigma2, case.w, case.eps)
-    tuning = None if args.no_autotune else g.autotune(4)
+    tuning = None if args.no_autotune else g.autotune(8)
     stream = torch.cuda.current_stream(dev)
     out = torch.empty((M, N), device=dev, dtype=torch.float32)
     lam = torch.empty((1,), device=dev, dtype=torch.float32)

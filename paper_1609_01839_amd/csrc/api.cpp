@@ -1105,7 +1105,14 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
       return false;
     }
     if ((rc = capture_graph(c)) != GFD_OK) return false;
-    e = hipGraphLaunch(c->gexec, s);  // warm-up replay
+    // every trial runs the same iterations: from the saved estimate and search state
+    for (int i = 0; i < c->count && e == hipSuccess; ++i) {
+      const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
+      e = hipMemcpyAsync(c->main.imgs[i].uE, ue_save[i], P * sizeof(float), hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->st, st_save.data(), c->count * sizeof(LamState), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipGraphLaunch(c->gexec, s);  // warm-up replay
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     for (int k = 0; k < n && e == hipSuccess; ++k) e = hipGraphLaunch(c->gexec, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
