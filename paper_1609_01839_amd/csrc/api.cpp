@@ -298,7 +298,7 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   const size_t P = (size_t)M * N, nb = L.bins();
   d.nchunk = lam_sweep_chunks(nb);
   d.npart = std::max(L.NT, d.nchunk);
-  cf *twM, *twN, *H, *Y, *HY, *S1, *SI, *SP;
+  cf *twM, *twN, *H, *Y, *HY, *S1, *SIP;
   float *H2, *dM, *dN, *uE, *uI, *uP, *q, *part;
   cd *twMd, *twNd;
   hipError_t e = hipSuccess;
@@ -317,8 +317,7 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   ALLOC(uP, P);
   ALLOC(q, nb);
   ALLOC(S1, nb);
-  ALLOC(SI, nb);
-  ALLOC(SP, nb);
+  ALLOC(SIP, 2 * nb);
   ALLOC(part, (size_t)2 * kLamAcc * d.npart);
   float *u0 = nullptr;
   ALLOC(u0, P);
@@ -339,8 +338,7 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   d.uP = uP;
   d.q = q;
   d.S1 = S1;
-  d.SI = SI;
-  d.SP = SP;
+  d.SIP = SIP;
   d.part = part;
   d.st = c->st + i;
   d.lam_hist = c->lam_hist + (size_t)i * c->hist_cap;
@@ -621,7 +619,7 @@ static hipError_t build_bwd(gfd_ctx *c) {
     const size_t P = (size_t)m.L.M * m.L.N, nb = m.L.bins();
     Img d = m;
     float *uR, *ga, *gmu, *gpb, *gve, *gc, *gd, *gu, *gI, *gP, *gpart, *geh, *gsh;
-    cf *SgI, *SgP, *Gs, *Gz;
+    cf *SgI, *SgP, *Gs;
 #define BALLOC(ptr, cnt) \
   if (e == hipSuccess) e = balloc(b, &(ptr), (cnt))
     BALLOC(uR, P);
@@ -637,7 +635,6 @@ static hipError_t build_bwd(gfd_ctx *c) {
     BALLOC(SgI, nb);
     BALLOC(SgP, nb);
     BALLOC(Gs, nb);
-    BALLOC(Gz, nb);
     BALLOC(geh, c->hist_cap);
     BALLOC(gsh, c->hist_cap);
 #undef BALLOC
@@ -645,7 +642,6 @@ static hipError_t build_bwd(gfd_ctx *c) {
     adj_geometry(d);
     e = balloc(b, &gpart, (size_t)adj_strips(d));
     if (e != hipSuccess) break;
-    e = hipMemset(Gz, 0, nb * sizeof(cf));
     d.uE = uR;
     d.st = b->st + i;
     d.ga = ga;
@@ -672,9 +668,9 @@ static hipError_t build_bwd(gfd_ctx *c) {
     gp.S1 = SgP;
     b->grad.imgs.push_back(gi);
     b->grad.imgs.push_back(gp);
-    Img go = d;          // inverse transform of the adjoint spectrum into the gradient
-    go.SI = m.SI;
-    go.SP = Gz;
+    Img go = d;          // inverse transform of the adjoint spectrum into the gradient: its column
+                         // pass writes (G, 0) pairs into the solves' buffer
+    go.SIP = m.SIP;
     go.uI = gu;
     go.uP = m.uP;
     b->gout.imgs.push_back(go);

@@ -61,7 +61,9 @@ struct Img {
   const float *dM, *dN;  // |F(grad)|^2 = dM[m] + dN[k]
   float *uE, *uI, *uP;   // images (u_E is also the filter's output)
   float *q;              // Hermitian-weighted |R|^2, tile-major
-  cf *S1, *SI, *SP;      // spectra: row transforms / U_E, and the two solves
+  cf *S1;                // spectra: row transforms, then U_E
+  cf *SIP;               // the two solves after the column inverse, row-major and interleaved:
+                         // bin (m, k) holds U_I at SIP[2 (m RP + k)] and U_p right after it
   float *part;           // partial sums, [2 * kLamAcc][npart]
   int npart;             // stride of `part` (>= NT and >= nchunk)
   int nchunk;            // blocks of a lambda evaluation round

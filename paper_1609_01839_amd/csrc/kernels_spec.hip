@@ -358,7 +358,8 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SP)[(size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1))] = buf[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x)
+    G(d.SIP)[2 * ((size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1))) + 1] = buf[e];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < E; ++u) {
@@ -367,7 +368,8 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SI)[(size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1))] = buf[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x)
+    G(d.SIP)[2 * ((size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1)))] = buf[e];
   GFD_ITEM_END
 }
 
@@ -390,7 +392,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 #pragma unroll 4
     for (int k = threadIdx.x; k < Wh; k += blockDim.x) {
       const size_t g = (size_t)m * lay.RP + k;
-      cf A = G(d.SI)[g], B = G(d.SP)[g];
+      cf A = G(d.SIP)[2 * g], B = G(d.SIP)[2 * g + 1];
       if (k == 0 || 2 * k == N) {
         A.im = 0.0f;
         B.im = 0.0f;
@@ -577,15 +579,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     d.st->meanP = vp[0].re;
     d.st->meanI = vi[0].re;
   }
+  // both transforms, then one 16-byte store per bin (U_I, U_p): the two columns of the tile give
+  // 32 contiguous bytes per row
   reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
-  if (active) {
-#pragma unroll
-    for (int m = 0; m < 16; ++m) G(d.SP)[(size_t)(t + T * m) * lay.RP + k] = vp[m];
-  }
   reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
   if (active) {
+    GFD_AS1 float4 *out = reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP));
 #pragma unroll
-    for (int m = 0; m < 16; ++m) G(d.SI)[(size_t)(t + T * m) * lay.RP + k] = vi[m];
+    for (int m = 0; m < 16; ++m)
+      out[(size_t)(t + T * m) * lay.RP + k] = make_float4(vi[m].re, vi[m].im, vp[m].re, vp[m].im);
   }
   GFD_ITEM_END
 }
@@ -612,8 +614,9 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
       const int n = t + T * m;
       const int kk = n < Wh ? n : N - n;
       const size_t g = (size_t)rowc * lay.RP + kk;
-      A[m] = G(d.SI)[g];
-      B[m] = G(d.SP)[g];
+      const float4 ab = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP))[g];
+      A[m] = cf{ab.x, ab.y};
+      B[m] = cf{ab.z, ab.w};
     }
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
