@@ -372,6 +372,9 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   if (e == hipSuccess) e = launch_state_reset(d.st, s);
   if (e == hipSuccess) e = launch_fill_f(uE, P, 0.0f, s);
   if (e == hipSuccess) e = launch_fill_f(u0, P, 0.0f, s);
+  // q of the padding columns (and of the last tile, which a folded residual pass never writes)
+  // stays zero: the lambda sweeps sum over every bin
+  if (e == hipSuccess) e = launch_fill_f(q, nb, 0.0f, s);
   c->u0.push_back(u0);
   // the FP64 temporaries are shared by the images: finish before the next image reuses them
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -30,6 +30,10 @@ struct Layout {
   FastDiv Ndiv;   // division by N
   FastDiv RCdiv;  // division by R * C
   FastDiv RfCdiv; // division by Rf * C
+  // 1: the register-resident column inverse folds column N/2 (alone in the last tile) into the
+  // block of tile 0 as the imaginary part of column 0, so it launches NT - 1 blocks
+  int fold;
+  __host__ __device__ int col_blocks() const { return NT - fold; }
   __host__ __device__ size_t bins() const { return (size_t)NT * M * C; }
 };
 
@@ -131,14 +135,14 @@ inline hipError_t set_lds(K kern, size_t lds) {
 // Append the work items of one image (blocks 0 .. nblk-1), padded to a multiple of 8 and
 // permuted so that every 8th item (one XCD's share: the hardware deals blocks to the 8 XCDs
 // in turn) covers a contiguous run of blocks, which then share that XCD's L2.
-inline void append_items(ImgSet &set, int img, int nblk) {
+inline void append_items(ImgSet &set, int img, int nblk, int first = 0) {
   const int nx = 8;
   const int padded = (nblk + nx - 1) / nx * nx;
   const int per = padded / nx;
   for (int i = 0; i < padded; ++i) {
     const int xcd = i % nx, local = i / nx;
     const int blk = xcd * per + local;
-    set.items_host.push_back(Item{img, blk < nblk ? blk : -1});
+    set.items_host.push_back(Item{img, blk < nblk ? first + blk : -1});
   }
 }
 

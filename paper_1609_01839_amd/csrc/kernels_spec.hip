@@ -534,6 +534,11 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
   GFD_ITEM_END
 }
 
+// With Layout::fold the block of tile 0 also solves column N/2 (column 0 of the last tile,
+// which no block owns) and transforms it as the imaginary part of column 0: both solved columns
+// are Hermitian, so their inverse transforms are real and the real and imaginary parts of the
+// one transform are the two columns.  The folded column is solved first and parked in LDS, so
+// that it adds no registers to the main solve.
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) k_col_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -548,6 +553,21 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   const int k = wi.blk * C + c;
   const bool valid = active && k < lay.Wh;
   const float dk = valid ? G(d.dN)[k] : 0.0f;
+  const bool fold = lay.fold && wi.blk == 0;  // uniform over the block
+  const bool fc = fold && c == 0 && active;
+  if (fc) {  // column N/2, parked in LDS (free until the transforms)
+    const size_t offN = (size_t)(lay.NT - 1) * lay.M * C;
+    const float dN2 = G(d.dN)[lay.N / 2];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int row = t + T * m;
+      const size_t e = offN + (size_t)row * C;
+      cf Up, Ui;
+      solve_bin(sp, G(d.S1)[e], G(d.HY)[e], G(d.H2)[e], G(d.dM)[row] + dN2, Up, Ui);
+      lds[row] = Up;
+      lds[lay.M + row] = Ui;
+    }
+  }
   // all loads first (no store in between), then the solves
   // Straight-line rows (the solve's case split is taken once, outside the loop; padding columns
   // are computed and then zeroed; the means are written after the loop), so the compiler can
@@ -579,15 +599,35 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     d.st->meanP = vp[0].re;
     d.st->meanI = vi[0].re;
   }
+  if (fold) {
+    if (fc) {  // U_0 + i U_N
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const cf np = lds[t + T * m], ni = lds[lay.M + t + T * m];
+        vp[m] = cf{vp[m].re - np.im, vp[m].im + np.re};
+        vi[m] = cf{vi[m].re - ni.im, vi[m].im + ni.re};
+      }
+    }
+    __syncthreads();  // the parked column is read before the transforms use the LDS
+  }
   // both transforms, then one 16-byte store per bin (U_I, U_p): the two columns of the tile give
   // 32 contiguous bytes per row
   reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
   reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
   if (active) {
     GFD_AS1 float4 *out = reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP));
+    if (fc) {  // real parts: column 0; imaginary parts: column N/2
 #pragma unroll
-    for (int m = 0; m < 16; ++m)
-      out[(size_t)(t + T * m) * lay.RP + k] = make_float4(vi[m].re, vi[m].im, vp[m].re, vp[m].im);
+      for (int m = 0; m < 16; ++m) {
+        const size_t g = (size_t)(t + T * m) * lay.RP;
+        out[g] = make_float4(vi[m].re, 0.0f, vp[m].re, 0.0f);
+        out[g + lay.N / 2] = make_float4(vi[m].im, 0.0f, vp[m].im, 0.0f);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+        out[(size_t)(t + T * m) * lay.RP + k] = make_float4(vi[m].re, vi[m].im, vp[m].re, vp[m].im);
+    }
   }
   GFD_ITEM_END
 }
@@ -940,6 +980,7 @@ Layout make_layout(int M, int N, const Tuning &tune) {
   L.logC = ilog2(C);
   L.NT = (L.Wh + C - 1) / C;
   L.RP = L.NT * C;
+  L.fold = (reg_plan_ok(M) && N % 2 == 0 && (N / 2) % C == 0 && L.NT >= 2) ? 1 : 0;
   // rows per block in the LDS-resident row passes: aim at >= 128-byte segments, LDS <= 64 KiB
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
@@ -1103,7 +1144,8 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
     int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
-    ItemRange r = add_items(set, imgs, [](const Img &d) { return d.L.NT; });
+    const bool reg = std::get<0>(k) != 0;  // the register-resident pass folds the last tile
+    ItemRange r = add_items(set, imgs, [reg](const Img &d) { return reg ? d.L.col_blocks() : d.L.NT; });
     if (std::get<0>(k)) {
       int threads = 0; size_t lds = 0;
       for (int i : imgs) {
