@@ -204,14 +204,14 @@ static hipError_t build_plans(gfd_ctx *c) {
   for (int i = 0; i < c->count; ++i) all[i] = i;
   plan_row_fwd(c->stage[0], c->main, all);
   plan_col_fwd(c->stage[1], c->main, all, true);
-  plan_lambda(c->stage[2], c->main, all, kSweeps);
+  plan_lambda(c->stage[2], c->main, all, kSweeps, true);
   plan_col_inv(c->stage[3], c->main, all);
   plan_row_inv(c->stage[4], c->main, all);
-  plan_guided_filter(c->stage[5], c->main, all, true);
+  plan_guided_filter(c->stage[5], c->main, all);
   for (int k = 0; k < kStages; ++k) append(c->iter, c->stage[k]);
   append(c->warm, c->stage[0]);
   append(c->warm, c->stage[1]);
-  plan_lambda(c->warm, c->main, all, kSweepsFull);
+  plan_lambda(c->warm, c->main, all, kSweepsFull, false);
   hipError_t e = finalize_items(c->main);
   if (e != hipSuccess) return e;
   if (c->count == 1) {
@@ -222,7 +222,7 @@ static hipError_t build_plans(gfd_ctx *c) {
     plan_row_inv(c->aux_solve, c->aux, one);
     plan_row_fwd(c->aux_lam, c->aux, one);
     plan_col_fwd(c->aux_lam, c->aux, one, true);
-    plan_lambda(c->aux_lam, c->aux, one, kSweepsFull);
+    plan_lambda(c->aux_lam, c->aux, one, kSweepsFull, false);
     e = finalize_items(c->aux);
   }
   return e;
@@ -691,7 +691,7 @@ static hipError_t build_bwd(gfd_ctx *c) {
   plan_col_fwd(b->fwd_a, b->bwd, all, false);
   plan_col_inv(b->fwd_b, b->bwd, all);
   plan_row_inv(b->fwd_b, b->bwd, all);
-  plan_guided_filter(b->gf, b->bwd, all, false);
+  plan_guided_filter(b->gf, b->bwd, all);
   for (int st = 0; st < 3; ++st) plan_box_stage(b->box[st], b->bwd, all, st + 1);
   plan_adj_spec(b->spec, b->bwd, all);
   plan_adj_col(b->col, b->bwd, all);

@@ -185,10 +185,10 @@ inline Launch make_launch(ImgSet *setp, K kern, ItemRange r, int threads, size_t
 // set.items_dev, so finalize_items() must run before a plan is enqueued.
 void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid);
-void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds);
+void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, bool advance);
 void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
-void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool close_iteration);
+void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel);
 hipError_t finalize_items(ImgSet &set);
 void gf_geometry(Img &d, int ty = 0);
 bool guided_filter_supported(int w);

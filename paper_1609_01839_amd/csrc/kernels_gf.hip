@@ -186,32 +186,15 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
 // Inside the iteration: one launch filters every image of the group (images of one radius).
 // Four waves per SIMD (at most 128 VGPRs): the widest radius spills a few registers, which
 // costs less than the lost occupancy.
-// The item of block 0 of each image also closes that image's iteration: the counter advances
-// and the first lambda candidates of the next search are seeded.  Nothing else in this launch
-// reads those fields, and the means used as offsets are left untouched.
 template <int R, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
-                                                     int nitems, int close_iteration) {
+                                                     int nitems) {
   __shared__ __align__(16) GfLds<R> sh;
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
     const Item wi = W[ii];
     if (wi.blk < 0) continue;
     const Img &d = D[wi.img];
-    LamState *st = d.st;
-    const float cI = st->meanI, cP = st->meanP;
-    if (close_iteration && wi.blk == 0 && threadIdx.x == 0) {
-      LamState s;
-      s.lam_prev = st->lam_prev;
-      s.lam_prev2 = st->lam_prev2;
-      lam_first_candidates(s);
-      for (int j = 0; j < kLamFirstCand; ++j) {
-        st->cand[j] = s.cand[j];
-        st->mu[j] = s.mu[j];
-      }
-      st->nc = s.nc;
-      st->k += 1;
-      st->phase = 0;
-    }
+    const float cI = d.st->meanI, cP = d.st->meanP;
     gf_strip<R, CLIP>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
     __syncthreads();
   }
@@ -257,7 +240,7 @@ void gf_geometry(Img &d, int ty) {
     default: break;                                                                                         \
   }
 
-void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool close_iteration) {
+void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   std::map<int, std::vector<int>> byR;  // key 2 r + clip
   for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
@@ -267,11 +250,11 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool 
       append_items(set, i, (d.L.N + d.gfTX - 1) / d.gfTX * d.gfNBY);
     }
     const size_t n = set.items_host.size() - off;
-    const int r = kv.first / 2, close = close_iteration ? 1 : 0;
+    const int r = kv.first / 2;
     const bool clip = (kv.first & 1) != 0;
     const ItemRange range{off, n};
 #define GFD_PLAN_GF(RR) \
-  p.steps.push_back(make_launch(&set, clip ? k_gf_g<RR, true> : k_gf_g<RR, false>, range, kGfThreads, 0, close))
+  p.steps.push_back(make_launch(&set, clip ? k_gf_g<RR, true> : k_gf_g<RR, false>, range, kGfThreads, 0))
     GFD_R_SWITCH(r, GFD_PLAN_GF)
 #undef GFD_PLAN_GF
   }

@@ -103,8 +103,11 @@ __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict_
 }
 
 // Commit the lambda of this iteration (one thread, once the search is finished).  The search
-// state is a private copy `st` that the caller writes back.
-__device__ __forceinline__ void lam_commit(const Img &d, LamState &st) {
+// state is a private copy `st` that the caller writes back.  With `advance` the iteration's
+// bookkeeping is closed as well: the counter moves on and the first candidates of the next
+// search are seeded (nothing later in the iteration reads the counter or the candidates).
+// The search that precedes the first iteration (a warm start) leaves both as they are.
+__device__ __forceinline__ void lam_commit(const Img &d, LamState &st, int advance) {
   const float ls = st.lam_star;
   float lam = ls;
   if (!isinf(ls)) {
@@ -121,6 +124,10 @@ __device__ __forceinline__ void lam_commit(const Img &d, LamState &st) {
     d.lam_hist[st.k] = lam;
     d.flag_hist[st.k] = st.flags;
     if (d.lam_star_hist != nullptr) d.lam_star_hist[st.k] = ls;
+  }
+  if (advance) {
+    st.k += 1;
+    lam_first_candidates(st);
   }
 }
 
@@ -688,7 +695,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
 
 // After the residual pass: one block per image finishes the first round.
 __global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                    LamState *__restrict__ stv) {
+                                                    LamState *__restrict__ stv, int advance) {
   __shared__ float scratch[2 * kLamAcc * 16];
   GFD_ITEM_LOOP
   constexpr int NC = kLamFirstCand;
@@ -700,7 +707,7 @@ __global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, c
     st.flags = 0;
     float cand[NC];
     for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
-    if (lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(d, st);
+    if (lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(d, st, advance);
     stv[wi.img] = st;
   }
   GFD_ITEM_END
@@ -758,7 +765,7 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
 
 // One block per image folds a round into the bracket and picks the next candidates.
 __global__ void __launch_bounds__(1024) k_lam_round(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                    LamState *__restrict__ stv, int last) {
+                                                    LamState *__restrict__ stv, int last, int advance) {
   __shared__ float scratch[2 * kLamAcc * 16];
   constexpr int NC = kLamMaxCand;
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
@@ -772,7 +779,7 @@ __global__ void __launch_bounds__(1024) k_lam_round(const Img *__restrict__ D, c
       float cand[NC];
       for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
       lam_absorb(st, NC, cand, hi, lo, hi + NC);
-      if (lam_decide(st, last != 0)) lam_commit(d, st);
+      if (lam_decide(st, last != 0)) lam_commit(d, st, advance);
       stv[wi.img] = st;
     }
     __syncthreads();
@@ -1128,13 +1135,14 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
   });
 }
 
-void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds) {
+void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, bool advance) {
   ItemRange one = add_one_per_image(set, sel);
-  p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0, set.st_base));
+  const int adv = advance ? 1 : 0;
+  p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0, set.st_base, adv));
   ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
   for (int k = 0; k < rounds; ++k) {
     p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0, (const LamState *)set.st_base));
-    p.steps.push_back(make_launch(&set, k_lam_round, one, 1024, 0, set.st_base, (int)(k == rounds - 1)));
+    p.steps.push_back(make_launch(&set, k_lam_round, one, 1024, 0, set.st_base, (int)(k == rounds - 1), adv));
   }
 }
 
