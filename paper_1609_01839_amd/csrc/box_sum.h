@@ -24,6 +24,9 @@ __device__ __forceinline__ void kahan_slide(Kahan &k, float xn, float xo) {
   k.s = t;
 }
 
+// Running window sum moved by one row: the row xo leaves, xn enters.
+__device__ __forceinline__ void slide(float &s, float xn, float xo) { s = __fadd_rn(s, __fsub_rn(xn, xo)); }
+
 // Pixels of the window of half-width R centred at c (a row or column index) inside [0, n).
 template <int R>
 __device__ __forceinline__ int clip_count(int c, int n) {

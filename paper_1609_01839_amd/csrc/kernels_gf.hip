@@ -3,9 +3,11 @@
 // One block owns a strip of TX output columns and TY output rows and streams down its rows,
 // RB rows per round of barriers.  Every thread owns one column of the strip extended by 2r on
 // each side (r = (w-1)/2):
-//   stage 1: vertical running sums over the last w rows of I, p, I*I, I*p (Kahan-compensated
-//            FP32), then horizontal sliding sums across the block's columns (LDS) -> w x w window
-//            sums -> a_k, b_k (Eqs.(3)-(4)) for one row of windows;
+//   stage 1: vertical running sums over the last w rows of I, p, I*I, I*p (FP32, summed afresh
+//            from the register ring once every w rows and slid by one row in between, so that
+//            rounding errors never accumulate over more than w slides), then horizontal sliding
+//            sums across the block's columns (LDS) -> w x w window sums -> a_k, b_k
+//            (Eqs.(3)-(4)) for one row of windows;
 //   stage 2: the same two-direction sums over a and b -> abar, bbar (Eq.(5)), then
 //            u = abar * I + bbar.
 // The inputs of the last w rows and the coefficients of the last w rows of windows stay in
@@ -74,7 +76,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
     I = uI[g];
     p = uP[g];
   };
-  Kahan sI = {0, 0}, sP = {0, 0}, sII = {0, 0}, sIP = {0, 0}, sA = {0, 0}, sB = {0, 0};
+  float sI = 0.0f, sP = 0.0f, sII = 0.0f, sIP = 0.0f, sA = 0.0f, sB = 0.0f;
   float rI[W], rP[W], rA[W], rB[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) rI[k] = rP[k] = rA[k] = rB[k] = 0.0f;
@@ -102,14 +104,25 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         Ig[q] = rI[sg];  // stream row it - 2r: the guide of this round's output row
         float *vb = vbuf + q * 4 * VP + cj;
         if (active && base + q < nrows) {
-          kahan_slide(sI, I, Io);
-          kahan_slide(sP, p, po);
-          kahan_slide(sII, I * I, Io * Io);
-          kahan_slide(sIP, I * p, Io * po);
-          vb[0] = sI.s;
-          vb[VP] = sP.s;
-          vb[2 * VP] = sII.s;
-          vb[3 * VP] = sIP.s;
+          if (s == W - 1) {  // the ring holds exactly the window's W rows: sum them afresh
+            sI = sP = sII = sIP = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              sI = __fadd_rn(sI, rI[k]);
+              sP = __fadd_rn(sP, rP[k]);
+              sII = __fmaf_rn(rI[k], rI[k], sII);
+              sIP = __fmaf_rn(rI[k], rP[k], sIP);
+            }
+          } else {
+            slide(sI, I, Io);
+            slide(sP, p, po);
+            slide(sII, I * I, Io * Io);
+            slide(sIP, I * p, Io * po);
+          }
+          vb[0] = sI;
+          vb[VP] = sP;
+          vb[2 * VP] = sII;
+          vb[3 * VP] = sIP;
         } else {
           vb[0] = vb[VP] = vb[2 * VP] = vb[3 * VP] = 0.0f;
         }
@@ -148,10 +161,19 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           const float ao = it2 >= W ? rA[slot] : 0.0f, bo = it2 >= W ? rB[slot] : 0.0f;
           rA[slot] = a;
           rB[slot] = b;
-          kahan_slide(sA, a, ao);
-          kahan_slide(sB, b, bo);
-          vb[0] = sA.s;
-          vb[VP] = sB.s;
+          if (slot == W - 1) {  // rows it2 - W + 1 .. it2 of coefficients: sum them afresh
+            sA = sB = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              sA = __fadd_rn(sA, rA[k]);
+              sB = __fadd_rn(sB, rB[k]);
+            }
+          } else {
+            slide(sA, a, ao);
+            slide(sB, b, bo);
+          }
+          vb[0] = sA;
+          vb[VP] = sB;
         } else {
           // Columns without coefficients still enter the first window of a sliding run before
           // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
