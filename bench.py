@@ -32,8 +32,8 @@ ALG_BYTES = {
     "guided_filter": (12, 0),   # read u_I, u_p (8P); write u (4P)
 }
 KERNEL_SYMBOL = {
-    "row_fwd": "k_row_fwd_r16", "col_fwd_resid": "k_col_fwd_r16<true>", "lambda_sweeps": "k_lam_sweep",
-    "col_inv_solve": "k_col_inv_r16", "row_inv": "k_row_inv_r16", "guided_filter": "k_gf_g<8, false>",
+    "row_fwd": "k_row_fwd_r16<4096>", "col_fwd_resid": "k_col_fwd_r16<true, 4096>", "lambda_sweeps": "k_lam_sweep",
+    "col_inv_solve": "k_col_inv_r16<4096>", "row_inv": "k_row_inv_r16<4096>", "guided_filter": "k_gf_g<8, false>",
 }
 
 

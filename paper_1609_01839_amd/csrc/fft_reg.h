@@ -60,6 +60,12 @@ __device__ __forceinline__ void dftR(cf *x) {
   else dft2<DIR>(x);
 }
 
+// Twiddle source of the compile-time transforms: the FP32 table tw[e] = w_L^e of the image.
+struct TwGlobal {
+  const GFD_AS1 cf *__restrict__ tw;
+  __device__ __forceinline__ cf operator()(int e) const { return E(tw, (uint32_t)e); }
+};
+
 // One pass.  `lds` addresses the sequence's region: slot(p) = lds[lds_pad(p) * ls].
 // Inactive threads (blocks sized for a larger image of a batch) only join the barriers.
 template <int R, int DIR>
@@ -77,7 +83,7 @@ __device__ __forceinline__ void reg_pass(cf (&v)[16], int t, int T, int s, int L
     if (s > 1 && active) {
 #pragma unroll
       for (int i = 1; i < R; ++i) {
-        cf w = tw[i * k * tstride];
+        cf w = E(tw, (uint32_t)(i * k * tstride));
         if (DIR > 0) w.im = -w.im;
         x[i] = cmul(x[i], w);
       }
@@ -117,6 +123,72 @@ __device__ __forceinline__ void reg_fft(cf (&v)[16], int t, bool active, const R
       default: reg_pass<2, DIR>(v, t, p.T, s, p.L, last, active, lds, ls, tw); break;
     }
     s *= p.radix[q];
+  }
+}
+
+// Compile-time form for one length L and LDS stride LS (the column passes interleave LS
+// sequences).  Every pass's stride, butterfly count and LDS positions are constants: an
+// exchange computes one LDS address per thread and reaches the other slots through immediate
+// offsets (slot p sits at lds_pad(p) = p + p / 16, and both the write positions base + i s and
+// the read positions t + T m advance by a multiple of 16, so their padded positions advance by
+// a constant), and a butterfly's twiddle indices are multiples of one product.
+template <int R, int DIR, int L, int S, int LS, bool LAST, bool GUARD, class TW>
+__device__ __forceinline__ void reg_pass_c(cf (&v)[16], int t, bool active_, cf *lds, const TW &tw) {
+  const bool active = !GUARD || active_;
+  constexpr int T = L / 16, NBF = 16 / R, TSTRIDE = L / (S * R);
+  static_assert(T % 16 == 0 && ((S == 1 && R == 16) || S % 16 == 0), "padded positions advance linearly");
+  constexpr int WSTEP = S == 1 ? 1 : S + S / 16;  // lds_pad(base + (i + 1) S) - lds_pad(base + i S)
+  constexpr int RSTEP = T + T / 16;               // lds_pad(t + T (m + 1)) - lds_pad(t + T m)
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int j = t + T * b;
+    const int k = j & (S - 1);
+    cf x[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = v[b + i * NBF];
+    if (S > 1 && active) {
+      const int e1 = k * TSTRIDE;
+#pragma unroll
+      for (int i = 1; i < R; ++i) {
+        cf w = tw(i * e1);
+        if (DIR > 0) w.im = -w.im;
+        x[i] = cmul(x[i], w);
+      }
+    }
+    dftR<R, DIR>(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) v[b + i * NBF] = x[i];
+    } else if (active) {
+      cf *w0 = lds + lds_pad((j - k) * R + k) * LS;
+#pragma unroll
+      for (int i = 0; i < R; ++i) w0[i * WSTEP * LS] = x[i];
+    }
+  }
+  if constexpr (!LAST) {
+    __syncthreads();
+    if (active) {
+      const cf *r0 = lds + lds_pad(t) * LS;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) v[m] = r0[m * RSTEP * LS];
+    }
+    __syncthreads();
+  }
+}
+
+// GUARD = false: every thread of the block holds a sequence (`active` is ignored), so the
+// passes carry no per-thread branches.
+template <int L, int DIR, int LS, bool GUARD = true, class TW>
+__device__ __forceinline__ void reg_fft_c(cf (&v)[16], int t, bool active, cf *lds, const TW &tw) {
+  static_assert(L >= 256 && L <= 4096 && (L & (L - 1)) == 0, "power of two in [256, 4096]");
+  constexpr int rest = L / 256;
+  if constexpr (rest == 1) {
+    reg_pass_c<16, DIR, L, 1, LS, false, GUARD>(v, t, active, lds, tw);
+    reg_pass_c<16, DIR, L, 16, LS, true, GUARD>(v, t, active, lds, tw);
+  } else {
+    reg_pass_c<16, DIR, L, 1, LS, false, GUARD>(v, t, active, lds, tw);
+    reg_pass_c<16, DIR, L, 16, LS, false, GUARD>(v, t, active, lds, tw);
+    reg_pass_c<rest, DIR, L, 256, LS, true, GUARD>(v, t, active, lds, tw);
   }
 }
 

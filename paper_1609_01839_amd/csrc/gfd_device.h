@@ -18,12 +18,46 @@ namespace gfd {
 template <class T> __device__ __forceinline__ GFD_AS1 T *G(T *p) { return (GFD_AS1 T *)p; }
 template <class T> __device__ __forceinline__ const GFD_AS1 T *G(const T *p) { return (const GFD_AS1 T *)p; }
 
+// Element i of a global array through a 32-bit unsigned byte offset (every array here is far
+// below 4 GiB): the access then takes the SGPR base plus one VGPR offset instead of a 64-bit
+// address computed per element.
+template <class T> __device__ __forceinline__ const GFD_AS1 T &E(const GFD_AS1 T *p, uint32_t i) {
+  return *reinterpret_cast<const GFD_AS1 T *>(reinterpret_cast<const GFD_AS1 char *>(p) + i * (uint32_t)sizeof(T));
+}
+template <class T> __device__ __forceinline__ GFD_AS1 T &E(GFD_AS1 T *p, uint32_t i) {
+  return *reinterpret_cast<GFD_AS1 T *>(reinterpret_cast<GFD_AS1 char *>(p) + i * (uint32_t)sizeof(T));
+}
+
+// A global array addressed in bytes as base + soff + voff: soff is the same for the whole
+// block (scalar arithmetic), voff a 32-bit per-thread offset, so the accesses of one thread at
+// block-uniform distances share one address register and need no 64-bit arithmetic.
+struct GBytes {
+  GFD_AS1 char *p;
+};
+__device__ __forceinline__ GBytes gbytes(const void *base) { return GBytes{(GFD_AS1 char *)base}; }
+__device__ __forceinline__ float ld_f(GBytes b, uint32_t voff, uint32_t soff) {
+  return *reinterpret_cast<const GFD_AS1 float *>(b.p + soff + voff);
+}
+__device__ __forceinline__ void st_f(float v, GBytes b, uint32_t voff, uint32_t soff) {
+  *reinterpret_cast<GFD_AS1 float *>(b.p + soff + voff) = v;
+}
+__device__ __forceinline__ void st_f4(float x, float y, float z, float w, GBytes b, uint32_t voff, uint32_t soff) {
+  *reinterpret_cast<GFD_AS1 float4 *>(b.p + soff + voff) = make_float4(x, y, z, w);
+}
+
 template <class T>
 struct alignas(2 * sizeof(T)) cpx {
   T re, im;
 };
 using cf = cpx<float>;
 using cd = cpx<double>;
+
+__device__ __forceinline__ cf ld_cf(GBytes b, uint32_t voff, uint32_t soff) {
+  return *reinterpret_cast<const GFD_AS1 cf *>(b.p + soff + voff);
+}
+__device__ __forceinline__ void st_cf(cf v, GBytes b, uint32_t voff, uint32_t soff) {
+  *reinterpret_cast<GFD_AS1 cf *>(b.p + soff + voff) = v;
+}
 
 template <class T> __device__ __forceinline__ cpx<T> mk(T a, T b) { return cpx<T>{a, b}; }
 template <class T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }

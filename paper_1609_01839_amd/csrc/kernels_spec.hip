@@ -426,6 +426,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 // and last passes straight from / to global memory.  Threads beyond an image's need (blocks
 // sized for a larger image of the batch) only join the barriers.
 
+template <int LF>
 __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -439,42 +440,74 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
   const int r0 = wi.blk * R;
   const int ra = r0 + 2 * seq, rb = ra + 1;
   cf v[16];
-  if (active) {
+  {  // every load is issued (rows clamped into the image), the values are selected afterwards
+    const GFD_AS1 float *u = G(d.uE);
+    const uint32_t oa = (uint32_t)min(ra, M - 1) * (uint32_t)N + (uint32_t)t;
+    const uint32_t ob = (uint32_t)min(rb, M - 1) * (uint32_t)N + (uint32_t)t;
+    const bool ua = active && ra < M, ub = active && rb < M;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      const int n = t + T * m;
-      v[m] = cf{ra < M ? G(d.uE)[(size_t)ra * N + n] : 0.0f, rb < M ? G(d.uE)[(size_t)rb * N + n] : 0.0f};
+      const float a = E(u + (size_t)T * m, oa), b = E(u + (size_t)T * m, ob);
+      v[m] = cf{ua ? a : 0.0f, ub ? b : 0.0f};
     }
   }
   cf *my = lds + seq * LP;
-  reg_fft<-1>(v, t, active, d.rn, my, 1, G(d.twN));
+  if constexpr (LF != 0) reg_fft_c<LF, -1, 1>(v, t, active, my, TwGlobal{G(d.twN)});
+  else reg_fft<-1>(v, t, active, d.rn, my, 1, G(d.twN));
   if (active) {
+    cf *w0 = my + lds_pad(t);
+    const int st = T + T / 16;  // T is a multiple of 16
 #pragma unroll
-    for (int m = 0; m < 16; ++m) my[lds_pad(t + T * m)] = v[m];
+    for (int m = 0; m < 16; ++m) w0[m * st] = v[m];
   }
   __syncthreads();
   const int C = lay.C, per_t = R * C, Wh = lay.Wh;
-  const int total = lay.NT * per_t;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int tt = fdiv(e, lay.RfCdiv), rem = e - tt * per_t;
+  if ((blockDim.x & (per_t - 1)) == 0) {
+    // every thread keeps one (row, column-in-tile) pair and walks the tiles
+    const int lp = __ffs(per_t) - 1;
+    const int rem = threadIdx.x & (per_t - 1);
     const int rho = rem >> lay.logC, c = rem & (C - 1);
     const int m = r0 + rho;
-    if (m >= M) continue;
-    const int k = tt * C + c;
-    cf X = {0.0f, 0.0f};
-    if (k < Wh) {
+    if (m < M) {
+      const int tstep = blockDim.x >> lp, tt0 = threadIdx.x >> lp;
       const cf *z = lds + (rho >> 1) * LP;
-      const cf Zk = z[lds_pad(k)], Zn = z[lds_pad(k == 0 ? 0 : N - k)];
-      if ((rho & 1) == 0) X = cf{(Zk.re + Zn.re) * 0.5f, (Zk.im - Zn.im) * 0.5f};
-      else X = cf{(Zk.im + Zn.im) * 0.5f, (Zn.re - Zk.re) * 0.5f};
+      const bool odd = (rho & 1) != 0;
+      const uint32_t ostep = (uint32_t)tstep * (uint32_t)M * (uint32_t)C;
+      uint32_t o = ((uint32_t)tt0 * (uint32_t)M + (uint32_t)m) * (uint32_t)C + (uint32_t)c;
+      for (int tt = tt0; tt < lay.NT; tt += tstep, o += ostep) {
+        const int k = tt * C + c;
+        cf X = {0.0f, 0.0f};
+        if (k < Wh) {
+          const cf Zk = z[lds_pad(k)], Zn = z[lds_pad(k == 0 ? 0 : N - k)];
+          X = odd ? cf{(Zk.im + Zn.im) * 0.5f, (Zn.re - Zk.re) * 0.5f}
+                  : cf{(Zk.re + Zn.re) * 0.5f, (Zk.im - Zn.im) * 0.5f};
+        }
+        E(G(d.S1), o) = X;
+      }
     }
-    G(d.S1)[((size_t)tt * M + m) * C + c] = X;
+  } else {
+    const int total = lay.NT * per_t;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int tt = fdiv(e, lay.RfCdiv), rem = e - tt * per_t;
+      const int rho = rem >> lay.logC, c = rem & (C - 1);
+      const int m = r0 + rho;
+      if (m >= M) continue;
+      const int k = tt * C + c;
+      cf X = {0.0f, 0.0f};
+      if (k < Wh) {
+        const cf *z = lds + (rho >> 1) * LP;
+        const cf Zk = z[lds_pad(k)], Zn = z[lds_pad(k == 0 ? 0 : N - k)];
+        if ((rho & 1) == 0) X = cf{(Zk.re + Zn.re) * 0.5f, (Zk.im - Zn.im) * 0.5f};
+        else X = cf{(Zk.im + Zn.im) * 0.5f, (Zn.re - Zk.re) * 0.5f};
+      }
+      G(d.S1)[((size_t)tt * M + m) * C + c] = X;
+    }
   }
   GFD_ITEM_END
 }
 
-template <bool RESID>
-__global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
+template <bool RESID, int LF>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) k_col_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
@@ -484,18 +517,22 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
   const int C = lay.C, T = d.rm.T;
   const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
   const bool active = t < T;
-  const size_t off = (size_t)wi.blk * lay.M * C;
-  GFD_AS1 cf *tile = G(d.S1) + off;
+  // element m of this thread's column sits at byte to + sm * m of the tile: sm * m is the same
+  // for the whole block, to a 32-bit per-thread offset (inactive threads read a valid element
+  // and never use it)
+  const size_t tb = (size_t)wi.blk * lay.M * C;
+  const uint32_t sm = (uint32_t)(T * C * sizeof(cf));
+  const uint32_t to = (uint32_t)(((active ? t : 0) * C + c) * sizeof(cf));
+  const auto rS = gbytes(d.S1 + tb);
   cf v[16];
-  if (active) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = tile[(t + T * m) * C + c];
-  }
-  reg_fft<-1>(v, t, active, d.rm, lds + c, C, G(d.twM));
+  for (int m = 0; m < 16; ++m) v[m] = ld_cf(rS, to, sm * m);
+  if constexpr (LF != 0) reg_fft_c<LF, -1, 2, false>(v, t, active, lds + c, TwGlobal{G(d.twM)});
+  else reg_fft<-1>(v, t, active, d.rm, lds + c, C, G(d.twM));
   if (!RESID) {
     if (active) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) tile[(t + T * m) * C + c] = v[m];
+      for (int m = 0; m < 16; ++m) st_cf(v[m], rS, to, sm * m);
     }
   } else {
     constexpr int NC = kLamFirstCand;
@@ -513,11 +550,11 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
       // to order them against, so the 32 loads are in flight together
       // (padding columns hold zeros in H and Y, so they are loaded like the others)
       cf hv[16], yv[16];
+      const auto rH = gbytes(d.H + tb), rY = gbytes(d.Y + tb);
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        const int e = (t + T * m) * C + c;
-        hv[m] = G(d.H)[off + e];
-        yv[m] = G(d.Y)[off + e];
+        hv[m] = ld_cf(rH, to, sm * m);
+        yv[m] = ld_cf(rY, to, sm * m);
       }
       float qv[16];
 #pragma unroll
@@ -527,11 +564,11 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
         qv[m] = qq;
         first_round_terms<NC>(qq, abs2f(hv[m]), mu, acc);
       }
+      const auto rq = gbytes(d.q + tb);
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        const int e = (t + T * m) * C + c;
-        tile[e] = v[m];
-        G(d.q)[off + e] = qv[m];
+        st_cf(v[m], rS, to, sm * m);
+        st_f(qv[m], rq, to / 2, sm / 2 * m);
       }
     }
     float h, l;
@@ -546,6 +583,7 @@ __global__ void __launch_bounds__(512) k_col_fwd_r16(const Img *__restrict__ D, 
 // are Hermitian, so their inverse transforms are real and the real and imaginary parts of the
 // one transform are the two columns.  The folded column is solved first and parked in LDS, so
 // that it adds no registers to the main solve.
+template <int LF>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) k_col_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -580,16 +618,24 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   // are computed and then zeroed; the means are written after the loop), so the compiler can
   // issue the loads of later rows ahead of the arithmetic of earlier ones.
   cf vp[16], vi[16];
+  // element m of this thread's column: element to + sm * m of the tile (sm * m the same for the
+  // whole block, to a 32-bit per-thread offset)
+  const uint32_t sm = (uint32_t)(T * C), to = (uint32_t)(t * C + c);
+  const auto rS = gbytes(d.S1 + off), rHY = gbytes(d.HY + off);
+  const auto rH2 = gbytes(d.H2 + off), rdM = gbytes(d.dM);
   auto rows = [&](auto mode) {
     constexpr int MODE = decltype(mode)::value;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      const int row = t + T * m;
-      const size_t e = off + (size_t)row * C + c;
       cf Up, Ui;
-      solve_bin_mode<MODE>(sp, G(d.S1)[e], G(d.HY)[e], G(d.H2)[e], G(d.dM)[row] + dk, Up, Ui);
+      solve_bin_mode<MODE>(sp, ld_cf(rS, 8 * to, 8 * sm * m), ld_cf(rHY, 8 * to, 8 * sm * m),
+                           ld_f(rH2, 4 * to, 4 * sm * m), ld_f(rdM, 4 * (uint32_t)t, 4 * (uint32_t)(T * m)) + dk,
+                           Up, Ui);
       vp[m] = valid ? Up : cf{0.0f, 0.0f};
       vi[m] = valid ? Ui : cf{0.0f, 0.0f};
+      // two groups of eight rows: the second group's loads are issued after the first group's
+      // solves, which bounds the loaded operands held in registers
+      if (m == 7) __builtin_amdgcn_sched_barrier(0);
     }
   };
   if (!active) {
@@ -619,27 +665,40 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   }
   // both transforms, then one 16-byte store per bin (U_I, U_p): the two columns of the tile give
   // 32 contiguous bytes per row
-  reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
-  reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
+  if constexpr (LF != 0) {
+    reg_fft_c<LF, +1, 2, false>(vp, t, active, lds + c, TwGlobal{G(d.twM)});
+    // the second transform loads its twiddles again: an opaque copy of the table pointer keeps
+    // the compiler from holding the first transform's twiddles in registers across both
+    const cf *tw2 = d.twM;
+    asm volatile("" : "+s"(tw2));
+    reg_fft_c<LF, +1, 2, false>(vi, t, active, lds + c, TwGlobal{G(tw2)});
+  } else {
+    reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
+    reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
+  }
   if (active) {
     GFD_AS1 float4 *out = reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP));
+    // rows t + T m are rs bytes apart (the same for the whole block)
+    const uint32_t rs = (uint32_t)(T * lay.RP * 16);
+    const auto rO = gbytes(out);
     if (fc) {  // real parts: column 0; imaginary parts: column N/2
+      const uint32_t g0 = (uint32_t)t * (uint32_t)lay.RP * 16u;
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        const size_t g = (size_t)(t + T * m) * lay.RP;
-        out[g] = make_float4(vi[m].re, 0.0f, vp[m].re, 0.0f);
-        out[g + lay.N / 2] = make_float4(vi[m].im, 0.0f, vp[m].im, 0.0f);
+        st_f4(vi[m].re, 0.0f, vp[m].re, 0.0f, rO, g0, rs * m);
+        st_f4(vi[m].im, 0.0f, vp[m].im, 0.0f, rO, g0, rs * m + (uint32_t)(lay.N / 2) * 16u);
       }
     } else {
+      const uint32_t g0 = ((uint32_t)t * (uint32_t)lay.RP + (uint32_t)k) * 16u;
 #pragma unroll
-      for (int m = 0; m < 16; ++m)
-        out[(size_t)(t + T * m) * lay.RP + k] = make_float4(vi[m].re, vi[m].im, vp[m].re, vp[m].im);
+      for (int m = 0; m < 16; ++m) st_f4(vi[m].re, vi[m].im, vp[m].re, vp[m].im, rO, g0, rs * m);
     }
   }
   GFD_ITEM_END
 }
 
 // Row pass, inverse; the Hermitian completion is gathered straight from the tile-major spectra.
+template <int LF>
 __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -656,12 +715,13 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
   if (active) {
     // every load of the row first, then the combination (keeps the 32 loads in flight together)
     cf A[16], B[16];
+    const GFD_AS1 float4 *sip = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP));
+    const uint32_t g0 = (uint32_t)rowc * (uint32_t)lay.RP;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int n = t + T * m;
       const int kk = n < Wh ? n : N - n;
-      const size_t g = (size_t)rowc * lay.RP + kk;
-      const float4 ab = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP))[g];
+      const float4 ab = E(sip, g0 + (uint32_t)kk);
       A[m] = cf{ab.x, ab.y};
       B[m] = cf{ab.z, ab.w};
     }
@@ -675,13 +735,14 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
       v[m] = direct ? cf{A[m].re - bi, ai + B[m].re} : cf{A[m].re + bi, B[m].re - ai};
     }
   }
-  reg_fft<+1>(v, t, active, d.rn, lds + seq * LP, 1, G(d.twN));
+  if constexpr (LF != 0) reg_fft_c<LF, +1, 1>(v, t, active, lds + seq * LP, TwGlobal{G(d.twN)});
+  else reg_fft<+1>(v, t, active, d.rn, lds + seq * LP, 1, G(d.twN));
   if (active && row < M) {
+    const uint32_t g0 = (uint32_t)row * (uint32_t)N + (uint32_t)t;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
-      const size_t g = (size_t)row * N + t + T * m;
-      G(d.uI)[g] = v[m].re;
-      G(d.uP)[g] = v[m].im;
+      E(G(d.uI) + (size_t)T * m, g0) = v[m].re;
+      E(G(d.uP) + (size_t)T * m, g0) = v[m].im;
     }
   }
   GFD_ITEM_END
@@ -1067,7 +1128,12 @@ static int pick_E(size_t elems, int &threads) {
 }
 
 // Group images by a key and call `emit` for each group.
-using GKey = std::tuple<int, int, int>;  // (register-resident?, threads, E)
+using GKey = std::tuple<int, int, int>;  // (register-resident?, threads or compile-time length, E)
+
+// Length of the compile-time register-resident transform for a pass of length L whose
+// sequences are interleaved LS apart in LDS (1 in the row passes, the tile width C in the
+// column passes), given the interleave the kernel is compiled for; 0: the run-time transform.
+static int fixed_len(int L, int LS, int compiled_LS) { return L == 4096 && LS == compiled_LS ? 4096 : 0; }
 static void group_by(const ImgSet &set, const std::vector<int> &sel, const std::function<GKey(const Img &)> &key,
                      const std::function<void(const GKey &, const std::vector<int> &)> &emit) {
   std::map<GKey, std::vector<int>> g;
@@ -1082,7 +1148,7 @@ static auto pickE(int E, K4 a, K8 b, K16 c) {
 
 void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.N)) return GKey{1, 0, 0};
+    if (reg_plan_ok(d.L.N)) return GKey{1, fixed_len(d.L.N, 1, 1), 0};
     int th; int E = pick_E((size_t)(d.L.R / 2) * d.L.N, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1094,7 +1160,7 @@ void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         lds = std::max(lds, (size_t)(d.L.Rf / 2) * (d.L.N + d.L.N / 16) * sizeof(cf));
       }
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Rf - 1) / d.L.Rf; });
-      p.steps.push_back(make_launch(&set, k_row_fwd_r16, r, threads, lds));
+      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_fwd_r16<4096> : k_row_fwd_r16<0>, r, threads, lds));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1107,7 +1173,7 @@ void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
 
 void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.M)) return GKey{1, 0, 0};
+    if (reg_plan_ok(d.L.M)) return GKey{1, fixed_len(d.L.M, d.L.C, 2), 0};
     int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1119,8 +1185,10 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
         threads = std::max(threads, d.L.C * d.rm.T);
         lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
       }
-      p.steps.push_back(resid ? make_launch(&set, k_col_fwd_r16<true>, r, threads, lds)
-                              : make_launch(&set, k_col_fwd_r16<false>, r, threads, lds));
+      const bool fx = std::get<1>(k) != 0;
+      p.steps.push_back(resid ? make_launch(&set, fx ? k_col_fwd_r16<true, 4096> : k_col_fwd_r16<true, 0>, r, threads, lds)
+                              : make_launch(&set, fx ? k_col_fwd_r16<false, 4096> : k_col_fwd_r16<false, 0>, r, threads,
+                                            lds));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1148,7 +1216,7 @@ void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, 
 
 void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.M)) return GKey{1, 0, 0};
+    if (reg_plan_ok(d.L.M)) return GKey{1, fixed_len(d.L.M, d.L.C, 2), 0};
     int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1161,7 +1229,7 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         threads = std::max(threads, d.L.C * d.rm.T);
         lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
       }
-      p.steps.push_back(make_launch(&set, k_col_inv_r16, r, threads, lds));
+      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_col_inv_r16<4096> : k_col_inv_r16<0>, r, threads, lds));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1173,7 +1241,7 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
 
 void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.N)) return GKey{1, 0, 0};
+    if (reg_plan_ok(d.L.N)) return GKey{1, fixed_len(d.L.N, 1, 1), 0};
     int th; int E = pick_E((size_t)d.L.R * d.L.N, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1185,7 +1253,7 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         lds = std::max(lds, (size_t)d.L.Ri * (d.L.N + d.L.N / 16) * sizeof(cf));
       }
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Ri - 1) / d.L.Ri; });
-      p.steps.push_back(make_launch(&set, k_row_inv_r16, r, threads, lds));
+      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_inv_r16<4096> : k_row_inv_r16<0>, r, threads, lds));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
