@@ -106,7 +106,9 @@ __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict_
 // state is a private copy `st` that the caller writes back.  With `advance` the iteration's
 // bookkeeping is closed as well: the counter moves on and the first candidates of the next
 // search are seeded (nothing later in the iteration reads the counter or the candidates).
-// The search that precedes the first iteration (a warm start) leaves both as they are.
+// A search that precedes the first iteration (a warm start, `advance` = 0) keeps the counter;
+// the next search has the same estimate and hence the same root, so its candidates are seeded
+// around lambda_star with the narrowest spacing.
 __device__ __forceinline__ void lam_commit(const Img &d, LamState &st, int advance) {
   const float ls = st.lam_star;
   float lam = ls;
@@ -127,6 +129,9 @@ __device__ __forceinline__ void lam_commit(const Img &d, LamState &st, int advan
   }
   if (advance) {
     st.k += 1;
+    lam_first_candidates(st);
+  } else if (!isinf(ls) && !(st.flags & kFlagNoRoot)) {
+    st.lam_prev2 = st.lam_prev;
     lam_first_candidates(st);
   }
 }
@@ -545,30 +550,29 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     const int k = wi.blk * C + c;
     const bool valid = active && k < lay.Wh;
     const float wgt = (k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f;
+    __builtin_amdgcn_sched_barrier(0);  // H and Y are not loaded before the transform is done
     if (active) {
-      // all loads first, stores last: no store between the loads that the compiler would have
-      // to order them against, so the 32 loads are in flight together
-      // (padding columns hold zeros in H and Y, so they are loaded like the others)
-      cf hv[16], yv[16];
-      const auto rH = gbytes(d.H + tb), rY = gbytes(d.Y + tb);
+      // two halves of eight bins: the 16 loads of a half are in flight together, and each bin's
+      // U_E and q are stored as soon as q is known (padding columns hold zeros in H and Y, so
+      // they are loaded like the others)
+      const auto rH = gbytes(d.H + tb), rY = gbytes(d.Y + tb), rq = gbytes(d.q + tb);
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        hv[m] = ld_cf(rH, to, sm * m);
-        yv[m] = ld_cf(rY, to, sm * m);
-      }
-      float qv[16];
+      for (int h0 = 0; h0 < 16; h0 += 8) {
+        cf hv[8], yv[8];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const cf r = cmul(hv[m], v[m]) - yv[m];
-        const float qq = valid ? wgt * abs2f(r) : 0.0f;
-        qv[m] = qq;
-        first_round_terms<NC>(qq, abs2f(hv[m]), mu, acc);
-      }
-      const auto rq = gbytes(d.q + tb);
+        for (int i = 0; i < 8; ++i) {
+          hv[i] = ld_cf(rH, to, sm * (h0 + i));
+          yv[i] = ld_cf(rY, to, sm * (h0 + i));
+        }
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        st_cf(v[m], rS, to, sm * m);
-        st_f(qv[m], rq, to / 2, sm / 2 * m);
+        for (int i = 0; i < 8; ++i) {
+          const int m = h0 + i;
+          const cf r = cmul(hv[i], v[m]) - yv[i];
+          const float qq = valid ? wgt * abs2f(r) : 0.0f;
+          st_cf(v[m], rS, to, sm * m);
+          st_f(qq, rq, to / 2, sm / 2 * m);
+          first_round_terms<NC>(qq, abs2f(hv[i]), mu, acc);
+        }
       }
     }
     float h, l;

@@ -34,7 +34,10 @@
 namespace gfd {
 
 constexpr int kLamMaxCand = 8;     // candidates per evaluation round
-constexpr int kLamFirstCand = 8;   // candidates folded into the residual pass
+// candidates folded into the residual pass: around the previous lambda_star the first round
+// decides as often with 4 as with 8 (the spacing follows the last change), and each one costs
+// a reciprocal and six more operations per bin in that pass
+constexpr int kLamFirstCand = 4;
 constexpr float kLamFloor = 1e-30f;
 constexpr float kLamCeil = 1e30f;
 
@@ -81,14 +84,17 @@ GFD_HD inline void lam_set_cand(LamState &s, int n, const float *c) {
 
 // First candidates of an iteration: around the previous lambda_star when there is one, spaced
 // by the size of the last change (so that a settled sequence is bracketed tightly and a jump
-// is still caught), otherwise spread over the whole admissible range.
+// is still caught), otherwise spread over the whole admissible range.  Around the previous
+// root two close candidates (+-sp/2) give a tight bracket for a settled sequence and two far
+// ones (+-3.5 sp) catch a jump.
 GFD_HD inline void lam_first_candidates(LamState &s) {
+  static_assert(kLamFirstCand == 4, "offsets below are for four candidates");
+  const float off[kLamFirstCand] = {-3.5f, -0.5f, 0.5f, 3.5f};
   float c[kLamFirstCand];
   if (s.lam_prev > 0.0f) {
     float sp = 1.0f;
     if (s.lam_prev2 > 0.0f) sp = fminf(fmaxf(1.5f * fabsf(logf(s.lam_prev / s.lam_prev2)), 0.02f), 1.0f);
-    for (int j = 0; j < kLamFirstCand; ++j)
-      c[j] = s.lam_prev * GFD_QEXP(sp * ((float)j - 0.5f * (kLamFirstCand - 1)));
+    for (int j = 0; j < kLamFirstCand; ++j) c[j] = s.lam_prev * GFD_QEXP(sp * off[j]);
   } else {
     const float x0 = logf(kLamFloor), x1 = logf(kLamCeil);
     for (int j = 0; j < kLamFirstCand; ++j)
