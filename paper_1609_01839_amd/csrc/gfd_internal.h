@@ -35,6 +35,10 @@ struct Layout {
   int fold;
   __host__ __device__ int col_blocks() const { return NT - fold; }
   __host__ __device__ size_t bins() const { return (size_t)NT * M * C; }
+  // tile-major position of bin (m, k): tile k / C, row m, column k % C
+  __host__ __device__ size_t tpos(int m, int k) const {
+    return ((size_t)(k >> logC) * M + m) * C + (k & (C - 1));
+  }
 };
 
 // Launch-shape choices that do not change results (the autotuner's knobs); 0 = default.
@@ -66,8 +70,9 @@ struct Img {
   float *uE, *uI, *uP;   // images (u_E is also the filter's output)
   float *q;              // Hermitian-weighted |R|^2, tile-major
   cf *S1;                // spectra: row transforms, then U_E
-  cf *SIP;               // the two solves after the column inverse, row-major and interleaved:
-                         // bin (m, k) holds U_I at SIP[2 (m RP + k)] and U_p right after it
+  cf *SIP;               // the two solves after the column inverse, tile-major like S1 and
+                         // interleaved: bin (m, k) of tile t = k / C, column c = k % C holds
+                         // U_I at SIP[2 e] and U_p at SIP[2 e + 1], e = (t M + m) C + c
   float *part;           // partial sums, [2 * kLamAcc][npart]
   int npart;             // stride of `part` (>= NT and >= nchunk)
   int nchunk;            // blocks of a lambda evaluation round

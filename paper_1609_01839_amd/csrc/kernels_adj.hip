@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, c
     if (active) {
 #pragma unroll
       for (int m = 0; m < 16; ++m)
-        reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP))[(size_t)(t + T * m) * lay.RP + k] = make_float4(v[m].re, v[m].im, 0.0f, 0.0f);
+        reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP))[off + (size_t)(t + T * m) * C + c] = make_float4(v[m].re, v[m].im, 0.0f, 0.0f);
     }
     __syncthreads();
   }
@@ -454,8 +454,7 @@ __global__ void __launch_bounds__(1024) k_adjcol_g(const Img *__restrict__ D, co
     __syncthreads();
     lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
-      const size_t g = (size_t)(e >> lay.logC) * lay.RP + wi.blk * C + (e & (C - 1));
-      reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP))[g] = make_float4(buf[e].re, buf[e].im, 0.0f, 0.0f);
+      reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP))[off + e] = make_float4(buf[e].re, buf[e].im, 0.0f, 0.0f);
     }
     __syncthreads();
   }

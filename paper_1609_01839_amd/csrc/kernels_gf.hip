@@ -72,9 +72,9 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   // one round ahead: a round first consumes the rows loaded during the previous round, then
   // issues the next loads, and only then does its LDS work.
   auto fetch = [&](int it, float &I, float &p) {
-    const size_t g = (size_t)wrap(ybase + min(it, nrows - 1), M) * N + gx;
-    I = uI[g];
-    p = uP[g];
+    const uint32_t g = (uint32_t)wrap(ybase + min(it, nrows - 1), M) * (uint32_t)N + (uint32_t)gx;
+    I = E(uI, g);
+    p = E(uP, g);
   };
   float sI = 0.0f, sP = 0.0f, sII = 0.0f, sIP = 0.0f, sA = 0.0f, sB = 0.0f;
   float rI[W], rP[W], rA[W], rB[W];
@@ -197,7 +197,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           const float *hb = hbuf + q * 2 * kHsOut + hj;
           const float nrm = CLIP ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yo, M) * ncol)) : inv_w2;
           const float abar = hb[0] * nrm, bbar = hb[kHsOut] * nrm;
-          u[(size_t)yo * N + xo] = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
+          E(u, (uint32_t)yo * (uint32_t)N + (uint32_t)xo) = __fadd_rn(__fmaf_rn(abar, Ig[q], bbar), cP);
         }
       }
       // the next round's first barrier orders these hbuf reads before hbuf is rewritten

@@ -370,8 +370,7 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-  for (int e = threadIdx.x; e < n; e += blockDim.x)
-    G(d.SIP)[2 * ((size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1))) + 1] = buf[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SIP)[2 * (off + e) + 1] = buf[e];
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < E; ++u) {
@@ -380,8 +379,7 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   }
   __syncthreads();
   lds_fft<float, E, +1, true>(buf, C, lay.logC, C, 1, d.pm, G(d.twM));
-  for (int e = threadIdx.x; e < n; e += blockDim.x)
-    G(d.SIP)[2 * ((size_t)(e >> lay.logC) * lay.RP + kbase + (e & (C - 1)))] = buf[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) G(d.SIP)[2 * (off + e)] = buf[e];
   GFD_ITEM_END
 }
 
@@ -403,7 +401,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
     cf *z = buf + rho * LP;
 #pragma unroll 4
     for (int k = threadIdx.x; k < Wh; k += blockDim.x) {
-      const size_t g = (size_t)m * lay.RP + k;
+      const size_t g = lay.tpos(m, k);
       cf A = G(d.SIP)[2 * g], B = G(d.SIP)[2 * g + 1];
       if (k == 0 || 2 * k == N) {
         A.im = 0.0f;
@@ -681,21 +679,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
   }
   if (active) {
-    GFD_AS1 float4 *out = reinterpret_cast<GFD_AS1 float4 *>(G(d.SIP));
-    // rows t + T m are rs bytes apart (the same for the whole block)
-    const uint32_t rs = (uint32_t)(T * lay.RP * 16);
-    const auto rO = gbytes(out);
-    if (fc) {  // real parts: column 0; imaginary parts: column N/2
-      const uint32_t g0 = (uint32_t)t * (uint32_t)lay.RP * 16u;
+    // the solved spectra are tile-major like the inputs: the bins of this thread sit at the
+    // same elements to + sm * m of the tile, and a wave's 16-byte stores are contiguous
+    const auto rO = gbytes(reinterpret_cast<float4 *>(d.SIP) + off);
+    if (fc) {  // real parts: column 0 (this tile); imaginary parts: column N/2 (column 0 of the last tile)
+      const auto rN = gbytes(reinterpret_cast<float4 *>(d.SIP) + (size_t)(lay.NT - 1) * lay.M * C);
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        st_f4(vi[m].re, 0.0f, vp[m].re, 0.0f, rO, g0, rs * m);
-        st_f4(vi[m].im, 0.0f, vp[m].im, 0.0f, rO, g0, rs * m + (uint32_t)(lay.N / 2) * 16u);
+        st_f4(vi[m].re, 0.0f, vp[m].re, 0.0f, rO, 16 * to, 16 * sm * m);
+        st_f4(vi[m].im, 0.0f, vp[m].im, 0.0f, rN, 16 * to, 16 * sm * m);
       }
     } else {
-      const uint32_t g0 = ((uint32_t)t * (uint32_t)lay.RP + (uint32_t)k) * 16u;
 #pragma unroll
-      for (int m = 0; m < 16; ++m) st_f4(vi[m].re, vi[m].im, vp[m].re, vp[m].im, rO, g0, rs * m);
+      for (int m = 0; m < 16; ++m) st_f4(vi[m].re, vi[m].im, vp[m].re, vp[m].im, rO, 16 * to, 16 * sm * m);
     }
   }
   GFD_ITEM_END
@@ -720,12 +716,13 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
     // every load of the row first, then the combination (keeps the 32 loads in flight together)
     cf A[16], B[16];
     const GFD_AS1 float4 *sip = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP));
-    const uint32_t g0 = (uint32_t)rowc * (uint32_t)lay.RP;
+    // tile-major: bin (row, kk) at ((kk / C) M + row) C + kk % C
+    const uint32_t g0 = (uint32_t)rowc << lay.logC, ts = (uint32_t)M << lay.logC, cm = (uint32_t)(lay.C - 1);
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int n = t + T * m;
-      const int kk = n < Wh ? n : N - n;
-      const float4 ab = E(sip, g0 + (uint32_t)kk);
+      const uint32_t kk = (uint32_t)(n < Wh ? n : N - n);
+      const float4 ab = E(sip, (kk >> lay.logC) * ts + g0 + (kk & cm));
       A[m] = cf{ab.x, ab.y};
       B[m] = cf{ab.z, ab.w};
     }
