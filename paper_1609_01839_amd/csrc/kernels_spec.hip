@@ -710,31 +710,52 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
   const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
   const bool active = seq < lay.Ri;
   const int row = wi.blk * lay.Ri + seq;
-  const int rowc = row < M ? row : M - 1;  // rows past the end compute a copy, never stored
   cf v[16];
-  if (active) {
-    // every load of the row first, then the combination (keeps the 32 loads in flight together)
-    cf A[16], B[16];
+  {
+    // The block's Ri rows are gathered together: in every tile they are Ri C consecutive 16-byte
+    // words (bins of Ri rows, C columns), so each word is loaded once (a row's bins k and N - k
+    // share one) in runs of Ri C words, and staged in LDS (rows past the end load a copy of the
+    // last row, never stored); then every thread picks its bins with the Hermitian completion.
+    // The staging memory is the transform's exchange area, free until the transform.
+    const int Ri = lay.Ri, C = lay.C, logC = lay.logC;
+    const int per = Ri << logC, lper = __ffs(per) - 1;  // words per tile (a power of two)
+    const int total = lay.NT * per, SP = lay.RP + 4;    // SP: staged row pitch in words
+    float4 *stage = reinterpret_cast<float4 *>(smem_raw);
     const GFD_AS1 float4 *sip = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP));
-    // tile-major: bin (row, kk) at ((kk / C) M + row) C + kk % C
-    const uint32_t g0 = (uint32_t)rowc << lay.logC, ts = (uint32_t)M << lay.logC, cm = (uint32_t)(lay.C - 1);
+    const int r0 = wi.blk * Ri;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * blockDim.x) {
+      float4 w[8];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int n = t + T * m;
-      const uint32_t kk = (uint32_t)(n < Wh ? n : N - n);
-      const float4 ab = E(sip, (kk >> lay.logC) * ts + g0 + (kk & cm));
-      A[m] = cf{ab.x, ab.y};
-      B[m] = cf{ab.z, ab.w};
-    }
+      for (int u = 0; u < 8; ++u) {  // loads first: the eight are in flight together
+        const int e = min(e0 + u * (int)blockDim.x, total - 1);
+        const int tile = e >> lper, rem = e & (per - 1);
+        const uint32_t m = (uint32_t)min(r0 + (rem >> logC), M - 1);
+        w[u] = E(sip, ((uint32_t)tile * (uint32_t)M + m) * (uint32_t)C + (uint32_t)(rem & (C - 1)));
+      }
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int n = t + T * m;
-      const bool direct = n < Wh;
-      const int kk = direct ? n : N - n;
-      const bool real_col = kk == 0 || 2 * kk == N;
-      const float ai = real_col ? 0.0f : A[m].im, bi = real_col ? 0.0f : B[m].im;
-      v[m] = direct ? cf{A[m].re - bi, ai + B[m].re} : cf{A[m].re + bi, B[m].re - ai};
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < total) {
+          const int tile = e >> lper, rem = e & (per - 1);
+          stage[(rem >> logC) * SP + (tile << logC) + (rem & (C - 1))] = w[u];
+        }
+      }
     }
+    __syncthreads();
+    if (active) {
+      const float4 *my = stage + seq * SP;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int n = t + T * m;
+        const bool direct = n < Wh;
+        const int kk = direct ? n : N - n;
+        const float4 ab = my[kk];
+        const bool real_col = kk == 0 || 2 * kk == N;
+        const float ai = real_col ? 0.0f : ab.y, bi = real_col ? 0.0f : ab.w;
+        v[m] = direct ? cf{ab.x - bi, ai + ab.z} : cf{ab.x + bi, ab.z - ai};
+      }
+    }
+    __syncthreads();  // the staged words are read before the transform writes the LDS
   }
   if constexpr (LF != 0) reg_fft_c<LF, +1, 1>(v, t, active, lds + seq * LP, TwGlobal{G(d.twN)});
   else reg_fft<+1>(v, t, active, d.rn, lds + seq * LP, 1, G(d.twN));
@@ -1251,7 +1272,9 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
       for (int i : imgs) {
         const Img &d = set.imgs[i];
         threads = std::max(threads, d.L.Ri * d.rn.T);
+        // the transform's exchange area, which first holds the staged 16-byte words of the rows
         lds = std::max(lds, (size_t)d.L.Ri * (d.L.N + d.L.N / 16) * sizeof(cf));
+        lds = std::max(lds, (size_t)d.L.Ri * (d.L.RP + 4) * 16);
       }
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Ri - 1) / d.L.Ri; });
       p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_inv_r16<4096> : k_row_inv_r16<0>, r, threads, lds));
