@@ -103,7 +103,9 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         rP[s] = p;
         Ig[q] = rI[sg];  // stream row it - 2r: the guide of this round's output row
         float *vb = vbuf + q * 4 * VP + cj;
-        if (active && base + q < nrows) {
+        // Threads past the strip's columns (narrow images) run the same arithmetic on their
+        // clamped, finite inputs and store zeros: a select per value, no divergent branch.
+        if (base + q < nrows) {  // uniform
           if (s == W - 1) {  // the ring holds exactly the window's W rows: sum them afresh
             sI = sP = sII = sIP = 0.0f;
 #pragma unroll
@@ -119,10 +121,10 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
             slide(sII, I * I, Io * Io);
             slide(sIP, I * p, Io * po);
           }
-          vb[0] = sI;
-          vb[VP] = sP;
-          vb[2 * VP] = sII;
-          vb[3 * VP] = sIP;
+          vb[0] = active ? sI : 0.0f;
+          vb[VP] = active ? sP : 0.0f;
+          vb[2 * VP] = active ? sII : 0.0f;
+          vb[3 * VP] = active ? sIP : 0.0f;
         } else {
           vb[0] = vb[VP] = vb[2 * VP] = vb[3 * VP] = 0.0f;
         }
@@ -141,7 +143,8 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         const int it = base + q;
         const int it2 = it - (W - 1);  // row index of (a, b) in the stage-2 stream
         float *vb = vbuf + q * 2 * VP + cj;
-        if (it < nrows && it2 >= 0 && j >= R && j < used - R) {
+        const bool cvalid = j >= R && j < used - R;  // columns with coefficients (selects below)
+        if (it < nrows && it2 >= 0) {  // uniform
           const float *hb = hbuf + q * 4 * kHsOut + hj;
           float nrm = inv_w2;
           bool cin = true;
@@ -172,11 +175,11 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
             slide(sA, a, ao);
             slide(sB, b, bo);
           }
-          vb[0] = sA;
-          vb[VP] = sB;
-        } else {
           // Columns without coefficients still enter the first window of a sliding run before
-          // they are subtracted again: keep them zero, never a stale (large) stage-1 sum.
+          // they are subtracted again: they hold zeros, never a stale (large) stage-1 sum.
+          vb[0] = cvalid ? sA : 0.0f;
+          vb[VP] = cvalid ? sB : 0.0f;
+        } else {
           vb[0] = 0.0f;
           vb[VP] = 0.0f;
         }
@@ -224,7 +227,7 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
 
 // Stand-alone filter: the offsets are the first pixels of the inputs.
 template <int R, bool CLIP>
-__global__ void __launch_bounds__(kGfThreads) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
+__global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
                                                          float *__restrict__ u, int M, int N, float eps, int TX,
                                                          int TY, int nby) {
   __shared__ __align__(16) GfLds<R> sh;

@@ -723,17 +723,20 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
     float4 *stage = reinterpret_cast<float4 *>(smem_raw);
     const GFD_AS1 float4 *sip = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP));
     const int r0 = wi.blk * Ri;
-    for (int e0 = threadIdx.x; e0 < total; e0 += 8 * blockDim.x) {
-      float4 w[8];
+    // kU words per thread in one batch of loads (with 8 a second batch waited a whole memory
+    // latency for the few words of the last tile; indices past the end repeat the last word)
+    constexpr int kU = 9;
+    for (int e0 = threadIdx.x; e0 < total; e0 += kU * blockDim.x) {
+      float4 w[kU];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {  // loads first: the eight are in flight together
+      for (int u = 0; u < kU; ++u) {  // loads first: they are in flight together
         const int e = min(e0 + u * (int)blockDim.x, total - 1);
         const int tile = e >> lper, rem = e & (per - 1);
         const uint32_t m = (uint32_t)min(r0 + (rem >> logC), M - 1);
         w[u] = E(sip, ((uint32_t)tile * (uint32_t)M + m) * (uint32_t)C + (uint32_t)(rem & (C - 1)));
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * (int)blockDim.x;
         if (e < total) {
           const int tile = e >> lper, rem = e & (per - 1);
