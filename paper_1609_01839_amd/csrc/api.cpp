@@ -1127,10 +1127,19 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
   Tuning best{};
   float best_ms = 0.0f;
   bool ok = trial(best, best_ms);
-  const int gf_ty[] = {32, 64, 96, 128}, seqs[] = {1, 2, 4};
+  // strip heights: a ladder, plus the lowest one whose strips of image 0 fit on the device at once
+  int gf_ty[8] = {32, 48, 64, 80, 96, 112, 128, 0};
+  int ngf = 7;
+  {
+    const int fill = gf_fill_height(c->main.imgs[0]);
+    bool have = fill == 0;
+    for (int i = 0; i < ngf; ++i) have = have || gf_ty[i] == fill;
+    if (!have) gf_ty[ngf++] = fill;
+  }
+  const int seqs[] = {1, 2, 4};
   for (int knob = 0; knob < 3 && ok; ++knob) {
     const int *vals = knob == 0 ? gf_ty : seqs;
-    const int nv = knob == 0 ? 4 : 3;
+    const int nv = knob == 0 ? ngf : 3;
     for (int v = 0; v < nv && ok; ++v) {
       Tuning t = best;
       int &field = knob == 0 ? t.gf_ty : knob == 1 ? t.seq_fwd : t.seq_inv;

@@ -196,6 +196,7 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel);
 hipError_t finalize_items(ImgSet &set);
 void gf_geometry(Img &d, int ty = 0);
+int gf_fill_height(const Img &d);
 bool guided_filter_supported(int w);
 
 // Reverse mode (kernels_adj.hip).

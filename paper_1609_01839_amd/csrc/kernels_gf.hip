@@ -251,6 +251,7 @@ void gf_geometry(Img &d, int ty) {
   gf_tiles(d.L.M, d.L.N, (d.w - 1) / 2, ty, d.gfTX, d.gfTY, nbx, d.gfNBY);
 }
 
+
 #define GFD_R_SWITCH(r, X)                                                                                  \
   switch (r) {                                                                                              \
     case 0: X(0); break;                                                                                    \
@@ -264,6 +265,30 @@ void gf_geometry(Img &d, int ty) {
     case 8: X(8); break;                                                                                    \
     default: break;                                                                                         \
   }
+
+// The lowest strip height (a multiple of 8, at least 32) whose strips of one image all fit on
+// the device at once (one wave of resident blocks); 0 if none does.  Taller strips re-read
+// fewer halo rows; more strips than resident blocks leave a second, mostly idle wave.
+int gf_fill_height(const Img &d) {
+  const int r = (d.w - 1) / 2;
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e = hipErrorInvalidValue;
+#define GFD_OCC(RR)                                                                                   \
+  {                                                                                                   \
+    auto kern = d.clip ? k_gf_g<RR, true> : k_gf_g<RR, false>;                                        \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void *)kern, kGfThreads, 0);        \
+  }
+  GFD_R_SWITCH(r, GFD_OCC)
+#undef GFD_OCC
+  if (e != hipSuccess || per < 1) return 0;
+  const long slots = (long)per * ncu;
+  const int TX = kGfThreads - 4 * r, nbx = (d.L.N + TX - 1) / TX;
+  for (int ty = 32; ty <= d.L.M; ty += 8)
+    if ((long)nbx * ((d.L.M + ty - 1) / ty) <= slots) return ty;
+  return 0;
+}
 
 void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   std::map<int, std::vector<int>> byR;  // key 2 r + clip
