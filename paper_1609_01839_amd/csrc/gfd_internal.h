@@ -30,8 +30,9 @@ struct Layout {
   FastDiv Ndiv;   // division by N
   FastDiv RCdiv;  // division by R * C
   FastDiv RfCdiv; // division by Rf * C
-  // 1: the register-resident column inverse folds column N/2 (alone in the last tile) into the
-  // block of tile 0 as the imaginary part of column 0, so it launches NT - 1 blocks
+  // 1: the register-resident residual pass and column inverse fold column N/2 (alone in the
+  // last tile) into the block of tile 0 as the imaginary part of column 0, so they launch
+  // NT - 1 blocks (the forward pass without the residual launches NT)
   int fold;
   __host__ __device__ int col_blocks() const { return NT - fold; }
   __host__ __device__ size_t bins() const { return (size_t)NT * M * C; }

@@ -509,6 +509,11 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
   GFD_ITEM_END
 }
 
+// With RESID and Layout::fold the block of tile 0 also transforms column N/2 (column 0 of the
+// last tile, which then has no block): after the row transforms columns 0 and N/2 are real, so
+// column N/2 rides in the imaginary part of column 0 and the two are separated after the
+// transform by the symmetry of real-input transforms, F(x)[-k] = conj F(x)[k].  Its residual
+// and first-round terms are added to the block's partial sums.
 template <bool RESID, int LF>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) k_col_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
@@ -523,13 +528,20 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   // element m of this thread's column sits at byte to + sm * m of the tile: sm * m is the same
   // for the whole block, to a 32-bit per-thread offset (inactive threads read a valid element
   // and never use it)
-  const size_t tb = (size_t)wi.blk * lay.M * C;
+  const size_t tb = (size_t)wi.blk * lay.M * C, tbN = (size_t)(lay.NT - 1) * lay.M * C;
   const uint32_t sm = (uint32_t)(T * C * sizeof(cf));
   const uint32_t to = (uint32_t)(((active ? t : 0) * C + c) * sizeof(cf));
   const auto rS = gbytes(d.S1 + tb);
+  const bool fold = RESID && lay.fold && wi.blk == 0;  // uniform over the block
+  const bool fc = fold && c == 0 && active;
   cf v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = ld_cf(rS, to, sm * m);
+  if (fc) {  // column N/2 (real) as the imaginary part of column 0 (real)
+    const auto rN = gbytes(d.S1 + tbN);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m].im = ld_f(rN, to, sm * m);
+  }
   if constexpr (LF != 0) reg_fft_c<LF, -1, 2, false>(v, t, active, lds + c, TwGlobal{G(d.twM)});
   else reg_fft<-1>(v, t, active, d.rm, lds + c, C, G(d.twM));
   if (!RESID) {
@@ -538,6 +550,25 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
       for (int m = 0; m < 16; ++m) st_cf(v[m], rS, to, sm * m);
     }
   } else {
+    cf *zB = lds + lay.M;  // column N/2 after the separation (the exchange area is free now)
+    if (fold) {
+      cf *zA = lds;
+      if (fc) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) zA[t + T * m] = v[m];
+      }
+      __syncthreads();
+      if (fc) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const int row = t + T * m;
+          const cf zm = zA[(lay.M - row) & (lay.M - 1)];  // Z[-k]
+          const cf d = cf{v[m].re - zm.re, v[m].im + zm.im};  // Z[k] - conj Z[-k] = 2i F(x_N/2)[k]
+          v[m] = cf{0.5f * (v[m].re + zm.re), 0.5f * (v[m].im - zm.im)};
+          zB[row] = cf{0.5f * d.im, -0.5f * d.re};
+        }
+      }
+    }
     constexpr int NC = kLamFirstCand;
     float mu[NC];
 #pragma unroll
@@ -549,11 +580,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     const bool valid = active && k < lay.Wh;
     const float wgt = (k == 0 || 2 * k == lay.N) ? 1.0f : 2.0f;
     __builtin_amdgcn_sched_barrier(0);  // H and Y are not loaded before the transform is done
-    if (active) {
-      // two halves of eight bins: the 16 loads of a half are in flight together, and each bin's
-      // U_E and q are stored as soon as q is known (padding columns hold zeros in H and Y, so
-      // they are loaded like the others)
-      const auto rH = gbytes(d.H + tb), rY = gbytes(d.Y + tb), rq = gbytes(d.q + tb);
+    // R = H U_E - Y, q = w |R|^2 and the first-round terms of a column of one tile, in two
+    // halves of eight bins: the 16 loads of a half are in flight together, and each bin's U_E
+    // and q are stored as soon as q is known (padding columns hold zeros in H and Y, so they
+    // are loaded like the others)
+    auto residual = [&](size_t tile, auto value, float w, bool ok) {
+      const auto rU = gbytes(d.S1 + tile), rH = gbytes(d.H + tile), rY = gbytes(d.Y + tile), rq = gbytes(d.q + tile);
 #pragma unroll
       for (int h0 = 0; h0 < 16; h0 += 8) {
         cf hv[8], yv[8];
@@ -565,14 +597,17 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
           const int m = h0 + i;
-          const cf r = cmul(hv[i], v[m]) - yv[i];
-          const float qq = valid ? wgt * abs2f(r) : 0.0f;
-          st_cf(v[m], rS, to, sm * m);
+          const cf u = value(m);
+          const cf r = cmul(hv[i], u) - yv[i];
+          const float qq = ok ? w * abs2f(r) : 0.0f;
+          st_cf(u, rU, to, sm * m);
           st_f(qq, rq, to / 2, sm / 2 * m);
           first_round_terms<NC>(qq, abs2f(hv[i]), mu, acc);
         }
       }
-    }
+    };
+    if (active) residual(tb, [&](int m) { return v[m]; }, wgt, valid);
+    if (fc) residual(tbN, [&](int m) { return zB[t + T * m]; }, 1.0f, true);
     float h, l;
     block_sum_plain_then_df<2 + 2 * NC>(acc, h, l, scratch);
     store_partial(G(d.part), d.npart, wi.blk, 2 + 2 * NC, h, l);
@@ -786,7 +821,7 @@ __global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, c
   GFD_ITEM_LOOP
   constexpr int NC = kLamFirstCand;
   float hi[2 + 2 * NC], lo[2 + 2 * NC];
-  reduce_partials<2 + 2 * NC>(G(d.part), d.npart, d.L.NT, hi, lo, scratch);
+  reduce_partials<2 + 2 * NC>(G(d.part), d.npart, d.L.col_blocks(), hi, lo, scratch);  // blocks of the residual pass
   if (threadIdx.x == 0) {
     LamState st = stv[wi.img];
     st.phase = 0;
@@ -1073,7 +1108,8 @@ Layout make_layout(int M, int N, const Tuning &tune) {
   L.logC = ilog2(C);
   L.NT = (L.Wh + C - 1) / C;
   L.RP = L.NT * C;
-  L.fold = (reg_plan_ok(M) && N % 2 == 0 && (N / 2) % C == 0 && L.NT >= 2) ? 1 : 0;
+  // (the folded passes also use 2 M complex values of the block's LDS, which C >= 2 provides)
+  L.fold = (reg_plan_ok(M) && C >= 2 && N % 2 == 0 && (N / 2) % C == 0 && L.NT >= 2) ? 1 : 0;
   // rows per block in the LDS-resident row passes: aim at >= 128-byte segments, LDS <= 64 KiB
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
@@ -1202,7 +1238,9 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
     int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
-    ItemRange r = add_items(set, imgs, [](const Img &d) { return d.L.NT; });
+    // the register-resident residual pass folds the last tile into the block of tile 0
+    const bool fold = std::get<0>(k) != 0 && resid;
+    ItemRange r = add_items(set, imgs, [fold](const Img &d) { return fold ? d.L.col_blocks() : d.L.NT; });
     if (std::get<0>(k)) {
       int threads = 0; size_t lds = 0;
       for (int i : imgs) {
