@@ -24,6 +24,17 @@ __device__ __forceinline__ void kahan_slide(Kahan &k, float xn, float xo) {
   k.s = t;
 }
 
+// Column of the strip owned by thread l.  Rows of sums are stored with a gap of 4 floats after
+// every 8 columns (hs_col), so 8-column block b of a wave's 64 columns starts at bank 12 b mod
+// 32: blocks 0, 2, 4, 6 cover the 32 banks once, and so do blocks 1, 3, 5, 7.  Lanes 0-31 of a
+// wave therefore own blocks 0, 2, 4, 6 and lanes 32-63 blocks 1, 3, 5, 7, which keeps the
+// one-float accesses of a half wave (served together) free of bank conflicts; a wave's global
+// loads and stores still cover its 64 contiguous columns.
+__device__ __forceinline__ int gf_col(int l) {
+  const int x = l & 63;
+  return (l & ~63) + 8 * (2 * ((x >> 3) & 3) + (x >> 5)) + (x & 7);
+}
+
 // Running window sum moved by one row: the row xo leaves, xn enters.
 __device__ __forceinline__ void slide(float &s, float xn, float xo) { s = __fadd_rn(s, __fsub_rn(xn, xo)); }
 

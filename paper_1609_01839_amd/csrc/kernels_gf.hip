@@ -51,7 +51,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const float inv_w2 = 1.0f / (float)(W * W);
   const int bx = lb / nby, by = lb - bx * nby;
   const int x0 = bx * TX, y0 = by * TY;
-  const int j = threadIdx.x;
+  const int j = gf_col(threadIdx.x);  // the strip column this thread owns
   const int used = TX + 4 * R;
   const bool active = j < used;
   const int gx = wrap(x0 - 2 * R + j, N);
@@ -135,7 +135,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
       if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
       // ---- stage 1, horizontal: RB rows x 4 quantities
 #pragma unroll
-      for (int t = j; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+      for (int t = threadIdx.x; t < RB * 4 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
       __syncthreads();
       // ---- a, b (Eqs. 3-4) and stage 2, vertical
 #pragma unroll
@@ -188,7 +188,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
       if (base + RB - 1 < 4 * R) continue;  // no complete stage-2 window yet (uniform)
       // ---- stage 2, horizontal: RB rows x 2 quantities
 #pragma unroll
-      for (int t = j; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
+      for (int t = threadIdx.x; t < RB * 2 * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);
       __syncthreads();
       // ---- output rows
 #pragma unroll
