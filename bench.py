@@ -193,7 +193,7 @@ def main():
     y = torch.from_numpy(case.y).to(dev)
     h = torch.from_numpy(case.h.astype(np.float32)).to(dev)
     g = gfd.GFDeconv(y, h, case.sigma2, case.w, case.eps)
-    tuning = None if args.no_autotune else g.autotune(8)
+    tuning = None if args.no_autotune else g.autotune(16)
     stream = torch.cuda.current_stream(dev)
     out = torch.empty((M, N), device=dev, dtype=torch.float32)
     lam = torch.empty((max(args.steps, args.warmup, 1),), device=dev, dtype=torch.float32)

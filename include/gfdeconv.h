@@ -221,7 +221,8 @@ gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_
 /*
  * deconv_autotune -- pick launch shapes for this context by timing: the guided filter's strip
  * height and the rows per block of the power-of-two row transforms are tried one knob at a
- * time (coordinate descent from the defaults), each candidate over `iters` replays of the
+ * time (coordinate descent from the defaults, the strip height starting at the lowest one
+ * whose strips all fit on the device at once), each candidate over `iters` replays of the
  * captured iteration (0 selects 4; at most 64), and the fastest is kept.  The arithmetic is
  * the same in every shape except where the filter's running sums restart (strip edges), so
  * results agree to rounding.  Needs a context with no

@@ -1123,15 +1123,17 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
     }
     return true;
   };
-  // coordinate descent over the knobs, starting from the defaults
+  // coordinate descent over the knobs, starting from the defaults with the filter's strip height
+  // set to the lowest one whose strips of image 0 fit on the device at once (when there is one);
+  // the strip heights tried are a ladder plus that one
+  const int fill = gf_fill_height(c->main.imgs[0]);
   Tuning best{};
+  best.gf_ty = fill;
   float best_ms = 0.0f;
   bool ok = trial(best, best_ms);
-  // strip heights: a ladder, plus the lowest one whose strips of image 0 fit on the device at once
   int gf_ty[8] = {32, 48, 64, 80, 96, 112, 128, 0};
   int ngf = 7;
   {
-    const int fill = gf_fill_height(c->main.imgs[0]);
     bool have = fill == 0;
     for (int i = 0; i < ngf; ++i) have = have || gf_ty[i] == fill;
     if (!have) gf_ty[ngf++] = fill;

@@ -27,14 +27,19 @@
 
 namespace gfd {
 
-// Rows per round of barriers of the filter's streaming strip.
-constexpr int kGfRows = 2;
+// Rows per round of barriers of the filter's streaming strip.  Four for the two widest radii
+// (measured at w = 17): one barrier per row, and the second-stage horizontal sums of a round
+// occupy every thread; the doubled LDS (about 50 KB) allows three blocks per CU, and with them
+// up to 168 VGPRs (at 128, with two rows per round, r = 7 spilled).  Two for the other radii,
+// whose registers allow four to six blocks per CU.
+template <int R>
+constexpr int gf_rows() { return R >= 7 ? 4 : 2; }
 
 // LDS of one strip: RB rows x 4 fields of padded vertical sums and of horizontal sums.
 template <int R>
 struct GfLds {
-  float vbuf[kGfRows * 4 * hs_pitch<R>()];
-  float hbuf[kGfRows * 4 * kHsOut];
+  float vbuf[gf_rows<R>() * 4 * hs_pitch<R>()];
+  float hbuf[gf_rows<R>() * 4 * kHsOut];
 };
 
 // One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
@@ -43,7 +48,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
                                          GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY, int nby,
                                          int lb, float cI, float cP, GfLds<R> &sh) {
   constexpr int W = 2 * R + 1;
-  constexpr int RB = kGfRows;
+  constexpr int RB = gf_rows<R>();
   constexpr int VP = hs_pitch<R>();  // padded row of vertical sums
   float *__restrict__ vbuf = sh.vbuf;
   float *__restrict__ hbuf = sh.hbuf;
