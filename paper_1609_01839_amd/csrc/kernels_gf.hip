@@ -35,6 +35,10 @@ namespace gfd {
 template <int R>
 constexpr int gf_rows() { return R >= 7 ? 4 : 2; }
 
+// Waves per SIMD the LDS of one strip allows: the occupancy the register allocator aims for.
+template <int R>
+constexpr int gf_waves() { return gf_rows<R>() == 4 ? 3 : 4; }
+
 // LDS of one strip: RB rows x 4 fields of padded vertical sums and of horizontal sums.
 template <int R>
 struct GfLds {
@@ -214,10 +218,8 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
 }
 
 // Inside the iteration: one launch filters every image of the group (images of one radius).
-// Four waves per SIMD (at most 128 VGPRs): the widest radius spills a few registers, which
-// costs less than the lost occupancy.
 template <int R, bool CLIP>
-__global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
+__global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(gf_waves<R>()))) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   __shared__ __align__(16) GfLds<R> sh;
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
@@ -232,7 +234,7 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
 
 // Stand-alone filter: the offsets are the first pixels of the inputs.
 template <int R, bool CLIP>
-__global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(4))) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
+__global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(gf_waves<R>()))) k_gf_plain(const float *__restrict__ uI, const float *__restrict__ uP,
                                                          float *__restrict__ u, int M, int N, float eps, int TX,
                                                          int TY, int nby) {
   __shared__ __align__(16) GfLds<R> sh;
