@@ -66,6 +66,14 @@ struct TwGlobal {
   __device__ __forceinline__ cf operator()(int e) const { return E(tw, (uint32_t)e); }
 };
 
+// Twiddle source from two 64-entry tables in LDS: w_L^e = w_L^(64 (e / 64)) w_L^(e % 64) for
+// e < 4096 (`lo` holds w_L^j, `hi` w_L^(64 j)).  Reads of LDS leave the vector-memory counter
+// alone, so loads issued before a transform are not waited for at its twiddles.
+struct TwSplit {
+  const cf *lo, *hi;
+  __device__ __forceinline__ cf operator()(int e) const { return cmul(hi[e >> 6], lo[e & 63]); }
+};
+
 // One pass.  `lds` addresses the sequence's region: slot(p) = lds[lds_pad(p) * ls].
 // Inactive threads (blocks sized for a larger image of a batch) only join the barriers.
 template <int R, int DIR>

@@ -429,11 +429,25 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 // and last passes straight from / to global memory.  Threads beyond an image's need (blocks
 // sized for a larger image of the batch) only join the barriers.
 
+// The compile-time transforms (length 4096) take their twiddles from two 64-entry tables in LDS
+// (TwSplit), written here from the image's FP32 table at the block's start into tab[0 .. 128),
+// a region no exchange touches; the first pass of a transform needs no twiddles and ends with
+// a barrier, which makes the tables visible before they are read.
+__device__ __forceinline__ void load_tw_split(cf *tab, const cf *tw) {
+  if (threadIdx.x < 128) {
+    const int j = threadIdx.x & 63;
+    tab[threadIdx.x] = E(G(tw), (uint32_t)(threadIdx.x < 64 ? j : 64 * j));
+  }
+}
+
 template <int LF>
 __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
-                                                     int nitems) {
+                                                     int nitems, int tw_off) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
+  if constexpr (LF != 0) {
+    if ((int)blockIdx.x < nitems) load_tw_split(lds + tw_off, D[W[blockIdx.x].img].twN);
+  }
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int M = lay.M, N = lay.N, R = lay.Rf, T = d.rn.T;
@@ -455,7 +469,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
     }
   }
   cf *my = lds + seq * LP;
-  if constexpr (LF != 0) reg_fft_c<LF, -1, 1>(v, t, active, my, TwGlobal{G(d.twN)});
+  if constexpr (LF != 0) reg_fft_c<LF, -1, 1>(v, t, active, my, TwSplit{lds + tw_off, lds + tw_off + 64});
   else reg_fft<-1>(v, t, active, d.rn, my, 1, G(d.twN));
   if (active) {
     cf *w0 = my + lds_pad(t);
@@ -516,10 +530,13 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
 // and first-round terms are added to the block's partial sums.
 template <bool RESID, int LF>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))) k_col_fwd_r16(const Img *__restrict__ D, const Item *__restrict__ W,
-                                                     int nitems) {
+                                                     int nitems, int tw_off) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
   __shared__ float scratch[kLamAcc * 16];
+  if constexpr (LF != 0) {
+    if ((int)blockIdx.x < nitems) load_tw_split(lds + tw_off, D[W[blockIdx.x].img].twM);
+  }
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int C = lay.C, T = d.rm.T;
@@ -542,7 +559,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m].im = ld_f(rN, to, sm * m);
   }
-  if constexpr (LF != 0) reg_fft_c<LF, -1, 2, false>(v, t, active, lds + c, TwGlobal{G(d.twM)});
+  if constexpr (LF != 0) reg_fft_c<LF, -1, 2, false>(v, t, active, lds + c, TwSplit{lds + tw_off, lds + tw_off + 64});
   else reg_fft<-1>(v, t, active, d.rm, lds + c, C, G(d.twM));
   if (!RESID) {
     if (active) {
@@ -703,6 +720,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   // both transforms, then one 16-byte store per bin (U_I, U_p): the two columns of the tile give
   // 32 contiguous bytes per row
   if constexpr (LF != 0) {
+    // (twiddles from the global table: the two products per twiddle of the LDS tables cost
+    // this kernel's register budget more spills than the loads' latency)
     reg_fft_c<LF, +1, 2, false>(vp, t, active, lds + c, TwGlobal{G(d.twM)});
     // the second transform loads its twiddles again: an opaque copy of the table pointer keeps
     // the compiler from holding the first transform's twiddles in registers across both
@@ -735,9 +754,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
 // Row pass, inverse; the Hermitian completion is gathered straight from the tile-major spectra.
 template <int LF>
 __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D, const Item *__restrict__ W,
-                                                     int nitems) {
+                                                     int nitems, int tw_off) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
+  if constexpr (LF != 0) {
+    if ((int)blockIdx.x < nitems) load_tw_split(lds + tw_off, D[W[blockIdx.x].img].twN);
+  }
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int M = lay.M, N = lay.N, Wh = lay.Wh, T = d.rn.T;
@@ -795,7 +817,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
     }
     __syncthreads();  // the staged words are read before the transform writes the LDS
   }
-  if constexpr (LF != 0) reg_fft_c<LF, +1, 1>(v, t, active, lds + seq * LP, TwGlobal{G(d.twN)});
+  if constexpr (LF != 0) reg_fft_c<LF, +1, 1>(v, t, active, lds + seq * LP, TwSplit{lds + tw_off, lds + tw_off + 64});
   else reg_fft<+1>(v, t, active, d.rn, lds + seq * LP, 1, G(d.twN));
   if (active && row < M) {
     const uint32_t g0 = (uint32_t)row * (uint32_t)N + (uint32_t)t;
@@ -1220,8 +1242,11 @@ void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         threads = std::max(threads, (d.L.Rf / 2) * d.rn.T);
         lds = std::max(lds, (size_t)(d.L.Rf / 2) * (d.L.N + d.L.N / 16) * sizeof(cf));
       }
+      // the compile-time transform's twiddle tables follow
+      const int tw_off = (int)(lds / sizeof(cf));
+      if (std::get<1>(k)) lds += 128 * sizeof(cf);
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Rf - 1) / d.L.Rf; });
-      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_fwd_r16<4096> : k_row_fwd_r16<0>, r, threads, lds));
+      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_fwd_r16<4096> : k_row_fwd_r16<0>, r, threads, lds, tw_off));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1249,9 +1274,12 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
         lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
       }
       const bool fx = std::get<1>(k) != 0;
-      p.steps.push_back(resid ? make_launch(&set, fx ? k_col_fwd_r16<true, 4096> : k_col_fwd_r16<true, 0>, r, threads, lds)
+      // the compile-time transform's twiddle tables follow
+      const int tw_off = (int)(lds / sizeof(cf));
+      if (fx) lds += 128 * sizeof(cf);
+      p.steps.push_back(resid ? make_launch(&set, fx ? k_col_fwd_r16<true, 4096> : k_col_fwd_r16<true, 0>, r, threads, lds, tw_off)
                               : make_launch(&set, fx ? k_col_fwd_r16<false, 4096> : k_col_fwd_r16<false, 0>, r, threads,
-                                            lds));
+                                            lds, tw_off));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1317,8 +1345,11 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         lds = std::max(lds, (size_t)d.L.Ri * (d.L.N + d.L.N / 16) * sizeof(cf));
         lds = std::max(lds, (size_t)d.L.Ri * (d.L.RP + 4) * 16);
       }
+      // the compile-time transform's twiddle tables follow
+      const int tw_off = (int)(lds / sizeof(cf));
+      if (std::get<1>(k)) lds += 128 * sizeof(cf);
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Ri - 1) / d.L.Ri; });
-      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_inv_r16<4096> : k_row_inv_r16<0>, r, threads, lds));
+      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_inv_r16<4096> : k_row_inv_r16<0>, r, threads, lds, tw_off));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
