@@ -847,6 +847,7 @@ __global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, c
   if (threadIdx.x == 0) {
     LamState st = stv[wi.img];
     st.phase = 0;
+    st.done = 0;
     st.flags = 0;
     float cand[NC];
     for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
@@ -856,10 +857,14 @@ __global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, c
   GFD_ITEM_END
 }
 
-// One evaluation round: per-chunk sums of q g_j and q g_j (1 - r_j) over the bins.
+// One evaluation round: per-chunk sums of q g_j and q g_j (1 - r_j) over the bins; the last
+// block of an image to store its sums folds the round into the bracket.  The count of stored
+// blocks lives in the image's state: each block's partial sums are made visible device-wide
+// before it counts itself, and the last block fences again before it reads them all.
 __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                   const LamState *__restrict__ stv) {
+                                                   LamState *stv, int last, int advance) {
   __shared__ float scratch[kLamAcc * 4];
+  __shared__ int is_last;
   constexpr int NC = kLamMaxCand;
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
     const Item wi = W[ii];
@@ -902,29 +907,25 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
     float h, l;
     block_sum_plain_then_df<2 * NC>(acc, h, l, scratch);
     store_partial(G(d.part), d.npart, wi.blk, 2 * NC, h, l);
+    __threadfence();
     __syncthreads();
-  }
-}
-
-// One block per image folds a round into the bracket and picks the next candidates.
-__global__ void __launch_bounds__(1024) k_lam_round(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                    LamState *__restrict__ stv, int last, int advance) {
-  __shared__ float scratch[2 * kLamAcc * 16];
-  constexpr int NC = kLamMaxCand;
-  for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
-    const Item wi = W[ii];
-    if (wi.blk < 0 || stv[wi.img].phase != 0) continue;
-    const Img &d = D[wi.img];
-    float hi[2 * NC], lo[2 * NC];
-    reduce_partials<2 * NC>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
-    if (threadIdx.x == 0) {
-      LamState st = stv[wi.img];
-      float cand[NC];
-      for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
-      lam_absorb(st, NC, cand, hi, lo, hi + NC);
-      if (lam_decide(st, last != 0)) lam_commit(d, st, advance);
-      stv[wi.img] = st;
+    if (threadIdx.x == 0) is_last = atomicAdd(&stv[wi.img].done, 1) == d.nchunk - 1;
+    __syncthreads();
+    if (is_last) {  // uniform over the block
+      __threadfence();
+      float hi[2 * NC], lo[2 * NC];
+      reduce_partials<2 * NC>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
+      if (threadIdx.x == 0) {
+        LamState st = stv[wi.img];
+        float cand[NC];
+        for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
+        lam_absorb(st, NC, cand, hi, lo, hi + NC);
+        if (lam_decide(st, last != 0)) lam_commit(d, st, advance);
+        st.done = 0;
+        stv[wi.img] = st;
+      }
     }
+    __syncthreads();
     __syncthreads();
   }
 }
@@ -1090,6 +1091,7 @@ __global__ void k_state_reset(LamState *st) {
   st->lam_prev2 = 0.0f;
   st->meanI = 0.0f;
   st->meanP = 0.0f;
+  st->done = 0;
   lam_first_candidates(*st);
 }
 
@@ -1299,10 +1301,8 @@ void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, 
   const int adv = advance ? 1 : 0;
   p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0, set.st_base, adv));
   ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
-  for (int k = 0; k < rounds; ++k) {
-    p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0, (const LamState *)set.st_base));
-    p.steps.push_back(make_launch(&set, k_lam_round, one, 1024, 0, set.st_base, (int)(k == rounds - 1), adv));
-  }
+  for (int k = 0; k < rounds; ++k)
+    p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0, set.st_base, (int)(k == rounds - 1), adv));
 }
 
 void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {

@@ -66,6 +66,7 @@ struct LamState {
   float mu[kLamMaxCand];  // 1 / cand
   // offsets subtracted from u_I and u_p inside the guided filter (their means)
   float meanI, meanP;
+  int done;  // blocks of the running evaluation round that have stored their partial sums
 };
 
 GFD_HD inline float lam_relF(float hi, float lo, float TP) {
