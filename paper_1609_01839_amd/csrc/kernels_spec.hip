@@ -57,11 +57,11 @@ __device__ __forceinline__ void store_partial(GFD_AS1 float *part, int npart, in
 
 // Compensated sums of the NV values of the partials of `nparts` blocks.  Wave w takes values
 // w, w + nwaves, ...: each lane accumulates the partials lane, lane + 64, ... in order (loaded
-// 32 at a time, so that up to 2048 partials cost one memory round trip), then the
+// U at a time, so that up to 64 U partials cost one memory round trip), then the
 // wave combines its lanes by shuffles, so no lane carries more than one value through the
 // shuffle tree (the tree is the expensive part).  Deterministic order; thread 0 receives all NV
-// sums.  `scratch` must hold 2 NV floats.
-template <int NV>
+// sums.  `scratch` must hold 2 NV floats.  U: partials per lane loaded together (2 U registers).
+template <int NV, int U = 32>
 __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict__ part, int npart, int nparts, float (&hi)[NV],
                                 float (&lo)[NV], float *scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -69,7 +69,6 @@ __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict_
     const GFD_AS1 float *ph = part + (size_t)(2 * v) * npart, *pl = part + (size_t)(2 * v + 1) * npart;
     float h = 0.0f, l = 0.0f;
     // U partials per lane per pass, loaded together before they are added in order
-    constexpr int U = 32;
     for (int p0 = lane; p0 < nparts; p0 += 64 * U) {
       float xh[U], xl[U];
 #pragma unroll
@@ -865,6 +864,7 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
                                                    LamState *stv, int last, int advance) {
   __shared__ float scratch[kLamAcc * 4];
   __shared__ int is_last;
+  __shared__ LamState sst;
   constexpr int NC = kLamMaxCand;
   for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
     const Item wi = W[ii];
@@ -907,16 +907,21 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
     float h, l;
     block_sum_plain_then_df<2 * NC>(acc, h, l, scratch);
     store_partial(G(d.part), d.npart, wi.blk, 2 * NC, h, l);
-    __threadfence();
-    __syncthreads();
+    // the partial sums are stored by lanes of wave 0 (2 NC < 64), which also takes the count
+    static_assert(2 * NC <= 64, "partials stored by the first wave");
+    if (threadIdx.x < 64) __threadfence();
     if (threadIdx.x == 0) is_last = atomicAdd(&stv[wi.img].done, 1) == d.nchunk - 1;
     __syncthreads();
     if (is_last) {  // uniform over the block
       __threadfence();
       float hi[2 * NC], lo[2 * NC];
-      reduce_partials<2 * NC>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
+      // (at most 512 chunks: one pass of 8 per lane, which keeps the sweep's registers low)
+      reduce_partials<2 * NC, 8>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
       if (threadIdx.x == 0) {
-        LamState st = stv[wi.img];
+        // the serial search works on a copy in LDS: in registers its fields would raise the
+        // register count of the whole sweep (and lower its occupancy)
+        LamState &st = sst;
+        st = stv[wi.img];
         float cand[NC];
         for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
         lam_absorb(st, NC, cand, hi, lo, hi + NC);
