@@ -60,7 +60,8 @@ __device__ __forceinline__ void dftR(cf *x) {
   else dft2<DIR>(x);
 }
 
-// Twiddle source of the compile-time transforms: the FP32 table tw[e] = w_L^e of the image.
+// Twiddle source from the image's FP32 table in global memory, tw[e] = w_L^e (the column
+// inverse's transforms).
 struct TwGlobal {
   const GFD_AS1 cf *__restrict__ tw;
   __device__ __forceinline__ cf operator()(int e) const { return E(tw, (uint32_t)e); }

@@ -428,8 +428,8 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 // and last passes straight from / to global memory.  Threads beyond an image's need (blocks
 // sized for a larger image of the batch) only join the barriers.
 
-// The compile-time transforms (length 4096) take their twiddles from two 64-entry tables in LDS
-// (TwSplit), written here from the image's FP32 table at the block's start into tab[0 .. 128),
+// The compile-time row transforms and the forward column pass (length 4096) take their
+// twiddles from two 64-entry tables in LDS (TwSplit), written here from the image's FP32 table at the block's start into tab[0 .. 128),
 // a region no exchange touches; the first pass of a transform needs no twiddles and ends with
 // a barrier, which makes the tables visible before they are read.
 __device__ __forceinline__ void load_tw_split(cf *tab, const cf *tw) {
