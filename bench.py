@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="launch shapes instead of the autotuner: strip rows, forward row pairs, inverse rows")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the deconvolution of one frame runs on a single device "
@@ -193,7 +195,14 @@ def main():
     y = torch.from_numpy(case.y).to(dev)
     h = torch.from_numpy(case.h.astype(np.float32)).to(dev)
     g = gfd.GFDeconv(y, h, case.sigma2, case.w, case.eps)
-    tuning = None if args.no_autotune else g.autotune(16)
+    if args.tuning:
+        vals = [int(x) for x in args.tuning.split(",")]
+        if len(vals) != 3:
+            raise SystemExit("--tuning takes three integers: strip rows, forward row pairs, inverse rows")
+        g.set_tuning(*vals)
+        tuning = dict(zip(("gf_strip_rows", "row_pairs_fwd", "rows_inv"), vals))
+    else:
+        tuning = None if args.no_autotune else g.autotune(16)
     stream = torch.cuda.current_stream(dev)
     out = torch.empty((M, N), device=dev, dtype=torch.float32)
     lam = torch.empty((max(args.steps, args.warmup, 1),), device=dev, dtype=torch.float32)

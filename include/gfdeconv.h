@@ -234,6 +234,17 @@ gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_
 gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stream);
 
 /*
+ * deconv_set_tuning -- set the launch shapes without timing them, in deconv_autotune's order:
+ * choice_host (3 ints, host) holds the guided filter's strip height in rows, the row pairs per
+ * block of the forward row pass and the rows per block of the inverse row pass; 0 keeps a
+ * default, and a value an image does not admit (not a power of two, or beyond the block's
+ * threads or LDS) falls back to the default.  The results agree with other shapes to rounding
+ * (as for deconv_autotune).  For repeating a measurement in a chosen shape.  Needs a context
+ * with no iterations run; GFD_ERR_ARG for a NULL pointer or a negative value.
+ */
+gfd_status deconv_set_tuning(gfd_ctx *ctx, const int *choice_host);
+
+/*
  * deconv_backward -- reverse mode of the iterations run since the estimate was last set
  * (deconv_init, deconv_reset or deconv_set_estimate): given g_u = dLoss/du for the current
  * estimate u^K, the gradient of the loss with respect to the guided-filter regulariser eps

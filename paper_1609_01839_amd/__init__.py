@@ -50,6 +50,7 @@ EXPORTS = {
     "deconv_profile": (_i, [_vp, _i, ctypes.POINTER(_f), _i, _vp]),
     "deconv_backward": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "deconv_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), _vp]),
+    "deconv_set_tuning": (_i, [_vp, ctypes.POINTER(_i)]),
     "deconv_destroy": (None, [_vp]),
     "gfd_last_error": (ctypes.c_char_p, []),
 }
@@ -194,6 +195,11 @@ class GFDeconv:
         ch = (_i * 3)()
         _check(load_library().deconv_autotune(self.handle, int(iters), ch, _stream(self.device)))
         return {"gf_strip_rows": ch[0], "row_pairs_fwd": ch[1], "rows_inv": ch[2]}
+
+    def set_tuning(self, gf_strip_rows: int = 0, row_pairs_fwd: int = 0, rows_inv: int = 0):
+        """Set the launch shapes autotune would choose, without timing (0 keeps a default)."""
+        ch = (_i * 3)(int(gf_strip_rows), int(row_pairs_fwd), int(rows_inv))
+        _check(load_library().deconv_set_tuning(self.handle, ch))
 
     def set_graph(self, use_graph: bool):
         _check(load_library().deconv_set_graph(self.handle, 1 if use_graph else 0))

@@ -1175,6 +1175,22 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
   return GFD_OK;
 }
 
+gfd_status deconv_set_tuning(gfd_ctx *ctx, const int *choice_host) {
+  g_err.clear();
+  if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
+  if (ctx->iters != 0) return fail(GFD_ERR_STATE, "deconv_set_tuning needs a context with no iterations run");
+  if (!choice_host) return fail(GFD_ERR_ARG, "choice_host must point to 3 ints");
+  for (int i = 0; i < 3; ++i)
+    if (choice_host[i] < 0) return fail(GFD_ERR_ARG, "launch shapes must be >= 0 (0: default)");
+  Tuning t;
+  t.gf_ty = choice_host[0];
+  t.seq_fwd = choice_host[1];
+  t.seq_inv = choice_host[2];
+  const hipError_t e = apply_tuning(ctx, t);
+  if (e != hipSuccess) return fail(GFD_ERR_HIP, "deconv_set_tuning rebuild failed: %s", hipGetErrorString(e));
+  return GFD_OK;
+}
+
 gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_dev, float *grad_scales_dev,
                            int checkpoint_every, void *stream) {
   g_err.clear();

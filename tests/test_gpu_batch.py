@@ -132,6 +132,25 @@ def test_autotune_keeps_state_and_results():
     assert e < 1e-6 and np.allclose(lam, lam_ref, rtol=1e-5)
 
 
+def test_set_tuning_results():
+    c = synth.make_case(1, size=(512, 512))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as ref:
+        u_ref, lam_ref = ref.iterate(4)
+        u_ref, lam_ref = u_ref.cpu().numpy(), lam_ref.cpu().numpy()
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+        with pytest.raises(gfd.GFDError):
+            g.set_tuning(-1, 0, 0)
+        g.set_tuning(48, 1, 2)         # strip height, forward row pairs, inverse rows
+        u, lam = g.iterate(4)
+        u, lam = u.cpu().numpy(), lam.cpu().numpy()
+        with pytest.raises(gfd.GFDError):
+            g.set_tuning(48, 1, 2)     # iterations have run
+    e = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+    print(f"set shapes vs default rel L2 {e:.2e}")
+    assert e < 1e-6 and np.allclose(lam, lam_ref, rtol=1e-5)
+
+
 def test_autotune_batch():
     cases = synth.make_batch(4, sizes=SMALL_SIZES, config=19)
     probs = problems(cases)
