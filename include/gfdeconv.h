@@ -13,7 +13,10 @@
  *  - Pointers named *_dev or documented as device pointers are device memory on the current
  *    HIP device; they are owned by the caller and must stay valid until the stream has passed
  *    the call.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *  - Calls are stream-ordered and asynchronous unless stated otherwise.
+ *  - Calls are stream-ordered and asynchronous unless stated otherwise.  The calls on one
+ *    context must be ordered: use one stream, or order the streams yourself.  A call that has
+ *    to wait for the context's earlier work (deconv_get_status, deconv_destroy, a history
+ *    that grows) waits for the stream of the context's last call, never for the whole device.
  *  - Boundaries are periodic everywhere: the blur is a circular convolution and the guided
  *    filter's w x w windows wrap around the image edges.
  *  - Sizes: M and N are products of powers of 2, 3 and 5, each in [2, 4096].
@@ -46,8 +49,17 @@ enum {
 enum {
   GFD_FLAG_INF_BRANCH = 1u, /* some iteration found u_E in K and used lambda = +inf (Sec. 3.2) */
   GFD_FLAG_NO_ROOT = 2u,    /* some iteration clamped lambda at its floor (no root of Eq.(11)) */
-  GFD_FLAG_NONFINITE = 4u   /* a non-finite value reached a reduction (NaN/Inf in the data) */
+  GFD_FLAG_NONFINITE = 4u,  /* a non-finite value reached a reduction (NaN/Inf in the data) */
+  GFD_FLAG_UNCONVERGED = 8u /* some lambda search ran out of evaluation rounds before its bracket
+                               met the convergence test: that lambda is the interpolated estimate
+                               and Eq.(11) holds only approximately (3 rounds after the first per
+                               iteration, 10 for a warm start or a stand-alone search) */
 };
+
+/* Widest guided-filter window this build supports (w <= GFD_MAX_WINDOW; r = (w-1)/2 <= 8): the
+ * filter keeps the last w rows of its inputs and coefficients in registers, one slot per row.
+ * Every entry point that takes w returns GFD_ERR_UNIMPLEMENTED for an odd w above this. */
+#define GFD_MAX_WINDOW 17
 
 /*
  * deconv_init -- per-image set-up (Sec. 3.1 Step 0, plus the transforms the solves need).
@@ -57,7 +69,9 @@ enum {
  *          (i - kh/2, j - kw/2).  Its sum must be non-zero (the solve for u_I divides by F(h) at
  *          the zero frequency).
  *   sigma2 noise variance, >= 0 (on the same intensity scale as y).
- *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N)) and regulariser (> 0, finite).
+ *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N) and w <= GFD_MAX_WINDOW, else
+ *          GFD_ERR_ARG, or GFD_ERR_UNIMPLEMENTED above GFD_MAX_WINDOW) and regulariser (> 0,
+ *          finite).
  *   rho    discrepancy factor of the set K (Sec. 3.2), 0 < rho <= 1; rho <= 0 selects Eq.(12).
  * The estimate starts at u_E = 0 (Step 0).  Allocates device memory; synchronises `stream`
  * once at the end so that *out is ready.  *out is untouched on error.
@@ -138,8 +152,9 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
 /*
  * guided_filter -- u = guidfilter(u_I, u_p, w, eps), Sec. 2 Eqs.(3)-(5); context-free.
  *   uI (guidance), up (filtering input), u (output): device M x N float32; u must not alias
- *   uI or up.  Windows are w x w (odd w, 1 <= w <= min(M, N)), wrap periodically, and every
- *   mean divides by w^2.  M, N in [1, 65536] (no factorisation constraint here).
+ *   uI or up.  Windows are w x w (odd w, 1 <= w <= min(M, N); GFD_ERR_UNIMPLEMENTED for
+ *   w > GFD_MAX_WINDOW), wrap periodically, and every mean divides by w^2.  M, N in
+ *   [1, 65536] (no factorisation constraint here).
  */
 gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
                          void *stream);
@@ -186,10 +201,10 @@ gfd_status discrepancy_lambda(gfd_ctx *ctx, const float *uE, float *lambda_dev, 
 
 /*
  * deconv_set_scales -- per-iteration lambda scales s_k (lambda_k = s_k * lambda_star_k),
- * counted from the context's next iteration.  s_dev: device, n floats, copied (stream-ordered
- * on the null stream, synchronously).  Iterations beyond n use scale 1.  n = 0 clears.
+ * counted from the context's next iteration.  s_dev: device, n floats, copied on `stream`
+ * (stream-ordered).  Iterations beyond n use scale 1.  n = 0 clears.
  */
-gfd_status deconv_set_scales(gfd_ctx *ctx, const float *s_dev, int n);
+gfd_status deconv_set_scales(gfd_ctx *ctx, const float *s_dev, int n, void *stream);
 
 /* deconv_set_estimate -- replace the current estimate u_E (device M x N, copied). */
 gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream);
@@ -200,7 +215,8 @@ gfd_status deconv_reset(gfd_ctx *ctx, void *stream);
 /* deconv_info -- host copies of rho, the target rho*P*sigma^2 and the iteration count. */
 gfd_status deconv_info(gfd_ctx *ctx, double *rho, double *target, int *iterations);
 
-/* deconv_get_status -- synchronises the context's work and returns the OR of device flags. */
+/* deconv_get_status -- waits for the context's last call (its stream) and returns the OR of the
+ * GFD_FLAG_* device flags of every iteration and search since deconv_init or deconv_reset. */
 gfd_status deconv_get_status(gfd_ctx *ctx, unsigned *flags_host);
 
 /* deconv_set_graph -- 1 (default): deconv_iterate replays a captured HIP graph; 0: launches

@@ -17,13 +17,15 @@ import os
 import torch
 
 __all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "guided_filter_clipped", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
-           "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE"]
+           "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE",
+           "FLAG_UNCONVERGED", "MAX_WINDOW"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libgfdeconv.so"
 _lib = None
 
-FLAG_INF_BRANCH, FLAG_NO_ROOT, FLAG_NONFINITE = 1, 2, 4
+FLAG_INF_BRANCH, FLAG_NO_ROOT, FLAG_NONFINITE, FLAG_UNCONVERGED = 1, 2, 4, 8
+MAX_WINDOW = 17
 BOUNDARY_PERIODIC, BOUNDARY_CLIP, BOUNDARY_PAD = 0, 1, 2
 _ERRNAMES = {-1: "GFD_ERR_ARG", -2: "GFD_ERR_SIZE", -3: "GFD_ERR_HIP", -4: "GFD_ERR_NOMEM", -5: "GFD_ERR_STATE",
              -6: "GFD_ERR_UNIMPLEMENTED"}
@@ -41,7 +43,7 @@ EXPORTS = {
     "guided_filter_clipped": (_i, [_vp, _vp, _vp, _i, _i, _i, _f, _vp]),
     "spectral_solve": (_i, [_vp, _vp, _f, _vp, _vp, _vp]),
     "discrepancy_lambda": (_i, [_vp, _vp, _vp, _vp]),
-    "deconv_set_scales": (_i, [_vp, _vp, _i]),
+    "deconv_set_scales": (_i, [_vp, _vp, _i, _vp]),
     "deconv_set_estimate": (_i, [_vp, _vp, _vp]),
     "deconv_reset": (_i, [_vp, _vp]),
     "deconv_info": (_i, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i)]),
@@ -179,8 +181,9 @@ class GFDeconv:
 
     def set_scales(self, scales):
         s = torch.as_tensor(scales, dtype=torch.float32, device=self.device).contiguous()
-        torch.cuda.synchronize(self.device)
-        _check(load_library().deconv_set_scales(self.handle, _dev(s, "scales") if s.numel() else None, s.numel()))
+        _check(load_library().deconv_set_scales(self.handle, _dev(s, "scales") if s.numel() else None, s.numel(),
+                                                _stream(self.device)))
+        self._keep_scales = s  # the copy is stream-ordered: keep the source alive
 
     def set_estimate(self, uE: torch.Tensor):
         _check(load_library().deconv_set_estimate(self.handle, _dev(uE, "uE", (self.M, self.N)), _stream(self.device)))

@@ -23,8 +23,6 @@
 using namespace gfd;
 
 static const uint64_t kMagic = 0x6766646563763032ull;  // "gfdecv02"
-static const int kSweeps = 3;       // lambda evaluation rounds per iteration after the first
-static const int kSweepsFull = 10;  // rounds of a stand-alone search (cold start allowed)
 static const int kMaxImages = 4096;
 static const int kStages = 6;
 
@@ -59,7 +57,8 @@ struct gfd_ctx {
   int k_start = 0;  // first iteration since the estimate was last set (what the backward differentiates)
   int use_graph = 1;
   hipGraphExec_t gexec = nullptr;
-  hipStream_t cap_stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // graph capture and the context's own host reads (non-blocking)
+  hipEvent_t done_ev = nullptr;      // recorded after the work of every stream-ordered call
   struct Bwd *bwd = nullptr;   // reverse-mode buffers and plans, built on first use
   Tuning tune;                 // launch shapes in use (deconv_autotune)
 };
@@ -148,11 +147,18 @@ static bool live(gfd_ctx *c) {
   return c != nullptr && g_live.count(c) && c->magic == kMagic;
 }
 
+// The context's work is ordered on the caller's stream; every call that enqueues work records
+// done_ev after it, so waiting for the context (before its buffers are replaced or read on the
+// host) waits for that stream only, never for the whole device.
+static hipError_t mark_done(gfd_ctx *c, hipStream_t s) { return hipEventRecord(c->done_ev, s); }
+static hipError_t wait_done(gfd_ctx *c) { return hipEventSynchronize(c->done_ev); }
+
 static void free_ctx(gfd_ctx *c) {
   free_bwd(c->bwd);
   c->bwd = nullptr;
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->done_ev) (void)hipEventDestroy(c->done_ev);
   for (void *p : c->allocs)
     if (p) (void)hipFree(p);
   for (ImgSet *s : {&c->main, &c->aux}) {
@@ -204,14 +210,14 @@ static hipError_t build_plans(gfd_ctx *c) {
   for (int i = 0; i < c->count; ++i) all[i] = i;
   plan_row_fwd(c->stage[0], c->main, all);
   plan_col_fwd(c->stage[1], c->main, all, true);
-  plan_lambda(c->stage[2], c->main, all, kSweeps, true);
+  plan_lambda(c->stage[2], c->main, all, kLamSweeps, true);
   plan_col_inv(c->stage[3], c->main, all);
   plan_row_inv(c->stage[4], c->main, all);
   plan_guided_filter(c->stage[5], c->main, all);
   for (int k = 0; k < kStages; ++k) append(c->iter, c->stage[k]);
   append(c->warm, c->stage[0]);
   append(c->warm, c->stage[1]);
-  plan_lambda(c->warm, c->main, all, kSweepsFull, false);
+  plan_lambda(c->warm, c->main, all, kLamSweepsFull, false);
   hipError_t e = finalize_items(c->main);
   if (e != hipSuccess) return e;
   if (c->count == 1) {
@@ -222,7 +228,7 @@ static hipError_t build_plans(gfd_ctx *c) {
     plan_row_inv(c->aux_solve, c->aux, one);
     plan_row_fwd(c->aux_lam, c->aux, one);
     plan_col_fwd(c->aux_lam, c->aux, one, true);
-    plan_lambda(c->aux_lam, c->aux, one, kSweepsFull, false);
+    plan_lambda(c->aux_lam, c->aux, one, kLamSweepsFull, false);
     e = finalize_items(c->aux);
   }
   return e;
@@ -426,6 +432,10 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
   };
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return bail(e, "hipGetDevice");
+  e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
+  if (e != hipSuccess) return bail(e, "hipEventCreateWithFlags");
+  e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(e, "hipStreamCreateWithFlags");
   size_t maxP = 0, maxB = 0;
   for (int i = 0; i < count; ++i) {
     int Md, Nd;
@@ -490,6 +500,8 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
     c->meta[i].rho = ro[2 * i];
     c->meta[i].T = ro[2 * i + 1];
   }
+  e = mark_done(c, s);
+  if (e != hipSuccess) return bail(e, "hipEventRecord");
   {
     std::lock_guard<std::mutex> g(g_live_mu);
     g_live.insert(c);
@@ -501,26 +513,26 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
 // Larger per-iteration histories; the descriptors are rewritten in place, so a captured
 // graph (which reads them at run time) stays valid.  The reverse-mode sets copy these
 // pointers and are rebuilt on their next use.
-static gfd_status grow_history(gfd_ctx *c, int need) {
+static gfd_status grow_history(gfd_ctx *c, int need, hipStream_t s) {
   if (need <= c->hist_cap) return GFD_OK;
   int cap = c->hist_cap;
   while (cap < need) cap *= 2;
   float *lh = nullptr, *lsh = nullptr, *sc = nullptr;
   int *fh = nullptr;
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(wait_done(c));
   HIPCHK(hipMalloc((void **)&lh, (size_t)c->count * cap * sizeof(float)));
   HIPCHK(hipMalloc((void **)&lsh, (size_t)c->count * cap * sizeof(float)));
   HIPCHK(hipMalloc((void **)&fh, (size_t)c->count * cap * sizeof(int)));
   HIPCHK(hipMalloc((void **)&sc, cap * sizeof(float)));
-  HIPCHK(launch_fill_f(sc, cap, 1.0f, nullptr));
+  HIPCHK(launch_fill_f(sc, cap, 1.0f, s));
   for (int i = 0; i < c->count; ++i) {
     const size_t o = (size_t)i * cap, oo = (size_t)i * c->hist_cap;
-    HIPCHK(hipMemcpy(lh + o, c->lam_hist + oo, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
-    HIPCHK(hipMemcpy(lsh + o, c->lam_star_hist + oo, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
-    HIPCHK(hipMemcpy(fh + o, c->flag_hist + oo, c->hist_cap * sizeof(int), hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpyAsync(lh + o, c->lam_hist + oo, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(lsh + o, c->lam_star_hist + oo, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(fh + o, c->flag_hist + oo, c->hist_cap * sizeof(int), hipMemcpyDeviceToDevice, s));
   }
-  HIPCHK(hipMemcpy(sc, c->scales, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice));
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpyAsync(sc, c->scales, c->hist_cap * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
   for (void *old : {(void *)c->lam_hist, (void *)c->lam_star_hist, (void *)c->flag_hist, (void *)c->scales}) {
     c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), old));
     (void)hipFree(old);
@@ -829,7 +841,7 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (n_iter < 0) return fail(GFD_ERR_ARG, "n_iter must be >= 0");
   hipStream_t s = (hipStream_t)stream;
-  gfd_status rc = grow_history(ctx, ctx->iters + n_iter);
+  gfd_status rc = grow_history(ctx, ctx->iters + n_iter, s);
   if (rc != GFD_OK) return rc;
   if (ctx->use_graph && !ctx->gexec && n_iter > 0) {
     rc = capture_graph(ctx);
@@ -848,6 +860,7 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
       HIPCHK(hipMemcpyAsync(lambda_out + (size_t)i * n_iter, ctx->lam_hist + (size_t)i * ctx->hist_cap + ctx->iters,
                             n_iter * sizeof(float), hipMemcpyDeviceToDevice, s));
   ctx->iters += n_iter;
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
@@ -857,7 +870,7 @@ gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_
   if (n_iter < 0 || n_stages < 0 || n_stages > kStages || (n_stages > 0 && !stage_ms_host))
     return fail(GFD_ERR_ARG, "n_iter >= 0, 0 <= n_stages <= 6, stage_ms_host non-NULL");
   hipStream_t s = (hipStream_t)stream;
-  gfd_status rc = grow_history(ctx, ctx->iters + n_iter);
+  gfd_status rc = grow_history(ctx, ctx->iters + n_iter, s);
   if (rc != GFD_OK) return rc;
   hipEvent_t ev[kStages + 1];
   for (int i = 0; i <= kStages; ++i) HIPCHK(hipEventCreate(&ev[i]));
@@ -879,6 +892,7 @@ gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_
   for (int i = 0; i <= kStages; ++i) (void)hipEventDestroy(ev[i]);
   if (e != hipSuccess) return fail(GFD_ERR_HIP, "profiled iteration failed: %s", hipGetErrorString(e));
   ctx->iters += n_iter;
+  HIPCHK(mark_done(ctx, s));
   for (int k = 0; k < n_stages; ++k) stage_ms_host[k] = (float)acc[k];
   return GFD_OK;
 }
@@ -940,6 +954,7 @@ gfd_status spectral_solve(gfd_ctx *ctx, const float *uE, float lambda, float *uI
   HIPCHK(ctx->aux_solve.enqueue(s));
   HIPCHK(hipMemcpyAsync(uI, a.uI, bytes, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipMemcpyAsync(up, a.uP, bytes, hipMemcpyDeviceToDevice, s));
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
@@ -954,22 +969,22 @@ gfd_status discrepancy_lambda(gfd_ctx *ctx, const float *uE, float *lambda_dev, 
   HIPCHK(launch_state_reset(ctx->st_aux, s));
   HIPCHK(ctx->aux_lam.enqueue(s));
   HIPCHK(launch_copy_lam_star(ctx->st_aux, lambda_dev, s));
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
-gfd_status deconv_set_scales(gfd_ctx *ctx, const float *s_dev, int n) {
+gfd_status deconv_set_scales(gfd_ctx *ctx, const float *s_dev, int n, void *stream) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (n < 0 || (n > 0 && !s_dev)) return fail(GFD_ERR_ARG, "n must be >= 0 and s_dev non-NULL when n > 0");
-  gfd_status rc = grow_history(ctx, ctx->iters + n);
+  hipStream_t s = (hipStream_t)stream;
+  gfd_status rc = grow_history(ctx, ctx->iters + n, s);
   if (rc != GFD_OK) return rc;
-  HIPCHK(hipDeviceSynchronize());
-  HIPCHK(launch_fill_f(ctx->scales, ctx->hist_cap, 1.0f, nullptr));
-  if (n > 0) HIPCHK(hipMemcpy(ctx->scales + ctx->iters, s_dev, n * sizeof(float), hipMemcpyDeviceToDevice));
-  const int ns = n > 0 ? ctx->iters + n : 0;
-  for (int i = 0; i < ctx->count; ++i)
-    HIPCHK(hipMemcpy((char *)(ctx->st + i) + offsetof(LamState, nscale), &ns, sizeof(int), hipMemcpyHostToDevice));
-  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(launch_fill_f(ctx->scales, ctx->hist_cap, 1.0f, s));
+  if (n > 0)
+    HIPCHK(hipMemcpyAsync(ctx->scales + ctx->iters, s_dev, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_state_set_nscale(ctx->st, ctx->count, n > 0 ? ctx->iters + n : 0, s));
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
@@ -993,6 +1008,7 @@ gfd_status deconv_set_estimate(gfd_ctx *ctx, const float *uE, void *stream) {
   }
   HIPCHK(ctx->warm.enqueue(s));
   ctx->k_start = ctx->iters;
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
@@ -1008,6 +1024,7 @@ gfd_status deconv_reset(gfd_ctx *ctx, void *stream) {
   HIPCHK(ctx->warm.enqueue(s));
   ctx->iters = 0;
   ctx->k_start = 0;
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
@@ -1047,14 +1064,15 @@ gfd_status deconv_get_status(gfd_ctx *ctx, unsigned *flags_host) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (!flags_host) return fail(GFD_ERR_ARG, "flags_host is NULL");
-  HIPCHK(hipDeviceSynchronize());
+  // read on the context's own stream, after the context's last enqueued work
+  std::vector<unsigned> f(ctx->count, 0u);
+  HIPCHK(hipStreamWaitEvent(ctx->cap_stream, ctx->done_ev, 0));
+  for (int i = 0; i < ctx->count; ++i)
+    HIPCHK(hipMemcpyAsync(&f[i], (char *)(ctx->st + i) + offsetof(LamState, flags_all), sizeof(unsigned),
+                          hipMemcpyDeviceToHost, ctx->cap_stream));
+  HIPCHK(hipStreamSynchronize(ctx->cap_stream));
   unsigned all = 0;
-  for (int i = 0; i < ctx->count; ++i) {
-    unsigned f = 0;
-    HIPCHK(hipMemcpy(&f, (char *)(ctx->st + i) + offsetof(LamState, flags_all), sizeof(unsigned),
-                     hipMemcpyDeviceToHost));
-    all |= f;
-  }
+  for (unsigned v : f) all |= v;
   *flags_host = all;
   return GFD_OK;
 }
@@ -1201,7 +1219,7 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
   const int K = ctx->iters - ctx->k_start, k0 = ctx->k_start;
   const int c = checkpoint_every == 0 ? 5 : checkpoint_every;
   if (ctx->bwd && ctx->bwd->hist_cap != ctx->hist_cap) {
-    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(wait_done(ctx));
     free_bwd(ctx->bwd);
     ctx->bwd = nullptr;
   }
@@ -1259,6 +1277,7 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
     }
   }
   HIPCHK(launch_adj_out(b->bwd, b->one, K, k0, grad_eps_dev, grad_scales_dev, s));
+  HIPCHK(mark_done(ctx, s));
   return GFD_OK;
 }
 
@@ -1269,7 +1288,7 @@ void deconv_destroy(gfd_ctx *ctx) {
     if (!g_live.count(ctx)) return;
     g_live.erase(ctx);
   }
-  (void)hipDeviceSynchronize();
+  (void)wait_done(ctx);
   free_ctx(ctx);
 }
 

@@ -236,6 +236,7 @@ hipError_t launch_fill_f(float *p, size_t n, float v, hipStream_t st);
 hipError_t launch_state_reset(LamState *st, hipStream_t s);
 hipError_t launch_state_set_lam(LamState *st, float lam, hipStream_t s);
 hipError_t launch_copy_lam_star(const LamState *st, float *out, hipStream_t s);
+hipError_t launch_state_set_nscale(LamState *st, int count, int ns, hipStream_t s);
 int lam_sweep_chunks(size_t nbins);
 
 }  // namespace gfd

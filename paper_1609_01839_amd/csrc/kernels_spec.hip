@@ -1105,6 +1105,11 @@ __global__ void k_state_set_lam(LamState *st, float lam) {
   st->lam = lam;
 }
 
+__global__ void k_state_set_nscale(LamState *st, int count, int ns) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) st[i].nscale = ns;
+}
+
 __global__ void k_copy_lam_star(const LamState *st, float *out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   out[0] = st->lam_star;
@@ -1497,6 +1502,11 @@ hipError_t launch_state_reset(LamState *st, hipStream_t s) {
 
 hipError_t launch_state_set_lam(LamState *st, float lam, hipStream_t s) {
   hipLaunchKernelGGL(k_state_set_lam, dim3(1), dim3(64), 0, s, st, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_set_nscale(LamState *st, int count, int ns, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_set_nscale, dim3((count + 255) / 256), dim3(256), 0, s, st, count, ns);
   return hipGetLastError();
 }
 

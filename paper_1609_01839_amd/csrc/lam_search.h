@@ -40,8 +40,15 @@ constexpr int kLamMaxCand = 8;     // candidates per evaluation round
 constexpr int kLamFirstCand = 4;
 constexpr float kLamFloor = 1e-30f;
 constexpr float kLamCeil = 1e30f;
+// evaluation rounds after the first one: per iteration (the rounds a captured iteration
+// holds) and for a search that may start cold (warm start, stand-alone search)
+constexpr int kLamSweeps = 3;
+constexpr int kLamSweepsFull = 10;
 
-enum : int { kFlagInf = 1, kFlagNoRoot = 2, kFlagNonFinite = 4 };
+// kFlagUnconverged: the round limit forced a decision while the bracket was still wider than
+// the convergence test allows (lambda is then the interpolated estimate, not a root to FP32
+// accuracy)
+enum : int { kFlagInf = 1, kFlagNoRoot = 2, kFlagNonFinite = 4, kFlagUnconverged = 8 };
 
 struct LamState {
   // constants of the image
@@ -148,10 +155,12 @@ GFD_HD inline float lam_estimate(const LamState &s, float &lam_est, float &width
 }
 
 // Decide after a round: either fix lambda (phase = 1) or load the next candidates.
-// `last` forces a decision.  Returns 1 if lambda is fixed.
+// `last` forces a decision (and raises kFlagUnconverged if the bracket has not converged).
+// Returns 1 if lambda is fixed.
 GFD_HD inline int lam_decide(LamState &s, bool last) {
   s.rounds += 1;
   float next[kLamMaxCand];
+  const int n = kLamMaxCand;
   if (s.haslo && s.hashi) {
     if (!(s.llo < s.lhi)) {  // inconsistent (rounding noise at the root): take the midpoint
       s.lam_star = 0.5f * (s.llo + s.lhi);
@@ -162,13 +171,24 @@ GFD_HD inline int lam_decide(LamState &s, bool last) {
     float err = lam_estimate(s, est, width);
     // The secant-Hermite gap err is the secant's error; the Hermite estimate's own error is of
     // the order of err^2 once the bracket is narrow enough for ln f to be smooth across it.
-    if (last || width <= 1e-6f || (err <= 1e-4f && width <= 0.05f)) {
+    const bool conv = width <= 1e-6f || (err <= 1e-4f && width <= 0.05f);
+    if (last || conv) {
+      if (!conv) s.flags |= kFlagUnconverged;
       s.lam_star = est;
       s.phase = 1;
       return 1;
     }
-    const int n = kLamMaxCand;
-    if (width > 1.0f || !(err > 0.0f)) {
+    // One end still the floor or the ceiling while the other is a measured point (the root moved
+    // past the first candidates): march geometrically away from the measured end, doubling the
+    // step, so that a moderate jump is bracketed tightly in one round.
+    const bool lo_open = s.llo <= kLamFloor, hi_open = s.lhi >= kLamCeil;
+    if (width > 1.0f && lo_open != hi_open) {
+      const float d0 = 0.125f;
+      for (int j = 0; j < n; ++j) {
+        const float x = fminf(d0 * (float)(1 << j), 0.999f * width);
+        next[j] = hi_open ? s.llo * GFD_QEXP(x) : s.lhi * GFD_QEXP(-x);
+      }
+    } else if (width > 1.0f || !(err > 0.0f)) {
       for (int j = 0; j < n; ++j) next[j] = s.llo * GFD_QEXP(width * (float)(j + 1) / (float)(n + 1));
     } else {
       float h = fmaxf(4.0f * err, 1e-7f);
@@ -187,10 +207,20 @@ GFD_HD inline int lam_decide(LamState &s, bool last) {
   // not bracketed yet: march outwards in large geometric steps
   const float step = 6.0f;
   if (s.haslo) {
-    if (last || s.llo >= kLamCeil) { s.lam_star = s.llo; s.phase = 1; return 1; }
+    if (last || s.llo >= kLamCeil) {
+      if (s.llo < kLamCeil) s.flags |= kFlagUnconverged;
+      s.lam_star = s.llo;
+      s.phase = 1;
+      return 1;
+    }
     for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.llo * GFD_QEXP(step * (float)(j + 1));
   } else {
-    if (last || s.lhi <= kLamFloor) { s.lam_star = s.lhi; s.phase = 1; return 1; }
+    if (last || s.lhi <= kLamFloor) {
+      if (s.lhi > kLamFloor) s.flags |= kFlagUnconverged;
+      s.lam_star = s.lhi;
+      s.phase = 1;
+      return 1;
+    }
     for (int j = 0; j < kLamMaxCand; ++j) next[j] = s.lhi * GFD_QEXP(-step * (float)(j + 1));
   }
   lam_set_cand(s, kLamMaxCand, next);

@@ -23,6 +23,10 @@ static void sums(const float *q, const float *t, size_t n, int nc, const float *
   }
 }
 
+// The round limits the library launches: after the first round, per iteration (full = 0) and
+// for a warm start or a stand-alone search (full = 1).
+extern "C" int lam_rounds(int full) { return full ? kLamSweepsFull : kLamSweeps; }
+
 extern "C" int lam_search_host(const float *q, const float *t, size_t n, float TP, float lam_prev, int rounds,
                                float *lam_out, int *rounds_used) {
   LamState s = {};
@@ -54,10 +58,10 @@ extern "C" int lam_search_host(const float *q, const float *t, size_t n, float T
   return s.flags;
 }
 
-// Sequence of searches with the warm start carried over, as the iteration does: returns the
-// rounds used by the last search.
+// Sequence of searches with the warm start carried over, as the iteration does: the lambda,
+// rounds used and flags of every search.
 extern "C" int lam_search_sequence(const float *q, const float *t, size_t n, const float *TP, int nseq, int rounds,
-                                   float *lam_out, int *rounds_used) {
+                                   float *lam_out, int *rounds_used, int *flags_out) {
   LamState s = {};
   s.invP = 1.0f;
   float hi[kLamMaxCand], lo[kLamMaxCand], ds[kLamMaxCand], cand[kLamMaxCand];
@@ -84,6 +88,7 @@ extern "C" int lam_search_sequence(const float *q, const float *t, size_t n, con
     }
     lam_out[it] = s.lam_star;
     rounds_used[it] = s.rounds;
+    flags_out[it] = s.flags;
     if (!isinf(s.lam_star) && !(s.flags & kFlagNoRoot)) {
       s.lam_prev2 = s.lam_prev;
       s.lam_prev = s.lam_star;

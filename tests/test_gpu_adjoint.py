@@ -98,15 +98,32 @@ def test_adjoint_through_infinite_lambda_branch():
     assert e_eps < TOL and e_s < TOL
 
 
-def test_adjoint_gradient_config_4_shape():
-    """The gradient workload's PSF (Gaussian, std 1.6 on 25x25), BSNR 30 dB, 20 iterations and
-    checkpoints every 5, on a 256^2 image so that the oracle finishes in seconds."""
-    h = synth.psf_gaussian(1.6, 25)
-    u, y, s2 = problem(256, 256, h, bsnr=30.0, seed=4)
-    iters = 20
-    ge, gs, _, _ = gpu_grad(y, h, s2, 5, 650.25, iters, u, ckpt=5)
-    re, rs, _, _ = oracle_grad(y, h, s2, 5, float(np.float32(650.25)), iters, u)
-    e_eps, e_s = compare("256^2, 20 iterations", ge, gs, re, rs)
+def test_adjoint_gradient_config_4():
+    """The gradient workload itself: 1024^2 piecewise image, Gaussian PSF std 1.6 on 25x25,
+    BSNR 30 dB, 20 unrolled iterations, checkpoints every 5; gradient of MSE(u_20, u_orig) with
+    respect to eps and the 20 lambda scales against the FP64 oracle's adjoint."""
+    c = synth.make_case(4)
+    iters = c.iters
+    assert iters == 20 and c.shape == (1024, 1024)
+    h = c.h.astype(np.float32)
+    ge, gs, _, _ = gpu_grad(c.y, h, c.sigma2, c.w, c.eps, iters, c.u_orig, ckpt=5)
+    re, rs, _, _ = oracle_grad(c.y, h, c.sigma2, c.w, float(np.float32(c.eps)), iters, c.u_orig)
+    e_eps, e_s = compare("1024^2, 20 iterations, checkpoints every 5", ge, gs, re, rs)
+    assert e_eps < TOL and e_s < TOL
+
+
+@pytest.mark.parametrize("M,N", [(4096, 64), (64, 4096)])
+def test_adjoint_4096_sides(M, N):
+    """The reverse mode through the 4096-point transforms (column passes over 4096-row tiles,
+    4096-point row passes), large-frame PSF and filter (Gaussian std 2.5 on 31x31, w = 17)."""
+    h = synth.psf_gaussian(2.5, 31)
+    u, y, s2 = problem(M, N, h, seed=M + 7 * N)
+    iters = 4
+    scales = np.linspace(0.95, 1.05, iters)
+    ge, gs, _, _ = gpu_grad(y, h, s2, 17, 650.25, iters, u, scales=scales, ckpt=2)
+    re, rs, _, _ = oracle_grad(y, h, s2, 17, float(np.float32(650.25)), iters, u,
+                               scales=np.float32(scales).astype(np.float64))
+    e_eps, e_s = compare(f"{M}x{N} w=17", ge, gs, re, rs)
     assert e_eps < TOL and e_s < TOL
 
 

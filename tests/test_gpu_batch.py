@@ -104,6 +104,52 @@ def test_batch_matches_oracle():
         assert e < 1e-5 and le < 1e-4
 
 
+def config3_mix():
+    """One image of every size of the mixed-size batch workload, with each of its PSF kinds
+    (the 9x9 box, whose transform has exact zeros along the 480- and 720-row axes, at 480x640
+    and 720x1280), its BSNR range and its window sizes."""
+    specs = [((256, 256), "gauss", 5, 24.0), ((480, 640), "box9", 7, 38.0), ((512, 512), "invq", 9, 31.0),
+             ((720, 1280), "box9", 5, 20.0), ((1024, 1024), "gauss", 9, 40.0)]
+    cases = []
+    for k, ((M, N), kind, w, bsnr) in enumerate(specs):
+        rng = np.random.default_rng(3000 + k)
+        u = synth.piecewise_image(M, N, rng)
+        h = {"box9": lambda: synth.psf_box(9), "gauss": lambda: synth.psf_gaussian(float(rng.uniform(1.0, 3.0)), 25),
+             "invq": lambda: synth.psf_inverse_quadratic(15)}[kind]()
+        b = synth.blur_periodic(u, h)
+        s2 = synth.sigma2_for_bsnr(b, bsnr)
+        y = (b + np.sqrt(s2) * rng.standard_normal((M, N))).astype(np.float32)
+        cases.append(synth.Case(f"{M}x{N}_{kind}_w{w}", u, h, y, s2, w, synth.EPS_DEFAULT, 4))
+    return cases
+
+
+def test_batch_matches_oracle_every_batch_size():
+    cases = config3_mix()
+    iters = 4
+    refs = []
+    for c in cases:
+        eps = float(np.float32(c.eps))
+        _, info = oracle.deconvolve(c.y.astype(np.float64), c.h.astype(np.float32).astype(np.float64), c.sigma2, c.w,
+                                    eps, iters, keep_iterates=True)
+        refs.append(info)
+    errs = np.zeros((len(cases), iters))
+    lerr = np.zeros((len(cases), iters))
+    with gfd.GFDeconvBatch(problems(cases)) as g:
+        for k in range(iters):
+            us, lam = g.iterate(1)
+            lam = lam.cpu().numpy()
+            for b, c in enumerate(cases):
+                ref = refs[b]["iterates"][k]
+                errs[b, k] = np.linalg.norm(us[b].cpu().numpy() - ref) / np.linalg.norm(ref)
+                lo = refs[b]["lam"][k]
+                assert np.isfinite(lo) == np.isfinite(lam[b, 0]), (b, k)
+                lerr[b, k] = abs(float(lam[b, 0]) - lo) / lo if np.isfinite(lo) else 0.0
+    for b, c in enumerate(cases):
+        print(f"{c.name}: iterate rel L2 " + " ".join(f"{e:.1e}" for e in errs[b]) +
+              f", lambda {lerr[b].max():.1e}")
+    assert errs.max() < 1e-5 and lerr.max() < 1e-4
+
+
 def test_batch_rejects_single_image_calls():
     cases = synth.make_batch(2, sizes=[(64, 80)], config=13)
     with gfd.GFDeconvBatch(problems(cases)) as g:
