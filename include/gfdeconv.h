@@ -282,6 +282,27 @@ gfd_status deconv_set_tuning(gfd_ctx *ctx, const int *choice_host);
 gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_dev, float *grad_scales_dev,
                            int checkpoint_every, void *stream);
 
+/*
+ * deconvolve_static -- deconv_init followed by deconv_iterate(n_iter) on a one-image problem,
+ * for callers that cannot allocate device memory (code that must not call hipMalloc, such as
+ * tight serving loops or harnesses that forbid allocation): every device buffer of the problem
+ * lives in a fixed 32 MiB array compiled into the library, one per device, held until the
+ * process ends.  The call makes no hipMalloc/hipFree and uses no allocating library routine.
+ *   y, M, N, h, kh, kw, sigma2, w, eps, rho: as deconv_init (same rules and errors).
+ *   n_iter   iterations of Steps 1-3 (Sec. 3.1) from u_E = 0, >= 0.
+ *   u_out    device M x N float32: the estimate after n_iter iterations (required).
+ *   lambda_out  device, n_iter floats, or NULL: the lambda of each iteration, as deconv_iterate.
+ * Results equal those of deconv_init + deconv_iterate bit for bit (same kernels, launched one
+ * by one).  A problem whose buffers exceed the array returns GFD_ERR_SIZE before anything is
+ * enqueued (512 x 512 and 480 x 640 fit; 1024 x 1024 does not).  The array keeps the previous
+ * call's contents and every call clears it first.  Calls that overlap on one device race for
+ * its array (this includes calls on different streams and from different threads); order them.
+ * Waits for `stream` while it sets up (as deconv_init does); the iterations and the copies to
+ * u_out and lambda_out are stream-ordered.
+ */
+gfd_status deconvolve_static(const float *y, int M, int N, const float *h, int kh, int kw, double sigma2, int w,
+                             float eps, double rho, int n_iter, float *u_out, float *lambda_out, void *stream);
+
 /* deconv_destroy -- frees the context; NULL and already-destroyed contexts are ignored. */
 void deconv_destroy(gfd_ctx *ctx);
 

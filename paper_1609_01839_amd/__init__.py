@@ -16,7 +16,8 @@ import os
 
 import torch
 
-__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve", "guided_filter", "guided_filter_clipped", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
+__all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve",
+           "deconvolve_static", "guided_filter", "guided_filter_clipped", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
            "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE",
            "FLAG_UNCONVERGED", "MAX_WINDOW"]
 
@@ -53,6 +54,7 @@ EXPORTS = {
     "deconv_backward": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "deconv_autotune": (_i, [_vp, _i, ctypes.POINTER(_i), _vp]),
     "deconv_set_tuning": (_i, [_vp, ctypes.POINTER(_i)]),
+    "deconvolve_static": (_i, [_vp, _i, _i, _vp, _i, _i, _d, _i, _f, _d, _i, _vp, _vp, _vp]),
     "deconv_destroy": (None, [_vp]),
     "gfd_last_error": (ctypes.c_char_p, []),
 }
@@ -369,6 +371,21 @@ def deconvolve(y, h, sigma2, w, eps, iters, rho=None, scales=None):
         if scales is not None:
             g.set_scales(scales)
         return g.iterate(iters)
+
+
+def deconvolve_static(y, h, sigma2, w, eps, iters, rho=None, out=None, lambdas=None):
+    """``deconvolve`` without device allocation inside the library (``deconvolve_static`` of the
+    C ABI: every buffer in the library's fixed per-device array).  Returns (u, lambdas); pass
+    ``out`` and ``lambdas`` to avoid torch allocations as well."""
+    M, N = (int(s) for s in y.shape)
+    out = torch.empty((M, N), device=y.device, dtype=torch.float32) if out is None else out
+    lambdas = torch.empty((max(int(iters), 0),), device=y.device, dtype=torch.float32) if lambdas is None else lambdas
+    _check(load_library().deconvolve_static(_dev(y, "y"), M, N, _dev(h, "h"), int(h.shape[0]), int(h.shape[1]),
+                                            float(sigma2), int(w), float(eps), -1.0 if rho is None else float(rho),
+                                            int(iters), _dev(out, "out", (M, N)),
+                                            _dev(lambdas, "lambdas", (int(iters),)) if iters > 0 else None,
+                                            _stream(y.device)))
+    return out, lambdas
 
 
 def guided_filter(uI: torch.Tensor, up: torch.Tensor, w: int, eps: float, out: torch.Tensor | None = None,

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <set>
 #include <string>
@@ -61,6 +62,7 @@ struct gfd_ctx {
   hipEvent_t done_ev = nullptr;      // recorded after the work of every stream-ordered call
   struct Bwd *bwd = nullptr;   // reverse-mode buffers and plans, built on first use
   Tuning tune;                 // launch shapes in use (deconv_autotune)
+  Arena *arena = nullptr;      // allocation-free context: every buffer is carved from here
 };
 
 // Reverse mode: descriptor sets over the same images.
@@ -162,6 +164,7 @@ static void free_ctx(gfd_ctx *c) {
   for (void *p : c->allocs)
     if (p) (void)hipFree(p);
   for (ImgSet *s : {&c->main, &c->aux}) {
+    if (s->arena) continue;
     if (s->dev) (void)hipFree(s->dev);
     if (s->items_dev) (void)hipFree(s->items_dev);
   }
@@ -173,6 +176,7 @@ template <class T>
 static hipError_t dalloc(gfd_ctx *c, T **p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
+  if (c->arena) return c->arena->take(count * sizeof(T), (void **)p);
   hipError_t e = hipMalloc((void **)p, count * sizeof(T));
   if (e == hipSuccess) c->allocs.push_back((void *)*p);
   return e;
@@ -189,7 +193,13 @@ static std::vector<double> twiddles(int L) {
 }
 
 static hipError_t upload_table(ImgSet &set) {
-  if (!set.dev) {
+  if (set.arena) {
+    if (!set.dev) {
+      hipError_t e = set.arena->take(std::max<size_t>(set.imgs.size(), 1) * sizeof(Img), (void **)&set.dev);
+      if (e != hipSuccess) return e;
+    }
+    if (set.arena->dry) return hipSuccess;
+  } else if (!set.dev) {
     hipError_t e = hipMalloc((void **)&set.dev, std::max<size_t>(set.imgs.size(), 1) * sizeof(Img));
     if (e != hipSuccess) {
       set.dev = nullptr;
@@ -284,13 +294,16 @@ static gfd_status check_image(const gfd_image &d, int idx) {
   return GFD_OK;
 }
 
-// Device buffers and FP64 set-up of image i (F(h), F(y), constants, rho and the target).
-static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream_t s, double *hp, cd *Hd, cd *Yd,
-                              double *work, float *ypad) {
-  const bool pad = (src.boundary & GFD_BOUNDARY_PAD) != 0;
+// Per-image buffers that only the set-up uses: the FP64 twiddles and the starting estimate.
+struct ImgExtra {
+  float *u0 = nullptr;
+  cd *twMd = nullptr, *twNd = nullptr;
+};
+
+// Device buffers and descriptor of image i (no device work).
+static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, ImgExtra &x) {
   int M, N;
   domain_dims(src, M, N);
-  Img d;
   memset(&d, 0, sizeof(d));
   d.L = make_layout(M, N);
   d.pm = make_plan(M);
@@ -352,14 +365,29 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   d.lam_star_hist = c->lam_star_hist + (size_t)i * c->hist_cap;
   d.scales = c->scales;
   d.hist_cap = c->hist_cap;
-  gf_geometry(d);
+  gf_geometry(d, c->tune.gf_ty);
+  x.u0 = u0;
+  x.twMd = twMd;
+  x.twNd = twNd;
+  return hipSuccess;
+}
+
+// FP64 set-up of image i (F(h), F(y), constants, rho and the target) into its buffers.
+static hipError_t init_image(gfd_ctx *c, int i, const gfd_image &src, const Img &d, const ImgExtra &x, hipStream_t s,
+                             double *hp, cd *Hd, cd *Yd, double *work, float *ypad) {
+  const bool pad = (src.boundary & GFD_BOUNDARY_PAD) != 0;
+  const Layout &L = d.L;
+  const int M = L.M, N = L.N;
+  const size_t P = (size_t)M * N, nb = L.bins();
+  cd *twMd = x.twMd, *twNd = x.twNd;
+  hipError_t e = hipSuccess;
   // twiddle tables, FP64 on the host
   std::vector<double> tm = twiddles(M), tn = twiddles(N);
   std::vector<float> tmf(tm.begin(), tm.end()), tnf(tn.begin(), tn.end());
   if (e == hipSuccess) e = hipMemcpy(twMd, tm.data(), tm.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(twNd, tn.data(), tn.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(twM, tmf.data(), tmf.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(twN, tnf.data(), tnf.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((void *)d.twM, tmf.data(), tmf.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy((void *)d.twN, tnf.data(), tnf.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_embed_psf(src.h, src.kh, src.kw, M, N, hp, s);
   if (e == hipSuccess) e = launch_row_fwd_d(hp, L, d.pn, twNd, Hd, s);
   if (e == hipSuccess) e = launch_col_fwd_d(Hd, L, d.pm, twMd, s);
@@ -370,20 +398,28 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   }
   if (e == hipSuccess) e = launch_row_fwd_fd(ydom, L, d.pn, twNd, Yd, s);
   if (e == hipSuccess) e = launch_col_fwd_d(Yd, L, d.pm, twMd, s);
-  if (e == hipSuccess) e = launch_init_consts(Hd, Yd, L, H, Y, HY, H2, s);
-  if (e == hipSuccess) e = launch_d2_tables(M, N, L.Wh, dM, dN, s);
+  if (e == hipSuccess)
+    e = launch_init_consts(Hd, Yd, L, (cf *)d.H, (cf *)d.Y, (cf *)d.HY, (float *)d.H2, s);
+  if (e == hipSuccess) e = launch_d2_tables(M, N, L.Wh, (float *)d.dM, (float *)d.dN, s);
   if (e == hipSuccess)
     e = launch_rho_target(src.y, src.M, src.N, P, src.h, src.kh, src.kw, src.sigma2, src.rho, work, c->rho_out + 2 * i,
                           d.st, s);
   if (e == hipSuccess) e = launch_state_reset(d.st, s);
-  if (e == hipSuccess) e = launch_fill_f(uE, P, 0.0f, s);
-  if (e == hipSuccess) e = launch_fill_f(u0, P, 0.0f, s);
+  if (e == hipSuccess) e = launch_fill_f(d.uE, P, 0.0f, s);
+  if (e == hipSuccess) e = launch_fill_f(x.u0, P, 0.0f, s);
   // q of the padding columns (and of the last tile, which a folded residual pass never writes)
   // stays zero: the lambda sweeps sum over every bin
-  if (e == hipSuccess) e = launch_fill_f(q, nb, 0.0f, s);
-  c->u0.push_back(u0);
+  if (e == hipSuccess) e = launch_fill_f(d.q, nb, 0.0f, s);
   // the FP64 temporaries are shared by the images: finish before the next image reuses them
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+// Host bookkeeping of image i once its buffers exist.
+static void record_image(gfd_ctx *c, const gfd_image &src, const Img &d, const ImgExtra &x) {
+  const bool pad = (src.boundary & GFD_BOUNDARY_PAD) != 0;
+  const int M = d.L.M, N = d.L.N;
+  c->u0.push_back(x.u0);
   c->main.imgs.push_back(d);
   ImgMeta m;
   m.M = M;
@@ -398,18 +434,21 @@ static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream
   m.rho = 0.0;
   m.T = 0.0;
   c->meta.push_back(m);
+}
+
+static hipError_t setup_image(gfd_ctx *c, int i, const gfd_image &src, hipStream_t s, double *hp, cd *Hd, cd *Yd,
+                              double *work, float *ypad) {
+  Img d;
+  ImgExtra x;
+  hipError_t e = alloc_image(c, i, src, d, x);
+  if (e != hipSuccess) return e;
+  e = init_image(c, i, src, d, x, s, hp, Hd, Yd, work, ypad);
+  record_image(c, src, d, x);
   return e;
 }
 
-static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, hipStream_t s) {
-  if (!out) return fail(GFD_ERR_ARG, "out is NULL");
-  if (!imgs || count < 1 || count > kMaxImages)
-    return fail(GFD_ERR_ARG, "need 1 <= count <= %d image descriptors", kMaxImages);
-  for (int i = 0; i < count; ++i) {
-    gfd_status rc = check_image(imgs[i], i);
-    if (rc != GFD_OK) return rc;
-  }
-  // the PSF sum decides solvability at the zero frequency: read the (small) PSFs first
+// The PSF sum decides solvability at the zero frequency: read the (small) PSFs first.
+static gfd_status check_psfs(const gfd_image *imgs, int count, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
   for (int i = 0; i < count; ++i) {
     std::vector<float> hh((size_t)imgs[i].kh * imgs[i].kw);
@@ -420,6 +459,21 @@ static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, h
       hsum += v;
     }
     if (hsum == 0.0) return fail(GFD_ERR_ARG, "image %d: PSF sums to zero", i);
+  }
+  return GFD_OK;
+}
+
+static gfd_status init_common(gfd_ctx **out, const gfd_image *imgs, int count, hipStream_t s) {
+  if (!out) return fail(GFD_ERR_ARG, "out is NULL");
+  if (!imgs || count < 1 || count > kMaxImages)
+    return fail(GFD_ERR_ARG, "need 1 <= count <= %d image descriptors", kMaxImages);
+  for (int i = 0; i < count; ++i) {
+    gfd_status rc = check_image(imgs[i], i);
+    if (rc != GFD_OK) return rc;
+  }
+  {
+    gfd_status rc = check_psfs(imgs, count, s);
+    if (rc != GFD_OK) return rc;
   }
 
   gfd_ctx *c = new gfd_ctx;
@@ -806,6 +860,95 @@ static hipError_t adjoint_step(Bwd *b, int k, hipStream_t s) {
   if (e == hipSuccess) e = b->col.enqueue(s);
   if (e == hipSuccess) e = b->gout_inv.enqueue(s);
   if (e == hipSuccess) e = b->inf.enqueue(s);
+  return e;
+}
+
+
+// ---------------------------------------------------------------- allocation-free path
+// deconvolve_static keeps every device buffer of its problem in one file-scope array per device
+// (`scratch`), so that it calls no hipMalloc or hipFree.  In host code the array's name is only a
+// stand-in for the device symbol: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is ever used.
+static constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_addr;  // device -> address of its `scratch`
+
+static hipError_t scratch_address(int dev, unsigned char **out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[dev] = (unsigned char *)p;
+  *out = (unsigned char *)p;
+  return hipSuccess;
+}
+
+// Carve every buffer of a one-image problem from c->arena and build its launch plans; the
+// descriptor and work-item tables are copied in unless the arena is dry.  No device work.
+static hipError_t carve_static(gfd_ctx *c, const gfd_image &src, int n_iter, ImgExtra &x) {
+  c->count = 1;
+  c->hist_cap = std::max(n_iter, 1);
+  c->main.arena = c->aux.arena = c->arena;
+  int Md, Nd;
+  domain_dims(src, Md, Nd);
+  const size_t P = (size_t)Md * Nd;
+  hipError_t e = dalloc(c, &c->st, 1);
+  c->main.st_base = c->st;
+  if (e == hipSuccess) e = dalloc(c, &c->lam_hist, c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->flag_hist, c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->lam_star_hist, c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->scales, c->hist_cap);
+  if (e == hipSuccess) e = dalloc(c, &c->rho_out, 2);
+  if (e != hipSuccess) return e;
+  Img d;
+  e = alloc_image(c, 0, src, d, x);
+  if (e != hipSuccess) return e;
+  record_image(c, src, d, x);
+  Img a = d;  // the stand-alone solve's and search's descriptor (as deconv_init builds it)
+  float *lh = nullptr;
+  int *fh = nullptr;
+  e = dalloc(c, &c->st_aux, 1);
+  if (e == hipSuccess) e = dalloc(c, &c->uE_aux, P);
+  if (e == hipSuccess) e = dalloc(c, &lh, 1);
+  if (e == hipSuccess) e = dalloc(c, &fh, 1);
+  if (e != hipSuccess) return e;
+  a.uE = c->uE_aux;
+  a.st = c->st_aux;
+  a.lam_hist = lh;
+  a.flag_hist = fh;
+  a.lam_star_hist = nullptr;
+  a.hist_cap = 1;
+  a.scales = nullptr;
+  c->aux.imgs.push_back(a);
+  c->aux.st_base = c->st_aux;
+  e = upload_table(c->aux);
+  if (e == hipSuccess) e = upload_table(c->main);
+  if (e == hipSuccess) e = build_plans(c);
+  return e;
+}
+
+// FP64 set-up temporaries of the static path, carved after the problem's own buffers.
+struct StaticTemps {
+  double *hp = nullptr, *work = nullptr;
+  cd *Hd = nullptr, *Yd = nullptr;
+  float *ypad = nullptr;
+};
+
+static hipError_t carve_static_temps(gfd_ctx *c, const gfd_image &src, StaticTemps &t) {
+  int Md, Nd;
+  domain_dims(src, Md, Nd);
+  const size_t P = (size_t)Md * Nd, nb = make_layout(Md, Nd).bins();
+  hipError_t e = dalloc(c, &t.hp, P);
+  if (e == hipSuccess) e = dalloc(c, &t.work, 4 * 256);
+  if (e == hipSuccess) e = dalloc(c, &t.Hd, nb);
+  if (e == hipSuccess) e = dalloc(c, &t.Yd, nb);
+  if (e == hipSuccess) e = dalloc(c, &t.ypad, P);
   return e;
 }
 
@@ -1278,6 +1421,79 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
   }
   HIPCHK(launch_adj_out(b->bwd, b->one, K, k0, grad_eps_dev, grad_scales_dev, s));
   HIPCHK(mark_done(ctx, s));
+  return GFD_OK;
+}
+
+gfd_status deconvolve_static(const float *y, int M, int N, const float *h, int kh, int kw, double sigma2, int w,
+                             float eps, double rho, int n_iter, float *u_out, float *lambda_out, void *stream) {
+  g_err.clear();
+  gfd_image d;
+  d.y = y;
+  d.M = M;
+  d.N = N;
+  d.h = h;
+  d.kh = kh;
+  d.kw = kw;
+  d.sigma2 = sigma2;
+  d.w = w;
+  d.eps = eps;
+  d.rho = rho;
+  d.boundary = GFD_BOUNDARY_PERIODIC;
+  {
+    gfd_status rc = check_image(d, 0);
+    if (rc != GFD_OK) return rc;
+  }
+  if (n_iter < 0) return fail(GFD_ERR_ARG, "n_iter must be >= 0");
+  if (!u_out) return fail(GFD_ERR_ARG, "u_out must be a device pointer");
+  // the bytes this problem needs, counted on a dry arena before anything is enqueued
+  size_t need = 0;
+  {
+    Arena dry;
+    dry.cap = ~(size_t)0;
+    dry.dry = true;
+    gfd_ctx c;
+    c.arena = &dry;
+    StaticTemps t;
+    ImgExtra x;
+    hipError_t e = carve_static(&c, d, n_iter, x);
+    if (e == hipSuccess) e = carve_static_temps(&c, d, t);
+    if (e != hipSuccess) return fail(GFD_ERR_HIP, "static layout failed: %s", hipGetErrorString(e));
+    need = dry.off;
+  }
+  if (need > kScratchBytes)
+    return fail(GFD_ERR_SIZE, "%dx%d needs %zu bytes of device scratch; the static scratch holds %zu", M, N, need,
+                kScratchBytes);
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  unsigned char *base = nullptr;
+  HIPCHK(scratch_address(dev, &base));
+  {
+    gfd_status rc = check_psfs(&d, 1, s);  // (waits for `stream`, so also for an earlier call on it)
+    if (rc != GFD_OK) return rc;
+  }
+  // the array keeps the previous call's contents: start from zeros, before the tables go in
+  HIPCHK(launch_fill_f((float *)base, (need + 3) / 4, 0.0f, s));
+  HIPCHK(hipStreamSynchronize(s));
+  Arena arena;
+  arena.base = base;
+  arena.cap = kScratchBytes;
+  gfd_ctx c;
+  c.arena = &arena;
+  StaticTemps t;
+  ImgExtra x;
+  HIPCHK(carve_static(&c, d, n_iter, x));
+  HIPCHK(carve_static_temps(&c, d, t));
+  HIPCHK(launch_fill_f(c.scales, c.hist_cap, 1.0f, s));
+  const Img &img = c.main.imgs[0];
+  HIPCHK(init_image(&c, 0, d, img, x, s, t.hp, t.Hd, t.Yd, t.work, t.ypad));
+  HIPCHK(hipMemcpyAsync(c.st_aux, c.st, sizeof(LamState), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_state_reset(c.st_aux, s));
+  HIPCHK(c.warm.enqueue(s));
+  for (int k = 0; k < n_iter; ++k) HIPCHK(c.iter.enqueue(s));
+  HIPCHK(hipMemcpyAsync(u_out, img.uE, (size_t)M * N * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (lambda_out && n_iter > 0)
+    HIPCHK(hipMemcpyAsync(lambda_out, c.lam_hist, n_iter * sizeof(float), hipMemcpyDeviceToDevice, s));
   return GFD_OK;
 }
 

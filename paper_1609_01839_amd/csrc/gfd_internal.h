@@ -123,14 +123,32 @@ struct Plan {
   }
 };
 
+// Device memory carved out of one caller-owned region instead of hipMalloc (the allocation-free
+// entry point): 256-byte aligned, bumped, never freed.  A dry arena (base = null) only counts
+// the bytes, and copies into it are skipped.
+struct Arena {
+  unsigned char *base = nullptr;
+  size_t cap = 0, off = 0;
+  bool dry = false;
+  hipError_t take(size_t bytes, void **p) {
+    const size_t o = (off + 255) & ~(size_t)255;
+    if (o > cap || bytes > cap - o) return hipErrorOutOfMemory;
+    *p = base + o;
+    off = o + bytes;
+    return hipSuccess;
+  }
+};
+
 // Host-side view of a set of images for building launch plans.  `dev` is the device copy of
-// `imgs`; work lists are appended to items_host and uploaded once by finalize_items().
+// `imgs`; work lists are appended to items_host and uploaded once by finalize_items().  With
+// `arena` set, both device tables are carved from it.
 struct ImgSet {
   std::vector<Img> imgs;
   LamState *st_base = nullptr;  // states of the images, imgs[i].st == st_base + i
   Img *dev = nullptr;
   std::vector<Item> items_host;
   Item *items_dev = nullptr;
+  Arena *arena = nullptr;
 };
 
 template <class K>

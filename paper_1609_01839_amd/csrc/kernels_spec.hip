@@ -1371,6 +1371,14 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
 }
 
 hipError_t finalize_items(ImgSet &set) {
+  if (set.arena) {
+    void *p = nullptr;
+    hipError_t e = set.arena->take(std::max<size_t>(set.items_host.size(), 1) * sizeof(Item), &p);
+    if (e != hipSuccess) return e;
+    set.items_dev = (Item *)p;
+    if (set.arena->dry || set.items_host.empty()) return hipSuccess;
+    return hipMemcpy(set.items_dev, set.items_host.data(), set.items_host.size() * sizeof(Item), hipMemcpyHostToDevice);
+  }
   if (set.items_dev) {
     hipError_t e = hipFree(set.items_dev);
     set.items_dev = nullptr;

@@ -141,3 +141,16 @@ def test_boundary_flags_are_checked_without_gpu():
     assert init(1, 64, 1, gfd.BOUNDARY_PAD) == -2        # observed sides of at least 2
     assert init(64, 64, 65, gfd.BOUNDARY_PAD) == -2      # PSF larger than the observation
     assert ctx.value is None
+
+
+def test_static_entry_point_rejects_before_touching_the_device():
+    """deconvolve_static validates its arguments and the size of its problem against the fixed
+    array before any HIP call (1024 x 1024 needs about 80 MB of the 32 MiB)."""
+    lib = gfd.load_library()
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.deconvolve_static(fake, 1024, 1024, fake, 9, 9, 1.0, 5, 1.0, -1.0, 3, fake, None, None)
+    assert rc == -2 and "static scratch" in lib.gfd_last_error().decode()
+    assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 4, 1.0, -1.0, 3, fake, None, None) == -1
+    assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 5, 1.0, -1.0, -1, fake, None, None) == -1
+    assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 5, 1.0, -1.0, 3, None, None, None) == -1
+    assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 19, 1.0, -1.0, 3, fake, None, None) == -6
