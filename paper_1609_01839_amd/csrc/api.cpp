@@ -95,6 +95,7 @@ static void free_bwd(Bwd *b) {
   for (ImgSet *s : {&b->bwd, &b->grad, &b->gout}) {
     if (s->dev) (void)hipFree(s->dev);
     if (s->items_dev) (void)hipFree(s->items_dev);
+    if (s->lamq) (void)hipFree(s->lamq);
   }
   delete b;
 }
@@ -167,6 +168,7 @@ static void free_ctx(gfd_ctx *c) {
     if (s->arena) continue;
     if (s->dev) (void)hipFree(s->dev);
     if (s->items_dev) (void)hipFree(s->items_dev);
+    if (s->lamq) (void)hipFree(s->lamq);
   }
   c->magic = 0;
   delete c;
@@ -196,10 +198,20 @@ static hipError_t upload_table(ImgSet &set) {
   if (set.arena) {
     if (!set.dev) {
       hipError_t e = set.arena->take(std::max<size_t>(set.imgs.size(), 1) * sizeof(Img), (void **)&set.dev);
+      if (e == hipSuccess) e = set.arena->take(sizeof(LamQueue), (void **)&set.lamq);  // zero: the arena is cleared
       if (e != hipSuccess) return e;
     }
     if (set.arena->dry) return hipSuccess;
-  } else if (!set.dev) {
+  } else if (!set.lamq) {
+    hipError_t e = hipMalloc((void **)&set.lamq, sizeof(LamQueue));
+    if (e == hipSuccess) e = hipMemset(set.lamq, 0, sizeof(LamQueue));
+    if (e != hipSuccess) {
+      (void)hipFree(set.lamq);
+      set.lamq = nullptr;
+      return e;
+    }
+  }
+  if (!set.arena && !set.dev) {
     hipError_t e = hipMalloc((void **)&set.dev, std::max<size_t>(set.imgs.size(), 1) * sizeof(Img));
     if (e != hipSuccess) {
       set.dev = nullptr;

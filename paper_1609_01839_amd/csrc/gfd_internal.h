@@ -149,6 +149,7 @@ struct ImgSet {
   std::vector<Item> items_host;
   Item *items_dev = nullptr;
   Arena *arena = nullptr;
+  LamQueue *lamq = nullptr;  // work queue of the lambda rounds (zeroed when allocated)
 };
 
 template <class K>

@@ -153,6 +153,13 @@ __device__ __forceinline__ void first_round_terms(float qq, float t2, const floa
   }
 }
 
+// The residual pass opens the image's search for the rounds launch that follows it (the kernel
+// boundary orders these stores before that launch's reads): lambda not fixed, no round folded.
+__device__ __forceinline__ void lam_open(LamState *st) {
+  st->phase = 0;
+  st->round = -1;
+}
+
 // ============================================================================ device bodies (any length)
 
 // Row pass, forward, rows [r0, r0 + R): rows are paired into complex sequences z = x_a + i x_b,
@@ -324,6 +331,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd_g(const Img *__restrict__ D, c
     float h, l;
     block_sum_plain_then_df<2 + 2 * NC>(acc, h, l, scratch);
     store_partial(G(d.part), d.npart, wi.blk, 2 + 2 * NC, h, l);
+    if (wi.blk == 0 && threadIdx.x == 0) lam_open(d.st);
   }
   GFD_ITEM_END
 }
@@ -627,6 +635,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     float h, l;
     block_sum_plain_then_df<2 + 2 * NC>(acc, h, l, scratch);
     store_partial(G(d.part), d.npart, wi.blk, 2 + 2 * NC, h, l);
+    if (wi.blk == 0 && threadIdx.x == 0) lam_open(d.st);
   }
   GFD_ITEM_END
 }
@@ -835,44 +844,139 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
 // `stv` is the array of the states of the set's images (index = image), read first so that an
 // image whose lambda is already fixed skips the round after one load.
 
-// After the residual pass: one block per image finishes the first round.
-__global__ void __launch_bounds__(1024) k_lam_begin(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                    LamState *__restrict__ stv, int advance) {
-  __shared__ float scratch[2 * kLamAcc * 16];
-  GFD_ITEM_LOOP
-  constexpr int NC = kLamFirstCand;
-  float hi[2 + 2 * NC], lo[2 + 2 * NC];
-  reduce_partials<2 + 2 * NC>(G(d.part), d.npart, d.L.col_blocks(), hi, lo, scratch);  // blocks of the residual pass
-  if (threadIdx.x == 0) {
-    LamState st = stv[wi.img];
-    st.phase = 0;
-    st.done = 0;
-    st.flags = 0;
-    float cand[NC];
-    for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
-    if (lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC, cand, hi + 2, lo + 2, hi + 2 + NC)) lam_commit(d, st, advance);
-    stv[wi.img] = st;
+// The lambda search after the residual pass, for every image of the launch, as one work queue:
+// entries 0 .. nimg-1 start the images' searches (reduce the residual pass's per-tile partial
+// sums, then lam_begin on one thread), entry nimg + i is round i / nitems of work item
+// i % nitems (an image's chunk of bins).  A block takes entries in queue order; before it
+// evaluates a chunk of round r it waits until the image's round r has been published (by the
+// start for r = 0, by the fold of round r - 1 after that) or its lambda fixed.  The wait cannot
+// deadlock: every entry it depends on was taken earlier by a block that is running, and those
+// finish without waiting on later entries.  Per chunk: sums of q g_j and q g_j (1 - r_j) over its
+// bins; the image's last block to store a round's sums (the count in the image's state, fenced
+// on both sides) folds the round into the bracket.  A search's state is stored first and
+// published after a fence (round r + 1, or phase = 1 with lambda fixed).  Blocks leave when the
+// queue is empty or every image's lambda is fixed; the last to leave clears the queue.
+// A single image skips the start entry: every block reduces the partials and runs the start
+// itself (the same sums in the same order give the same decision in every block), so no block
+// waits for another to start the search.  When the first round decides, block 0 commits lambda
+// and no block touches the queue; otherwise each block evaluates round 0 with its own copy of the
+// start's candidates, and the fold of round 0 starts from the folding block's copy.
+constexpr int kLamSpinLimit = 1 << 20;  // bounded wait (about 50 ms); never reached in practice
+
+__device__ __forceinline__ void lam_publish(LamState *sp, LamState &st, int fixed, int next_round, LamQueue *lq) {
+  st.phase = 0;
+  st.round = next_round - 1;
+  *sp = st;
+  __threadfence();
+  if (fixed) {
+    __hip_atomic_store(&sp->phase, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicAdd(&lq->closed, 1);
+  } else {
+    __hip_atomic_store(&sp->round, next_round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  GFD_ITEM_END
 }
 
-// One evaluation round: per-chunk sums of q g_j and q g_j (1 - r_j) over the bins; the last
-// block of an image to store its sums folds the round into the bracket.  The count of stored
-// blocks lives in the image's state: each block's partial sums are made visible device-wide
-// before it counts itself, and the last block fences again before it reads them all.
-__global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, const Item *__restrict__ W, int nitems,
-                                                   LamState *stv, int last, int advance) {
-  __shared__ float scratch[kLamAcc * 4];
-  __shared__ int is_last;
-  __shared__ LamState sst;
-  constexpr int NC = kLamMaxCand;
-  for (int ii = blockIdx.x; ii < nitems; ii += gridDim.x) {
-    const Item wi = W[ii];
-    if (wi.blk < 0 || stv[wi.img].phase != 0) continue;
+__global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, const Item *__restrict__ W1, int nimg,
+                                                    const Item *__restrict__ W, int nitems, LamState *stv,
+                                                    LamQueue *lq, int rounds, int advance) {
+  __shared__ float scratch[kLamAcc * 8];
+  __shared__ int s_item, s_go, is_last, s_fixed;
+  __shared__ float s_mu[kLamMaxCand], s_mu0[kLamMaxCand];
+  __shared__ LamState sst;  // single image: this block's copy of the start of the search
+  constexpr int NC = kLamMaxCand, NC1 = kLamFirstCand;
+  const int total = nimg + rounds * nitems;
+  const bool single = nimg == 1;
+  if (single) {
+    const Item w0 = W1[0];
+    const Img &d = D[w0.img];
+    float hi[2 + 2 * NC1], lo[2 + 2 * NC1];
+    reduce_partials<2 + 2 * NC1, 16>(G(d.part), d.npart, d.L.col_blocks(), hi, lo, scratch);
+    if (threadIdx.x == 0) {
+      LamState st = stv[w0.img];
+      st.done = 0;
+      st.flags = 0;
+      float cand[NC1];
+      for (int j = 0; j < NC1; ++j) cand[j] = st.cand[j];
+      const int fixed = lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC1, cand, hi + 2, lo + 2, hi + 2 + NC1);
+      if (fixed) {
+        if (blockIdx.x == 0) {
+          lam_commit(d, st, advance);
+          stv[w0.img] = st;
+        }
+      } else {
+        for (int j = 0; j < NC; ++j) s_mu0[j] = st.mu[j];
+        sst = st;
+      }
+      s_fixed = fixed;
+    }
+    __syncthreads();
+    if (s_fixed) return;  // uniform (and the same in every block)
+  }
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int qi = total;
+      if (__hip_atomic_load(&lq->closed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nimg) qi = atomicAdd(&lq->next, 1);
+      s_item = qi;
+    }
+    __syncthreads();
+    const int qi = s_item;
+    if (qi >= total) break;  // uniform
+    if (single && qi < nimg) continue;  // every block started the search itself
+    if (qi < nimg) {  // start of an image's search: the first round was evaluated in the residual pass
+      const Item wi = W1[qi];
+      const Img &d = D[wi.img];
+      float hi[2 + 2 * NC1], lo[2 + 2 * NC1];
+      // (one batch of 16 partials per lane and value: one memory round trip per value)
+      reduce_partials<2 + 2 * NC1, 16>(G(d.part), d.npart, d.L.col_blocks(), hi, lo, scratch);
+      if (threadIdx.x == 0) {
+        // the serial search works on a copy in registers
+        LamState st = stv[wi.img];
+        st.done = 0;
+        st.flags = 0;
+        float cand[NC1];
+        for (int j = 0; j < NC1; ++j) cand[j] = st.cand[j];
+        const int fixed = lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC1, cand, hi + 2, lo + 2, hi + 2 + NC1);
+        if (fixed) lam_commit(d, st, advance);
+        lam_publish(stv + wi.img, st, fixed, 0, lq);
+      }
+      __syncthreads();
+      continue;
+    }
+    const int r = (qi - nimg) / nitems;
+    const Item wi = W[qi - nimg - r * nitems];
+    if (threadIdx.x == 0) {
+      int go = 0;
+      if (single && r == 0) {  // round 0 of a single image: this block's own candidates
+        go = wi.blk >= 0;
+        for (int j = 0; j < NC; ++j) s_mu[j] = s_mu0[j];
+      } else if (wi.blk >= 0) {
+        LamState *sp = stv + wi.img;
+        for (int spin = 0;; ++spin) {
+          if (__hip_atomic_load(&sp->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+          if (__hip_atomic_load(&sp->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= r) {
+            go = 1;
+            break;
+          }
+          if (spin >= kLamSpinLimit) {
+            atomicOr(&sp->flags_all, (unsigned)kFlagUnconverged);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (go) {
+          __threadfence();
+#pragma unroll
+          for (int j = 0; j < NC; ++j) s_mu[j] = __hip_atomic_load(&sp->mu[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) continue;  // uniform
     const Img &d = D[wi.img];
     float mu[NC];
 #pragma unroll
-    for (int j = 0; j < NC; ++j) mu[j] = stv[wi.img].mu[j];
+    for (int j = 0; j < NC; ++j) mu[j] = s_mu[j];
     float acc[2 * NC];
 #pragma unroll
     for (int v = 0; v < 2 * NC; ++v) acc[v] = 0.0f;
@@ -886,10 +990,10 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
       for (int u = 0; u < 4; ++u) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float r = __builtin_amdgcn_rcpf(__fmaf_rn(ts[u], mu[j], 1.0f));
-          const float qg = qs[u] * (r * r);
+          const float rr = __builtin_amdgcn_rcpf(__fmaf_rn(ts[u], mu[j], 1.0f));
+          const float qg = qs[u] * (rr * rr);
           acc[j] += qg;
-          acc[NC + j] = __fmaf_rn(qg, 1.0f - r, acc[NC + j]);
+          acc[NC + j] = __fmaf_rn(qg, 1.0f - rr, acc[NC + j]);
         }
       }
     }
@@ -897,10 +1001,10 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
       for (size_t i = n4 * 4 + threadIdx.x; i < nbins; i += blockDim.x) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
-          const float r = __builtin_amdgcn_rcpf(__fmaf_rn(G(d.H2)[i], mu[j], 1.0f));
-          const float qg = G(d.q)[i] * (r * r);
+          const float rr = __builtin_amdgcn_rcpf(__fmaf_rn(G(d.H2)[i], mu[j], 1.0f));
+          const float qg = G(d.q)[i] * (rr * rr);
           acc[j] += qg;
-          acc[NC + j] = __fmaf_rn(qg, 1.0f - r, acc[NC + j]);
+          acc[NC + j] = __fmaf_rn(qg, 1.0f - rr, acc[NC + j]);
         }
       }
     }
@@ -915,23 +1019,25 @@ __global__ void __launch_bounds__(256) k_lam_sweep(const Img *__restrict__ D, co
     if (is_last) {  // uniform over the block
       __threadfence();
       float hi[2 * NC], lo[2 * NC];
-      // (at most 512 chunks: one pass of 8 per lane, which keeps the sweep's registers low)
+      // (at most 512 chunks: one batch of 8 per lane and value)
       reduce_partials<2 * NC, 8>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
       if (threadIdx.x == 0) {
-        // the serial search works on a copy in LDS: in registers its fields would raise the
-        // register count of the whole sweep (and lower its occupancy)
-        LamState &st = sst;
-        st = stv[wi.img];
+        LamState st = (single && r == 0) ? sst : stv[wi.img];
         float cand[NC];
         for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
         lam_absorb(st, NC, cand, hi, lo, hi + NC);
-        if (lam_decide(st, last != 0)) lam_commit(d, st, advance);
+        const int fixed = lam_decide(st, r == rounds - 1);
+        if (fixed) lam_commit(d, st, advance);
         st.done = 0;
-        stv[wi.img] = st;
+        lam_publish(stv + wi.img, st, fixed, r + 1, lq);
       }
     }
     __syncthreads();
-    __syncthreads();
+  }
+  if (threadIdx.x == 0 && atomicAdd(&lq->exits, 1) == (int)gridDim.x - 1) {
+    __hip_atomic_store(&lq->next, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&lq->closed, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&lq->exits, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1097,6 +1203,7 @@ __global__ void k_state_reset(LamState *st) {
   st->meanI = 0.0f;
   st->meanP = 0.0f;
   st->done = 0;
+  st->round = -1;
   lam_first_candidates(*st);
 }
 
@@ -1307,12 +1414,20 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
 }
 
 void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, bool advance) {
-  ItemRange one = add_one_per_image(set, sel);
+  // one launch for the whole search after the residual pass: blocks take the images' starts,
+  // then (round, chunk) entries from the set's queue, so the grid need not cover the chunks
+  const ItemRange one = add_one_per_image(set, sel);
+  const ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
   const int adv = advance ? 1 : 0;
-  p.steps.push_back(make_launch(&set, k_lam_begin, one, 1024, 0, set.st_base, adv));
-  ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
-  for (int k = 0; k < rounds; ++k)
-    p.steps.push_back(make_launch(&set, k_lam_sweep, chunks, 256, 0, set.st_base, (int)(k == rounds - 1), adv));
+  ImgSet *setp = &set;
+  p.steps.push_back([=](hipStream_t s) -> hipError_t {
+    if (one.n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<size_t>(std::max(chunks.n, one.n), 256);
+    hipLaunchKernelGGL(k_lam_rounds, dim3(grid), dim3(512), 0, s, (const Img *)setp->dev,
+                       (const Item *)(setp->items_dev + one.off), (int)one.n, (const Item *)(setp->items_dev + chunks.off),
+                       (int)chunks.n, setp->st_base, setp->lamq, rounds, adv);
+    return hipGetLastError();
+  });
 }
 
 void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {

@@ -73,7 +73,15 @@ struct LamState {
   float mu[kLamMaxCand];  // 1 / cand
   // offsets subtracted from u_I and u_p inside the guided filter (their means)
   float meanI, meanP;
-  int done;  // blocks of the running evaluation round that have stored their partial sums
+  int done;   // blocks of the running evaluation round that have stored their partial sums
+  int round;  // -1: search opened by the residual pass; r >= 0: candidates of round r published
+};
+
+// Work queue of one launch of the search (shared by the images of the launch): next entry to
+// take, blocks that have left, and images whose lambda the launch has fixed.  All zero between
+// launches.
+struct LamQueue {
+  int next, exits, closed;
 };
 
 GFD_HD inline float lam_relF(float hi, float lo, float TP) {
