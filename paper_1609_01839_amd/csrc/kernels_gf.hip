@@ -46,8 +46,10 @@ struct GfLds {
   float hbuf[gf_rows<R>() * 4 * kHsOut];
 };
 
-// One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).
-template <int R, bool CLIP>
+// One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).  FULL:
+// the strip uses every thread (TX = kGfThreads - 4R, images at least that wide), so no thread
+// needs the selects that zero the sums of columns past a narrow strip.
+template <int R, bool CLIP, bool FULL>
 __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, const GFD_AS1 float *__restrict__ uP,
                                          GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY, int nby,
                                          int lb, float cI, float cP, GfLds<R> &sh) {
@@ -62,10 +64,16 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const int x0 = bx * TX, y0 = by * TY;
   const int j = gf_col(threadIdx.x);  // the strip column this thread owns
   const int used = TX + 4 * R;
-  const bool active = j < used;
+  const bool active = FULL || j < used;
   const int gx = wrap(x0 - 2 * R + j, N);
-  const int nrows = TY + 4 * R;  // stream rows it = 0 .. nrows-1 are image rows y0 - 2R + it
-  const int ybase = y0 - 2 * R;
+  // Stream rows it = 0 .. nrows-1 run down the strip's rows (and the 2R halo rows on each side)
+  // in strips with even `by` and up in the others: neighbouring strips then read the 4R halo rows
+  // they share at the same time (both at their starts, or both at their ends), so the second
+  // read finds them in L2.  The windows are symmetric, so only the order of the sums changes.
+  const int nrows = TY + 4 * R;
+  const int dir = (by & 1) ? -1 : 1;
+  const int ybase = dir > 0 ? y0 - 2 * R : y0 + TY - 1 + 2 * R;  // image row of stream row 0
+  auto yrow = [&](int it) { return ybase + dir * it; };
   // CLIP: whether this thread's column lies in the image, and the reciprocal column count of
   // the windows centred on it (stage-1 coefficients and stage-2 outputs share the column)
   const int xcol = x0 - 2 * R + j;
@@ -73,52 +81,57 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   const int ncol = CLIP && colin ? clip_count<R>(xcol, N) : 1;
   const int cj = hs_col(j + R), hj = hs_col(j);  // this column in the rows of vertical / horizontal sums
 
-  // Each thread keeps, in registers, the mean-centred I and p of the last W stream rows of its
-  // column (slot it % W) and the coefficients (a, b) of the last W rows of windows centred on it
-  // (slot it2 % W), so rows leaving the windows and the guide value of the output row (stream
-  // row it - 2r, still in the ring) are never loaded or recomputed.  The row loop is unrolled
-  // over RB W rows (W rounds of RB), which makes every ring slot a compile-time index.  Loads run
-  // one round ahead: a round first consumes the rows loaded during the previous round, then
-  // issues the next loads, and only then does its LDS work.
+  // Each thread keeps, in registers, the mean-centred I and p of the last RS >= W stream rows of
+  // its column (slot it % RS) and the coefficients (a, b) of the last RS rows of windows centred
+  // on it (slot it2 % RS), so rows leaving the windows and the guide value of the output row
+  // (stream row it - 2r, still in the ring) are never loaded or recomputed.  RS is W rounded up
+  // to a multiple of RB: the row loop is unrolled over RS rows (RS / RB rounds), which makes
+  // every ring slot a compile-time index with a short unrolled body (RB W rows with RS = W had
+  // the register allocator shuffle the rings).  Loads run one round ahead: a round first
+  // consumes the rows loaded during the previous round, then issues the next loads, and only
+  // then does its LDS work.
   auto fetch = [&](int it, float &I, float &p) {
-    const uint32_t g = (uint32_t)wrap(ybase + min(it, nrows - 1), M) * (uint32_t)N + (uint32_t)gx;
+    const uint32_t g = (uint32_t)wrap(yrow(min(it, nrows - 1)), M) * (uint32_t)N + (uint32_t)gx;
     I = E(uI, g);
     p = E(uP, g);
   };
+  constexpr int RS = (W + RB - 1) / RB * RB;
   float sI = 0.0f, sP = 0.0f, sII = 0.0f, sIP = 0.0f, sA = 0.0f, sB = 0.0f;
-  float rI[W], rP[W], rA[W], rB[W];
+  float rI[RS], rP[RS], rA[RS], rB[RS];  // slots not yet written hold zeros (rows before the stream)
 #pragma unroll
-  for (int k = 0; k < W; ++k) rI[k] = rP[k] = rA[k] = rB[k] = 0.0f;
+  for (int k = 0; k < RS; ++k) rI[k] = rP[k] = rA[k] = rB[k] = 0.0f;
   float nI[RB], nP[RB];
 #pragma unroll
   for (int q = 0; q < RB; ++q) fetch(q, nI[q], nP[q]);
-  for (int base0 = 0; base0 < nrows; base0 += RB * W) {
+  for (int base0 = 0; base0 < nrows; base0 += RS) {
 #pragma unroll
-    for (int r = 0; r < W; ++r) {
+    for (int r = 0; r < RS / RB; ++r) {
       const int base = base0 + RB * r;
       if (base >= nrows) break;  // uniform
       float Ig[RB];
       // ---- stage 1, vertical
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
-        const int s = (RB * r + q) % W, sg = (RB * r + q + 1) % W;
+        // slots (base0 is a multiple of RS): this row, the row leaving the window (it - W) and
+        // the guide of this round's output row (it - 2r)
+        const int s = RB * r + q, so = (RB * r + q - W + RS) % RS, sg = (RB * r + q - 2 * R + RS) % RS;
         float I = __fsub_rn(nI[q], cI), p = __fsub_rn(nP[q], cP);
         if (CLIP) {
-          const int y = ybase + base + q;
+          const int y = yrow(base + q);
           if (!(colin && y >= 0 && y < M)) I = p = 0.0f;  // outside the image: no contribution
         }
-        const float Io = rI[s], po = rP[s];  // stream row it - W (zero while it < W)
+        const float Io = rI[so], po = rP[so];  // stream row it - W (zero while it < W)
         rI[s] = I;
         rP[s] = p;
-        Ig[q] = rI[sg];  // stream row it - 2r: the guide of this round's output row
+        Ig[q] = rI[sg];
         float *vb = vbuf + q * 4 * VP + cj;
         // Threads past the strip's columns (narrow images) run the same arithmetic on their
         // clamped, finite inputs and store zeros: a select per value, no divergent branch.
         if (base + q < nrows) {  // uniform
-          if (s == W - 1) {  // the ring holds exactly the window's W rows: sum them afresh
+          if (s == RS - 1) {  // slots RS - W .. RS - 1 hold the window's W rows: sum them afresh
             sI = sP = sII = sIP = 0.0f;
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
+            for (int k = RS - W; k < RS; ++k) {
               sI = __fadd_rn(sI, rI[k]);
               sP = __fadd_rn(sP, rP[k]);
               sII = __fmaf_rn(rI[k], rI[k], sII);
@@ -157,8 +170,8 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           const float *hb = hbuf + q * 4 * kHsOut + hj;
           float nrm = inv_w2;
           bool cin = true;
-          if (CLIP) {  // window centred at image row ybase + it - R, column xcol
-            const int yc = ybase + it - R;
+          if (CLIP) {  // window centred at image row yrow(it - R), column xcol
+            const int yc = yrow(it - R);
             cin = colin && yc >= 0 && yc < M;
             nrm = cin ? __builtin_amdgcn_rcpf((float)(clip_count<R>(yc, M) * ncol)) : 0.0f;
           }
@@ -169,14 +182,15 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
           float b = __fmaf_rn(-a, mu, pb);
           if (CLIP && !cin) a = b = 0.0f;  // windows centred outside the image do not exist
-          const int slot = (RB * r + q + 1) % W;  // it2 % W (base0 is a multiple of W)
-          const float ao = it2 >= W ? rA[slot] : 0.0f, bo = it2 >= W ? rB[slot] : 0.0f;
+          // slots of it2 and of it2 - W (zero while it2 < W)
+          const int slot = (RB * r + q - (W - 1) + RS) % RS, slo = (RB * r + q - (W - 1) - W + 2 * RS) % RS;
+          const float ao = rA[slo], bo = rB[slo];
           rA[slot] = a;
           rB[slot] = b;
-          if (slot == W - 1) {  // rows it2 - W + 1 .. it2 of coefficients: sum them afresh
+          if (slot == RS - 1) {  // slots RS - W .. RS - 1: rows it2 - W + 1 .. it2 of coefficients
             sA = sB = 0.0f;
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
+            for (int k = RS - W; k < RS; ++k) {
               sA = __fadd_rn(sA, rA[k]);
               sB = __fadd_rn(sB, rB[k]);
             }
@@ -203,7 +217,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
         const int it = base + q;
-        const int yo = ybase + it - 2 * R;  // output row
+        const int yo = yrow(it - 2 * R);  // output row
         const int xo = x0 - 2 * R + j;      // output column
         if (it < nrows && it >= 4 * R && j >= 2 * R && j < TX + 2 * R && xo < N && yo < M && yo < y0 + TY) {
           const float *hb = hbuf + q * 2 * kHsOut + hj;
@@ -227,7 +241,10 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
     if (wi.blk < 0) continue;
     const Img &d = D[wi.img];
     const float cI = d.st->meanI, cP = d.st->meanP;
-    gf_strip<R, CLIP>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
+    if (d.gfTX + 4 * R == kGfThreads)
+      gf_strip<R, CLIP, true>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
+    else
+      gf_strip<R, CLIP, false>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
     __syncthreads();
   }
 }
@@ -239,7 +256,8 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
                                                          int TY, int nby) {
   __shared__ __align__(16) GfLds<R> sh;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  gf_strip<R, CLIP>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
+  if (TX + 4 * R == kGfThreads) gf_strip<R, CLIP, true>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
+  else gf_strip<R, CLIP, false>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
 }
 
 bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
