@@ -198,13 +198,14 @@ static hipError_t upload_table(ImgSet &set) {
   if (set.arena) {
     if (!set.dev) {
       hipError_t e = set.arena->take(std::max<size_t>(set.imgs.size(), 1) * sizeof(Img), (void **)&set.dev);
-      if (e == hipSuccess) e = set.arena->take(sizeof(LamQueue), (void **)&set.lamq);  // zero: the arena is cleared
+      if (e == hipSuccess) e = set.arena->take(lam_queue_bytes((int)set.imgs.size()), (void **)&set.lamq);  // zeroed arena
       if (e != hipSuccess) return e;
     }
     if (set.arena->dry) return hipSuccess;
   } else if (!set.lamq) {
-    hipError_t e = hipMalloc((void **)&set.lamq, sizeof(LamQueue));
-    if (e == hipSuccess) e = hipMemset(set.lamq, 0, sizeof(LamQueue));
+    const size_t qb = lam_queue_bytes((int)set.imgs.size());
+    hipError_t e = hipMalloc((void **)&set.lamq, qb);
+    if (e == hipSuccess) e = hipMemset(set.lamq, 0, qb);
     if (e != hipSuccess) {
       (void)hipFree(set.lamq);
       set.lamq = nullptr;

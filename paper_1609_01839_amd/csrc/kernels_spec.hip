@@ -844,24 +844,28 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
 // `stv` is the array of the states of the set's images (index = image), read first so that an
 // image whose lambda is already fixed skips the round after one load.
 
-// The lambda search after the residual pass, for every image of the launch, as one work queue:
-// entries 0 .. nimg-1 start the images' searches (reduce the residual pass's per-tile partial
-// sums, then lam_begin on one thread), entry nimg + i is round i / nitems of work item
-// i % nitems (an image's chunk of bins).  A block takes entries in queue order; before it
-// evaluates a chunk of round r it waits until the image's round r has been published (by the
-// start for r = 0, by the fold of round r - 1 after that) or its lambda fixed.  The wait cannot
-// deadlock: every entry it depends on was taken earlier by a block that is running, and those
-// finish without waiting on later entries.  Per chunk: sums of q g_j and q g_j (1 - r_j) over its
-// bins; the image's last block to store a round's sums (the count in the image's state, fenced
-// on both sides) folds the round into the bracket.  A search's state is stored first and
-// published after a fence (round r + 1, or phase = 1 with lambda fixed).  Blocks leave when the
-// queue is empty or every image's lambda is fixed; the last to leave clears the queue.
+// The lambda search after the residual pass, for every image of the launch, as one work queue.
+// Entries 0 .. nimg-1 start the images' searches (reduce the residual pass's per-tile partial
+// sums, then lam_begin on one thread); a start that leaves the search open appends its image to
+// the queue's open list.  The entries after them are the evaluation rounds of the open images
+// only, round-major: entry nimg + q is round q / S, chunk q % S of the open images' chunks laid
+// end to end (S chunks per round).  A block takes entries in queue order.  Before a round entry
+// it waits until every start is done (the open list is then final), and before a chunk of round
+// r it waits until the image's round r has been published (by the start for r = 0, by the fold
+// of round r - 1 after that) or its lambda fixed.  The waits cannot deadlock: every entry a
+// block waits on was taken earlier by a block that is running, and those finish without waiting
+// on later entries.  Per chunk: sums of q g_j and q g_j (1 - r_j) over its bins; the image's last
+// block to store a round's sums (the count in the image's state, fenced on both sides) folds the
+// round into the bracket.  A search's state is stored first and published after a fence (round
+// r + 1, or phase = 1 with lambda fixed).  Blocks leave when their entry is past the last round
+// or every image's lambda is fixed; the last to leave clears the queue for the next launch.
 // A single image skips the start entry: every block reduces the partials and runs the start
 // itself (the same sums in the same order give the same decision in every block), so no block
 // waits for another to start the search.  When the first round decides, block 0 commits lambda
 // and no block touches the queue; otherwise each block evaluates round 0 with its own copy of the
 // start's candidates, and the fold of round 0 starts from the folding block's copy.
 constexpr int kLamSpinLimit = 1 << 20;  // bounded wait (about 50 ms); never reached in practice
+constexpr int kLamOpenLds = 4096;       // open images a block can map (every image of a batch)
 
 __device__ __forceinline__ void lam_publish(LamState *sp, LamState &st, int fixed, int next_round, LamQueue *lq) {
   st.phase = 0;
@@ -876,16 +880,20 @@ __device__ __forceinline__ void lam_publish(LamState *sp, LamState &st, int fixe
   }
 }
 
+__device__ __forceinline__ int ld_agent(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, const Item *__restrict__ W1, int nimg,
-                                                    const Item *__restrict__ W, int nitems, LamState *stv,
-                                                    LamQueue *lq, int rounds, int advance) {
+                                                    LamState *stv, LamQueue *lq, int rounds, int advance) {
   __shared__ float scratch[kLamAcc * 8];
-  __shared__ int s_item, s_go, is_last, s_fixed;
+  __shared__ int s_item, s_go, is_last, s_fixed, s_img, s_chunk, s_nopen, s_S;
   __shared__ float s_mu[kLamMaxCand], s_mu0[kLamMaxCand];
   __shared__ LamState sst;  // single image: this block's copy of the start of the search
+  __shared__ int s_open[kLamOpenLds], s_pre[kLamOpenLds + 1];  // open images, prefix sums of their chunks
   constexpr int NC = kLamMaxCand, NC1 = kLamFirstCand;
-  const int total = nimg + rounds * nitems;
   const bool single = nimg == 1;
+  if (threadIdx.x == 0) s_nopen = -1;  // open list not read yet
   if (single) {
     const Item w0 = W1[0];
     const Img &d = D[w0.img];
@@ -906,6 +914,11 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
       } else {
         for (int j = 0; j < NC; ++j) s_mu0[j] = st.mu[j];
         sst = st;
+        s_open[0] = w0.img;
+        s_pre[0] = 0;
+        s_pre[1] = d.nchunk;
+        s_nopen = 1;
+        s_S = d.nchunk;
       }
       s_fixed = fixed;
     }
@@ -913,16 +926,12 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
     if (s_fixed) return;  // uniform (and the same in every block)
   }
   for (;;) {
-    if (threadIdx.x == 0) {
-      int qi = total;
-      if (__hip_atomic_load(&lq->closed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nimg) qi = atomicAdd(&lq->next, 1);
-      s_item = qi;
-    }
+    if (threadIdx.x == 0) s_item = ld_agent(&lq->closed) < nimg ? atomicAdd(&lq->next, 1) : -1;
     __syncthreads();
     const int qi = s_item;
-    if (qi >= total) break;  // uniform
-    if (single && qi < nimg) continue;  // every block started the search itself
-    if (qi < nimg) {  // start of an image's search: the first round was evaluated in the residual pass
+    if (qi < 0) break;  // uniform: every image's lambda is fixed
+    if (qi < nimg) {    // start of an image's search: the first round was evaluated in the residual pass
+      if (single) continue;  // every block started the search itself
       const Item wi = W1[qi];
       const Img &d = D[wi.img];
       float hi[2 + 2 * NC1], lo[2 + 2 * NC1];
@@ -938,22 +947,57 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
         const int fixed = lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC1, cand, hi + 2, lo + 2, hi + 2 + NC1);
         if (fixed) lam_commit(d, st, advance);
         lam_publish(stv + wi.img, st, fixed, 0, lq);
+        if (!fixed) __hip_atomic_store(&lq->open[atomicAdd(&lq->nopen, 1)], wi.img, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        atomicAdd(&lq->begun, 1);
       }
       __syncthreads();
       continue;
     }
-    const int r = (qi - nimg) / nitems;
-    const Item wi = W[qi - nimg - r * nitems];
-    if (threadIdx.x == 0) {
+    if (s_nopen < 0) {  // first round entry of this block: the final open list (uniform)
+      if (threadIdx.x == 0) {
+        for (int spin = 0; ld_agent(&lq->begun) < nimg; ++spin) {
+          if (spin >= kLamSpinLimit) break;  // (the list below then covers the starts done so far)
+          __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        s_nopen = min(ld_agent(&lq->nopen), kLamOpenLds);
+      }
+      __syncthreads();
+      for (int k = threadIdx.x; k < s_nopen; k += blockDim.x) {
+        const int img = ld_agent(&lq->open[k]);
+        s_open[k] = img;
+        s_pre[k + 1] = D[img].nchunk;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        s_pre[0] = 0;
+        for (int k = 0; k < s_nopen; ++k) s_pre[k + 1] += s_pre[k];
+        s_S = s_pre[s_nopen];
+      }
+      __syncthreads();
+    }
+    const int q = qi - nimg, S = s_S;
+    if (q >= rounds * S) break;  // uniform: past the last round
+    const int r = q / S, rem = q - r * S;
+    if (threadIdx.x == 0) {  // the open image and chunk of this entry
+      int lo = 0, hi = s_nopen - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= rem) lo = mid;
+        else hi = mid - 1;
+      }
+      s_img = s_open[lo];
+      s_chunk = rem - s_pre[lo];
       int go = 0;
       if (single && r == 0) {  // round 0 of a single image: this block's own candidates
-        go = wi.blk >= 0;
+        go = 1;
         for (int j = 0; j < NC; ++j) s_mu[j] = s_mu0[j];
-      } else if (wi.blk >= 0) {
-        LamState *sp = stv + wi.img;
+      } else {
+        LamState *sp = stv + s_img;
         for (int spin = 0;; ++spin) {
-          if (__hip_atomic_load(&sp->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-          if (__hip_atomic_load(&sp->round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= r) {
+          if (ld_agent(&sp->phase) != 0) break;
+          if (ld_agent(&sp->round) >= r) {
             go = 1;
             break;
           }
@@ -973,7 +1017,8 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
     }
     __syncthreads();
     if (!s_go) continue;  // uniform
-    const Img &d = D[wi.img];
+    const int img = s_img, blk = s_chunk;
+    const Img &d = D[img];
     float mu[NC];
 #pragma unroll
     for (int j = 0; j < NC; ++j) mu[j] = s_mu[j];
@@ -983,7 +1028,7 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
     const size_t nbins = d.L.bins(), n4 = nbins / 4;
     const GFD_AS1 float4 *q4 = reinterpret_cast<const GFD_AS1 float4 *>(G(d.q));
     const GFD_AS1 float4 *h4 = reinterpret_cast<const GFD_AS1 float4 *>(G(d.H2));
-    for (size_t i = (size_t)wi.blk * blockDim.x + threadIdx.x; i < n4; i += (size_t)d.nchunk * blockDim.x) {
+    for (size_t i = (size_t)blk * blockDim.x + threadIdx.x; i < n4; i += (size_t)d.nchunk * blockDim.x) {
       const float4 qa = q4[i], ta = h4[i];
       const float qs[4] = {qa.x, qa.y, qa.z, qa.w}, ts[4] = {ta.x, ta.y, ta.z, ta.w};
 #pragma unroll
@@ -997,7 +1042,7 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
         }
       }
     }
-    if (wi.blk == 0) {  // bins that do not fill a float4
+    if (blk == 0) {  // bins that do not fill a float4
       for (size_t i = n4 * 4 + threadIdx.x; i < nbins; i += blockDim.x) {
 #pragma unroll
         for (int j = 0; j < NC; ++j) {
@@ -1010,11 +1055,11 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
     }
     float h, l;
     block_sum_plain_then_df<2 * NC>(acc, h, l, scratch);
-    store_partial(G(d.part), d.npart, wi.blk, 2 * NC, h, l);
+    store_partial(G(d.part), d.npart, blk, 2 * NC, h, l);
     // the partial sums are stored by lanes of wave 0 (2 NC < 64), which also takes the count
     static_assert(2 * NC <= 64, "partials stored by the first wave");
     if (threadIdx.x < 64) __threadfence();
-    if (threadIdx.x == 0) is_last = atomicAdd(&stv[wi.img].done, 1) == d.nchunk - 1;
+    if (threadIdx.x == 0) is_last = atomicAdd(&stv[img].done, 1) == d.nchunk - 1;
     __syncthreads();
     if (is_last) {  // uniform over the block
       __threadfence();
@@ -1022,14 +1067,14 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
       // (at most 512 chunks: one batch of 8 per lane and value)
       reduce_partials<2 * NC, 8>(G(d.part), d.npart, d.nchunk, hi, lo, scratch);
       if (threadIdx.x == 0) {
-        LamState st = (single && r == 0) ? sst : stv[wi.img];
+        LamState st = (single && r == 0) ? sst : stv[img];
         float cand[NC];
         for (int j = 0; j < NC; ++j) cand[j] = st.cand[j];
         lam_absorb(st, NC, cand, hi, lo, hi + NC);
         const int fixed = lam_decide(st, r == rounds - 1);
         if (fixed) lam_commit(d, st, advance);
         st.done = 0;
-        lam_publish(stv + wi.img, st, fixed, r + 1, lq);
+        lam_publish(stv + img, st, fixed, r + 1, lq);
       }
     }
     __syncthreads();
@@ -1037,6 +1082,8 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
   if (threadIdx.x == 0 && atomicAdd(&lq->exits, 1) == (int)gridDim.x - 1) {
     __hip_atomic_store(&lq->next, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&lq->closed, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&lq->begun, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&lq->nopen, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&lq->exits, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -1415,17 +1462,18 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
 
 void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, bool advance) {
   // one launch for the whole search after the residual pass: blocks take the images' starts,
-  // then (round, chunk) entries from the set's queue, so the grid need not cover the chunks
+  // then the open images' (round, chunk) entries from the set's queue, so the grid need not
+  // cover the chunks
   const ItemRange one = add_one_per_image(set, sel);
-  const ItemRange chunks = add_items(set, sel, [](const Img &d) { return d.nchunk; });
+  size_t chunks = 0;
+  for (int i : sel) chunks += (size_t)set.imgs[i].nchunk;
   const int adv = advance ? 1 : 0;
   ImgSet *setp = &set;
   p.steps.push_back([=](hipStream_t s) -> hipError_t {
     if (one.n == 0) return hipSuccess;
-    const unsigned grid = (unsigned)std::min<size_t>(std::max(chunks.n, one.n), 256);
+    const unsigned grid = (unsigned)std::min<size_t>(std::max(chunks, one.n), 256);
     hipLaunchKernelGGL(k_lam_rounds, dim3(grid), dim3(512), 0, s, (const Img *)setp->dev,
-                       (const Item *)(setp->items_dev + one.off), (int)one.n, (const Item *)(setp->items_dev + chunks.off),
-                       (int)chunks.n, setp->st_base, setp->lamq, rounds, adv);
+                       (const Item *)(setp->items_dev + one.off), (int)one.n, setp->st_base, setp->lamq, rounds, adv);
     return hipGetLastError();
   });
 }

@@ -77,12 +77,15 @@ struct LamState {
   int round;  // -1: search opened by the residual pass; r >= 0: candidates of round r published
 };
 
-// Work queue of one launch of the search (shared by the images of the launch): next entry to
-// take, blocks that have left, and images whose lambda the launch has fixed.  All zero between
-// launches.
+// Work queue of one launch of the search (shared by the images of the launch), all zero between
+// launches: next entry to take, blocks that have left, images whose lambda the launch has fixed,
+// starts done, and the images whose start left the search open (open[0 .. nopen), room for
+// every image of the set follows the header).
 struct LamQueue {
-  int next, exits, closed;
+  int next, exits, closed, begun, nopen;
+  int open[1];
 };
+inline size_t lam_queue_bytes(int nimg) { return sizeof(LamQueue) + sizeof(int) * (size_t)(nimg > 1 ? nimg - 1 : 0); }
 
 GFD_HD inline float lam_relF(float hi, float lo, float TP) {
   // f / T - 1 with the subtraction done exactly when hi is close to TP

@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "piecewise_image", "textured_image", "psf_box", "psf_gaussian", "psf_inverse_quadratic",
-    "psf_binomial", "blur_periodic", "sigma2_for_bsnr", "Case", "make_case", "make_batch",
+    "psf_binomial", "blur_periodic", "sigma2_for_bsnr", "Case", "make_case", "make_batch", "batch_case",
     "BATCH_SIZES", "TABLE1_SETTINGS", "table1_case",
 ]
 
@@ -197,26 +197,29 @@ def make_case(config: int, size=None, image_index: int = 0) -> Case:
     raise ValueError(f"no single-image workload for config {config}")
 
 
-def make_batch(n: int = 64, sizes=None, config: int = 3) -> list:
-    """Mixed-size batch: size, PSF, BSNR in [20, 40] dB and w in {5, 7, 9} drawn per image."""
+def batch_case(k: int, sizes=None, config: int = 3) -> Case:
+    """Image k of the mixed-size batch: size, PSF, BSNR in [20, 40] dB and w in {5, 7, 9} drawn
+    from its own seed (so any image can be made on its own)."""
     sizes = sizes or BATCH_SIZES
-    out = []
-    for k in range(n):
-        rng = np.random.default_rng(1000 * config + k)
-        M, N = sizes[int(rng.integers(len(sizes)))]
-        u = piecewise_image(M, N, rng)
-        kind = int(rng.integers(3))
-        if kind == 0:
-            h = psf_box(9)
-        elif kind == 1:
-            h = psf_gaussian(float(rng.uniform(1.0, 3.0)), 25)
-        else:
-            h = psf_inverse_quadratic(15)
-        w = int(rng.choice([5, 7, 9]))
-        bsnr = float(rng.uniform(20.0, 40.0))
-        y, s2 = _observe(u, h, rng, bsnr_db=bsnr)
-        out.append(Case(f"b{k}_{M}x{N}_psf{kind}", u, h, y, s2, w, EPS_DEFAULT, 20))
-    return out
+    rng = np.random.default_rng(1000 * config + k)
+    M, N = sizes[int(rng.integers(len(sizes)))]
+    u = piecewise_image(M, N, rng)
+    kind = int(rng.integers(3))
+    if kind == 0:
+        h = psf_box(9)
+    elif kind == 1:
+        h = psf_gaussian(float(rng.uniform(1.0, 3.0)), 25)
+    else:
+        h = psf_inverse_quadratic(15)
+    w = int(rng.choice([5, 7, 9]))
+    bsnr = float(rng.uniform(20.0, 40.0))
+    y, s2 = _observe(u, h, rng, bsnr_db=bsnr)
+    return Case(f"b{k}_{M}x{N}_psf{kind}", u, h, y, s2, w, EPS_DEFAULT, 20)
+
+
+def make_batch(n: int = 64, sizes=None, config: int = 3) -> list:
+    """Mixed-size batch of n images (batch_case 0 .. n-1)."""
+    return [batch_case(k, sizes, config) for k in range(n)]
 
 
 # Table 1 of the paper: PSF and noise variance (on the [0, 255] scale) of the five settings.
