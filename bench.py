@@ -206,6 +206,8 @@ def batch_leg(steps: int, warmup: int, n_images: int = 64, ref=None) -> dict:
             gb.iterate(warmup, out, lam[:, :warmup].contiguous())
         lam_s = torch.empty((gb.count, steps), device=dev, dtype=torch.float32)
         ms_batch = timed(lambda n: gb.iterate(n, out, lam_s), steps)
+        nprof = 5
+        stage_us = {k: round(v / nprof * 1e3, 2) for k, v in gb.profile(nprof).items()}
     singles = [gfd.GFDeconv(p["y"], p["h"], p["sigma2"], p["w"], p["eps"]) for p in probs]
     outs = [torch.empty(p["y"].shape, device=dev, dtype=torch.float32) for p in probs]
     n_single = max(2, steps // 4)
@@ -228,7 +230,7 @@ def batch_leg(steps: int, warmup: int, n_images: int = 64, ref=None) -> dict:
                        f"1/(1+x^2+y^2), BSNR 20-40 dB, w in {{5, 7, 9}}, one step = one iteration of every image",
            "images": n_images, "pixels": total_px, "autotune": tuning,
            "value": round(total_px / (ms_batch * 1e-3) / 1e6, 1), "unit": "Mpixel-iters/s",
-           "ms_per_step": round(ms_batch, 4),
+           "ms_per_step": round(ms_batch, 4), "stage_us": stage_us,
            "roofline": {"bound": "hbm", "alg_bytes_per_step": alg, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)},
            "one_image_per_launch": {"value": round(total_px / (ms_single * 1e-3) / 1e6, 1),
@@ -289,7 +291,8 @@ def main():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tuning", type=str, default="",
-                    help="launch shapes instead of the autotuner: strip rows, forward row pairs, inverse rows")
+                    help="launch shapes instead of the autotuner: strip rows, forward row pairs, inverse rows"
+                         "[, mixed-radix rows, mixed-radix schedule]")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the deconvolution of one frame runs on a single device "
@@ -326,10 +329,11 @@ def main():
     g = gfd.GFDeconv(y, h, case.sigma2, case.w, case.eps)
     if args.tuning:
         vals = [int(x) for x in args.tuning.split(",")]
-        if len(vals) != 3:
-            raise SystemExit("--tuning takes three integers: strip rows, forward row pairs, inverse rows")
+        if len(vals) not in (3, 5):
+            raise SystemExit("--tuning takes 3 or 5 integers: strip rows, forward row pairs, inverse rows"
+                             "[, mixed-radix rows, mixed-radix schedule]")
         g.set_tuning(*vals)
-        tuning = dict(zip(("gf_strip_rows", "row_pairs_fwd", "rows_inv"), vals))
+        tuning = dict(zip(gfd.GFDeconv.TUNING_KEYS, vals))
     else:
         tuning = None if args.no_autotune else g.autotune(16)
     stream = torch.cuda.current_stream(dev)

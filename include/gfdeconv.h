@@ -235,28 +235,35 @@ gfd_status deconv_set_graph(gfd_ctx *ctx, int use_graph);
 gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_stages, void *stream);
 
 /*
- * deconv_autotune -- pick launch shapes for this context by timing: the guided filter's strip
- * height and the rows per block of the power-of-two row transforms are tried one knob at a
- * time (coordinate descent from the defaults, the strip height starting at the lowest one
- * whose strips all fit on the device at once), each candidate over `iters` replays of the
- * captured iteration (0 selects 4; at most 64), and the fastest is kept.  The arithmetic is
- * the same in every shape except where the filter's running sums restart (strip edges), so
- * results agree to rounding.  Needs a context with no
- * iterations run (after deconv_init or deconv_reset); the estimate and the search state are
- * restored afterwards.  choice_host (3 ints, host, or NULL) receives the strip height, the
- * forward row pairs per block and the inverse rows per block chosen for image 0.
+ * deconv_autotune -- pick launch shapes for this context by timing, one knob at a time
+ * (coordinate descent from the defaults, the strip height starting at the lowest one whose
+ * strips all fit on the device at once), each candidate over `iters` replays of the captured
+ * iteration (0 selects 4; at most 64), keeping the fastest.  The knobs, in choice order:
+ *   0 the guided filter's strip height (rows),
+ *   1 row pairs per block of the forward power-of-two (register-resident) row transforms,
+ *   2 rows per block of the inverse power-of-two row transforms,
+ *   3 rows per block of the mixed-radix (LDS-resident) row transforms (only tried when some
+ *     image has a side that is not a power of two in [256, 4096]),
+ *   4 the radix schedule of the mixed-radix transforms: 8 (radix-8 passes) or 4 (radix-4 passes)
+ *     (tried likewise).
+ * The transforms give the same result to rounding in every schedule, the filter in every
+ * strip height (its running sums restart at strip edges).  Needs a context with no iterations
+ * run (after deconv_init or deconv_reset); the estimate and the search state are restored
+ * afterwards.  choice_host (5 ints, host, or NULL) receives the five choices for image 0.
  * Synchronises `stream`.
  */
 gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stream);
 
 /*
  * deconv_set_tuning -- set the launch shapes without timing them, in deconv_autotune's order:
- * choice_host (3 ints, host) holds the guided filter's strip height in rows, the row pairs per
- * block of the forward row pass and the rows per block of the inverse row pass; 0 keeps a
- * default, and a value an image does not admit (not a power of two, or beyond the block's
+ * choice_host (5 ints, host) holds the guided filter's strip height in rows, the row pairs per
+ * block of the forward power-of-two row pass, the rows per block of the inverse one, the rows
+ * per block of the mixed-radix row passes and the mixed-radix schedule (8 or 4); 0 keeps a
+ * default, and a value an image does not admit (not a power of two, odd, or beyond the block's
  * threads or LDS) falls back to the default.  The results agree with other shapes to rounding
  * (as for deconv_autotune).  For repeating a measurement in a chosen shape.  Needs a context
- * with no iterations run; GFD_ERR_ARG for a NULL pointer or a negative value.
+ * with no iterations run; GFD_ERR_ARG for a NULL pointer, a negative value or a schedule other
+ * than 0, 4 or 8.
  */
 gfd_status deconv_set_tuning(gfd_ctx *ctx, const int *choice_host);
 

@@ -195,15 +195,18 @@ class GFDeconv:
         _check(load_library().deconv_reset(self.handle, _stream(self.device)))
         self._k_start = 0
 
+    TUNING_KEYS = ("gf_strip_rows", "row_pairs_fwd", "rows_inv", "rows_lds", "radix")
+
     def autotune(self, iters: int = 4) -> dict:
         """Time candidate launch shapes and keep the fastest (needs no iterations run yet)."""
-        ch = (_i * 3)()
+        ch = (_i * 5)()
         _check(load_library().deconv_autotune(self.handle, int(iters), ch, _stream(self.device)))
-        return {"gf_strip_rows": ch[0], "row_pairs_fwd": ch[1], "rows_inv": ch[2]}
+        return dict(zip(self.TUNING_KEYS, list(ch)))
 
-    def set_tuning(self, gf_strip_rows: int = 0, row_pairs_fwd: int = 0, rows_inv: int = 0):
+    def set_tuning(self, gf_strip_rows: int = 0, row_pairs_fwd: int = 0, rows_inv: int = 0, rows_lds: int = 0,
+                   radix: int = 0):
         """Set the launch shapes autotune would choose, without timing (0 keeps a default)."""
-        ch = (_i * 3)(int(gf_strip_rows), int(row_pairs_fwd), int(rows_inv))
+        ch = (_i * 5)(int(gf_strip_rows), int(row_pairs_fwd), int(rows_inv), int(rows_lds), int(radix))
         _check(load_library().deconv_set_tuning(self.handle, ch))
 
     def set_graph(self, use_graph: bool):

@@ -60,6 +60,10 @@ struct gfd_ctx {
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;  // graph capture and the context's own host reads (non-blocking)
   hipEvent_t done_ev = nullptr;      // recorded after the work of every stream-ordered call
+  // graph branches: the launches of one pass (one per kernel variant, on disjoint images) are
+  // captured on these streams, forked from and joined back into the capture stream
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> branch_ev;
   struct Bwd *bwd = nullptr;   // reverse-mode buffers and plans, built on first use
   Tuning tune;                 // launch shapes in use (deconv_autotune)
   Arena *arena = nullptr;      // allocation-free context: every buffer is carved from here
@@ -162,6 +166,8 @@ static void free_ctx(gfd_ctx *c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->done_ev) (void)hipEventDestroy(c->done_ev);
+  for (hipStream_t s : c->branch) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : c->branch_ev) (void)hipEventDestroy(e);
   for (void *p : c->allocs)
     if (p) (void)hipFree(p);
   for (ImgSet *s : {&c->main, &c->aux}) {
@@ -257,11 +263,47 @@ static hipError_t build_plans(gfd_ctx *c) {
   return e;
 }
 
+// One pass of the iteration into the capture: its launches (one per kernel variant, each on its
+// own images) become parallel branches of the graph, so that the launches of a batch's image
+// groups overlap and fill each other's tails; a pass with one launch stays on the capture stream.
+static hipError_t capture_pass(gfd_ctx *c, const Plan &p, size_t &ev) {
+  hipStream_t s = c->cap_stream;
+  if (p.steps.size() <= 1) return p.enqueue(s);
+  hipError_t e = hipEventRecord(c->branch_ev[ev], s);
+  const size_t fork = ev++;
+  for (size_t i = 0; i < p.steps.size() && e == hipSuccess; ++i) {
+    e = hipStreamWaitEvent(c->branch[i], c->branch_ev[fork], 0);
+    if (e == hipSuccess) e = p.steps[i](c->branch[i]);
+    if (e == hipSuccess) e = hipEventRecord(c->branch_ev[ev], c->branch[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->branch_ev[ev++], 0);
+  }
+  return e;
+}
+
 static gfd_status capture_graph(gfd_ctx *c) {
   if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  // streams and events for the branches: one stream per launch of the widest pass, one event
+  // per fork and per join (default priority, like every stream here)
+  size_t widest = 0, nev = 0;
+  for (const Plan &p : c->stage) {
+    widest = std::max(widest, p.steps.size());
+    if (p.steps.size() > 1) nev += 1 + p.steps.size();
+  }
+  while (c->branch.size() < widest) {
+    hipStream_t s = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    c->branch.push_back(s);
+  }
+  while (c->branch_ev.size() < nev) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->branch_ev.push_back(e);
+  }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = c->iter.enqueue(c->cap_stream);
+  hipError_t e = hipSuccess;
+  size_t ev = 0;
+  for (int k = 0; k < kStages && e == hipSuccess; ++k) e = capture_pass(c, c->stage[k], ev);
   hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
   if (e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -319,8 +361,8 @@ static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, I
   domain_dims(src, M, N);
   memset(&d, 0, sizeof(d));
   d.L = make_layout(M, N);
-  d.pm = make_plan(M);
-  d.pn = make_plan(N);
+  d.pm = make_plan(M, c->tune.radix);
+  d.pn = make_plan(N, c->tune.radix);
   d.rm = make_reg_plan(reg_plan_ok(M) ? M : 256);
   d.rn = make_reg_plan(reg_plan_ok(N) ? N : 256);
   d.w = src.w;
@@ -651,12 +693,16 @@ static gfd_status copy_estimates_out(gfd_ctx *c, float *u_out, hipStream_t s) {
 static hipError_t apply_tuning(gfd_ctx *c, const Tuning &t) {
   for (Img &d : c->main.imgs) {
     d.L = make_layout(d.L.M, d.L.N, t);
+    d.pm = make_plan(d.L.M, t.radix);
+    d.pn = make_plan(d.L.N, t.radix);
     gf_geometry(d, t.gf_ty);
   }
   if (c->count == 1) {
     Img &a = c->aux.imgs[0];
     const Img &m = c->main.imgs[0];
     a.L = m.L;
+    a.pm = m.pm;
+    a.pn = m.pn;
     a.gfTX = m.gfTX;
     a.gfTY = m.gfTY;
     a.gfNBY = m.gfNBY;
@@ -1313,12 +1359,22 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
     if (!have) gf_ty[ngf++] = fill;
   }
   const int seqs[] = {1, 2, 4};
-  for (int knob = 0; knob < 3 && ok; ++knob) {
-    const int *vals = knob == 0 ? gf_ty : seqs;
-    const int nv = knob == 0 ? ngf : 3;
+  const int rows[] = {2, 4, 8, 16};
+  const int radices[] = {8, 4};
+  // the LDS-resident transforms' knobs only where an image uses them (a side that is not a
+  // power of two in [256, 4096])
+  bool lds_rows = false, lds_any = false;
+  for (const Img &d : c->main.imgs) {
+    lds_rows = lds_rows || !reg_plan_ok(d.L.N);
+    lds_any = lds_any || !reg_plan_ok(d.L.N) || !reg_plan_ok(d.L.M);
+  }
+  for (int knob = 0; knob < kTuningKnobs && ok; ++knob) {
+    if ((knob == 3 && !lds_rows) || (knob == 4 && !lds_any)) continue;
+    const int *vals = knob == 0 ? gf_ty : knob <= 2 ? seqs : knob == 3 ? rows : radices;
+    const int nv = knob == 0 ? ngf : knob <= 2 ? 3 : knob == 3 ? 4 : 2;
     for (int v = 0; v < nv && ok; ++v) {
       Tuning t = best;
-      int &field = knob == 0 ? t.gf_ty : knob == 1 ? t.seq_fwd : t.seq_inv;
+      int &field = knob == 0 ? t.gf_ty : knob == 1 ? t.seq_fwd : knob == 2 ? t.seq_inv : knob == 3 ? t.rows_lds : t.radix;
       field = vals[v];
       float ms = 0.0f;
       ok = trial(t, ms);
@@ -1345,6 +1401,8 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
     choice_host[0] = d.gfTY;
     choice_host[1] = d.L.Rf / 2;
     choice_host[2] = d.L.Ri;
+    choice_host[3] = d.L.R;
+    choice_host[4] = best.radix == 4 ? 4 : 8;
   }
   return GFD_OK;
 }
@@ -1353,13 +1411,17 @@ gfd_status deconv_set_tuning(gfd_ctx *ctx, const int *choice_host) {
   g_err.clear();
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (ctx->iters != 0) return fail(GFD_ERR_STATE, "deconv_set_tuning needs a context with no iterations run");
-  if (!choice_host) return fail(GFD_ERR_ARG, "choice_host must point to 3 ints");
-  for (int i = 0; i < 3; ++i)
+  if (!choice_host) return fail(GFD_ERR_ARG, "choice_host must point to %d ints", kTuningKnobs);
+  for (int i = 0; i < kTuningKnobs; ++i)
     if (choice_host[i] < 0) return fail(GFD_ERR_ARG, "launch shapes must be >= 0 (0: default)");
+  if (choice_host[4] != 0 && choice_host[4] != 4 && choice_host[4] != 8)
+    return fail(GFD_ERR_ARG, "the radix schedule is 0 (default), 8 or 4");
   Tuning t;
   t.gf_ty = choice_host[0];
   t.seq_fwd = choice_host[1];
   t.seq_inv = choice_host[2];
+  t.rows_lds = choice_host[3];
+  t.radix = choice_host[4] == 8 ? 0 : choice_host[4];
   const hipError_t e = apply_tuning(ctx, t);
   if (e != hipSuccess) return fail(GFD_ERR_HIP, "deconv_set_tuning rebuild failed: %s", hipGetErrorString(e));
   return GFD_OK;

@@ -44,15 +44,18 @@ struct Layout {
 
 // Launch-shape choices that do not change results (the autotuner's knobs); 0 = default.
 struct Tuning {
-  int gf_ty = 0;    // rows per guided-filter strip
-  int seq_fwd = 0;  // row pairs per block of the register-resident forward row pass
-  int seq_inv = 0;  // rows per block of the register-resident inverse row pass
+  int gf_ty = 0;     // rows per guided-filter strip
+  int seq_fwd = 0;   // row pairs per block of the register-resident forward row pass
+  int seq_inv = 0;   // rows per block of the register-resident inverse row pass
+  int rows_lds = 0;  // image rows per block of the LDS-resident (mixed-radix) row passes
+  int radix = 0;     // radix schedule of the LDS-resident transforms: 0 (or 8) radix-8 passes, 4 radix-4 passes
 };
+constexpr int kTuningKnobs = 5;
 
 Layout make_layout(int M, int N, const Tuning &tune = Tuning{});
 size_t reg_seq_lds(int N);
 bool reg_seqs_ok(int N, int seqs);
-FftPlan make_plan(int L);
+FftPlan make_plan(int L, int radix = 0);
 
 constexpr int kLamAccFirst = 2 + 2 * kLamFirstCand;  // Einf, floor, f and slope per candidate
 constexpr int kLamAccSweep = 2 * kLamMaxCand;
@@ -215,6 +218,7 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel);
 hipError_t finalize_items(ImgSet &set);
+void sort_by_size(const ImgSet &set, std::vector<int> &imgs);
 void gf_geometry(Img &d, int ty = 0);
 int gf_fill_height(const Img &d);
 bool guided_filter_supported(int w);

@@ -319,6 +319,7 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   std::map<int, std::vector<int>> byR;  // key 2 r + clip
   for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
+    sort_by_size(set, kv.second);
     const size_t off = set.items_host.size();
     for (int i : kv.second) {
       const Img &d = set.imgs[i];

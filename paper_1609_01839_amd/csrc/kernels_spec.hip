@@ -1301,6 +1301,10 @@ Layout make_layout(int M, int N, const Tuning &tune) {
   // rows per block in the LDS-resident row passes: aim at >= 128-byte segments, LDS <= 64 KiB
   int R = 2;
   while (R * C < 16 && (size_t)(R * 2) * (N + 1) * 8 <= 64 * 1024) R *= 2;
+  // (a tuned value: even, and R rows of the inverse row pass within 64 KiB of LDS)
+  if (tune.rows_lds >= 2 && tune.rows_lds % 2 == 0 && tune.rows_lds <= 64 &&
+      (size_t)tune.rows_lds * (N + 1) * 8 <= 64 * 1024)
+    R = tune.rows_lds;
   L.R = R;
   // register-resident row passes (power-of-two N): T = N / 16 threads per sequence, `seqs`
   // sequences per block (forward: pairs of rows; inverse: rows)
@@ -1332,17 +1336,26 @@ bool reg_seqs_ok(int N, int seqs) {
          seqs * reg_seq_lds(N) <= 160 * 1024;
 }
 
-FftPlan make_plan(int L) {
+// Radix schedule of an LDS-resident transform of length L = 2^a 3^b 5^c: the power of two in
+// radix-8 passes (radix 0 or 8; the remainder as one radix-4 or radix-2 pass, or two radix-4
+// passes) or in radix-4 passes (radix 4; a leftover factor 2 as one radix-2 pass), then the 3s
+// and 5s.  Fewer passes mean fewer LDS round trips; radix-4 butterflies need fewer registers.
+FftPlan make_plan(int L, int radix) {
   FftPlan p = FftPlan{};
   p.L = L;
   int rad[kMaxPasses];
   int n = 0, rest = L, a = 0;
   while (rest % 2 == 0) { rest /= 2; ++a; }
-  int n8 = a / 3, rem = a % 3;
-  if (rem == 1 && n8 > 0) { n8 -= 1; rad[n++] = 4; rad[n++] = 4; }
-  else if (rem == 1) rad[n++] = 2;
-  else if (rem == 2) rad[n++] = 4;
-  for (int i = 0; i < n8; ++i) rad[n++] = 8;
+  if (radix == 4) {
+    if (a % 2) rad[n++] = 2;
+    for (int i = 0; i < a / 2; ++i) rad[n++] = 4;
+  } else {
+    int n8 = a / 3, rem = a % 3;
+    if (rem == 1 && n8 > 0) { n8 -= 1; rad[n++] = 4; rad[n++] = 4; }
+    else if (rem == 1) rad[n++] = 2;
+    else if (rem == 2) rad[n++] = 4;
+    for (int i = 0; i < n8; ++i) rad[n++] = 8;
+  }
   while (rest % 3 == 0) { rest /= 3; rad[n++] = 3; }
   while (rest % 5 == 0) { rest /= 5; rad[n++] = 5; }
   p.npass = n;
@@ -1383,11 +1396,22 @@ using GKey = std::tuple<int, int, int>;  // (register-resident?, threads or comp
 // sequences are interleaved LS apart in LDS (1 in the row passes, the tile width C in the
 // column passes), given the interleave the kernel is compiled for; 0: the run-time transform.
 static int fixed_len(int L, int LS, int compiled_LS) { return L == 4096 && LS == compiled_LS ? 4096 : 0; }
+// Largest images first within a launch: blocks are dealt in item order, so the longest work
+// starts first and the small images fill the tail.
+void sort_by_size(const ImgSet &set, std::vector<int> &imgs) {
+  std::stable_sort(imgs.begin(), imgs.end(), [&](int a, int b) {
+    return (size_t)set.imgs[a].L.M * set.imgs[a].L.N > (size_t)set.imgs[b].L.M * set.imgs[b].L.N;
+  });
+}
+
 static void group_by(const ImgSet &set, const std::vector<int> &sel, const std::function<GKey(const Img &)> &key,
                      const std::function<void(const GKey &, const std::vector<int> &)> &emit) {
   std::map<GKey, std::vector<int>> g;
   for (int i : sel) g[key(set.imgs[i])].push_back(i);
-  for (auto &kv : g) emit(kv.first, kv.second);
+  for (auto &kv : g) {
+    sort_by_size(set, kv.second);
+    emit(kv.first, kv.second);
+  }
 }
 
 template <class K4, class K8, class K16>

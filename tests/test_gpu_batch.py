@@ -197,6 +197,29 @@ def test_set_tuning_results():
     assert e < 1e-6 and np.allclose(lam, lam_ref, rtol=1e-5)
 
 
+def test_mixed_radix_tuning_knobs():
+    """The mixed-radix transforms' knobs (rows per block of the LDS row passes, radix-4 schedule)
+    change launch shapes and the order of the butterflies only: results agree with the default
+    shapes to rounding and with the oracle to the iterate bar."""
+    c = synth.make_case(1, size=(480, 640))
+    y, h = to_gpu(c.y), to_gpu(c.h.astype(np.float32))
+    iters = 4
+    with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as ref:
+        u_ref, lam_ref = (t.cpu().numpy() for t in ref.iterate(iters))
+    ref_o, _ = oracle.deconvolve(c.y.astype(np.float64), c.h.astype(np.float32).astype(np.float64), c.sigma2, c.w,
+                                 float(np.float32(c.eps)), iters)
+    for rows, radix in ((2, 4), (8, 8), (4, 4)):
+        with gfd.GFDeconv(y, h, c.sigma2, c.w, c.eps) as g:
+            with pytest.raises(gfd.GFDError):
+                g.set_tuning(0, 0, 0, 0, 3)    # schedules are 8 and 4
+            g.set_tuning(0, 0, 0, rows, radix)
+            u, lam = (t.cpu().numpy() for t in g.iterate(iters))
+        e = float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref))
+        eo = float(np.linalg.norm(u - ref_o) / np.linalg.norm(ref_o))
+        print(f"rows {rows} radix {radix}: vs default {e:.2e}, vs oracle {eo:.2e}")
+        assert e < 1e-6 and eo < 1e-5 and np.allclose(lam, lam_ref, rtol=1e-5)
+
+
 def test_autotune_batch():
     cases = synth.make_batch(4, sizes=SMALL_SIZES, config=19)
     probs = problems(cases)
