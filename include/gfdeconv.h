@@ -56,10 +56,15 @@ enum {
                                iteration, 10 for a warm start or a stand-alone search) */
 };
 
-/* Widest guided-filter window this build supports (w <= GFD_MAX_WINDOW; r = (w-1)/2 <= 8): the
- * filter keeps the last w rows of its inputs and coefficients in registers, one slot per row.
- * Every entry point that takes w returns GFD_ERR_UNIMPLEMENTED for an odd w above this. */
-#define GFD_MAX_WINDOW 17
+/* Widest guided-filter window of the single-pass strip kernels (r = (w-1)/2 <= 8): they keep the
+ * last w rows of their inputs and coefficients in registers, one slot per row.  Wider windows,
+ * up to w = min(M, N), run as separable box passes (vertical sliding sums, then horizontal FP64
+ * prefix sums, each a launch) whose cost per pixel does not depend on w; they need window-sum and
+ * coefficient planes: a context allocates 6 float planes per such image at set-up, and each call
+ * of a context-free filter allocates its planes stream-ordered (hipMallocAsync / hipFreeAsync on
+ * the call's stream: 6 for the grey filters, 17 for the colour filter, plus M x (N + 1) doubles
+ * when N > 4096). */
+#define GFD_STRIP_MAX_WINDOW 17
 
 /*
  * deconv_init -- per-image set-up (Sec. 3.1 Step 0, plus the transforms the solves need).
@@ -69,8 +74,8 @@ enum {
  *          (i - kh/2, j - kw/2).  Its sum must be non-zero (the solve for u_I divides by F(h) at
  *          the zero frequency).
  *   sigma2 noise variance, >= 0 (on the same intensity scale as y).
- *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N) and w <= GFD_MAX_WINDOW, else
- *          GFD_ERR_ARG, or GFD_ERR_UNIMPLEMENTED above GFD_MAX_WINDOW) and regulariser (> 0,
+ *   w, eps guided-filter window side (odd, 1 <= w <= min(M, N), else GFD_ERR_ARG; windows
+ *          wider than GFD_STRIP_MAX_WINDOW take the separable passes) and regulariser (> 0,
  *          finite).
  *   rho    discrepancy factor of the set K (Sec. 3.2), 0 < rho <= 1; rho <= 0 selects Eq.(12).
  * The estimate starts at u_E = 0 (Step 0).  Allocates device memory; synchronises `stream`
@@ -152,9 +157,10 @@ gfd_status deconv_iterate(gfd_ctx *ctx, int n_iter, float *u_out, float *lambda_
 /*
  * guided_filter -- u = guidfilter(u_I, u_p, w, eps), Sec. 2 Eqs.(3)-(5); context-free.
  *   uI (guidance), up (filtering input), u (output): device M x N float32; u must not alias
- *   uI or up.  Windows are w x w (odd w, 1 <= w <= min(M, N); GFD_ERR_UNIMPLEMENTED for
- *   w > GFD_MAX_WINDOW), wrap periodically, and every mean divides by w^2.  M, N in
- *   [1, 65536] (no factorisation constraint here).
+ *   uI or up.  Windows are w x w (odd w, 1 <= w <= min(M, N), else GFD_ERR_ARG), wrap
+ *   periodically, and every mean divides by w^2.  M, N in [1, 65536] (no factorisation
+ *   constraint here).  w > GFD_STRIP_MAX_WINDOW allocates temporaries stream-ordered
+ *   (GFD_ERR_HIP if that fails).
  */
 gfd_status guided_filter(const float *uI, const float *up, float *u, int M, int N, int w, float eps,
                          void *stream);

@@ -19,14 +19,14 @@ import torch
 __all__ = ["GFDError", "GFDeconv", "GFDeconvBatch", "GfdImage", "GFDeconvFn", "deconvolve_autograd", "deconvolve",
            "deconvolve_static", "guided_filter", "guided_filter_clipped", "guided_filter_color", "spectral_solve", "discrepancy_lambda",
            "library_path", "load_library", "EXPORTS", "FLAG_INF_BRANCH", "FLAG_NO_ROOT", "FLAG_NONFINITE",
-           "FLAG_UNCONVERGED", "MAX_WINDOW"]
+           "FLAG_UNCONVERGED", "STRIP_MAX_WINDOW"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libgfdeconv.so"
 _lib = None
 
 FLAG_INF_BRANCH, FLAG_NO_ROOT, FLAG_NONFINITE, FLAG_UNCONVERGED = 1, 2, 4, 8
-MAX_WINDOW = 17
+STRIP_MAX_WINDOW = 17  # widest window of the single-pass filter kernels; wider ones run as separable passes
 BOUNDARY_PERIODIC, BOUNDARY_CLIP, BOUNDARY_PAD = 0, 1, 2
 _ERRNAMES = {-1: "GFD_ERR_ARG", -2: "GFD_ERR_SIZE", -3: "GFD_ERR_HIP", -4: "GFD_ERR_NOMEM", -5: "GFD_ERR_STATE",
              -6: "GFD_ERR_UNIMPLEMENTED"}

@@ -344,8 +344,6 @@ static gfd_status check_image(const gfd_image &d, int idx) {
   if (!(d.eps > 0.0f) || !isfinite(d.eps)) return fail(GFD_ERR_ARG, "image %d: eps must be finite and > 0", idx);
   if (!(d.rho <= 1.0) || !isfinite(d.rho))
     return fail(GFD_ERR_ARG, "image %d: rho must be <= 1 (<= 0 selects Eq.(12))", idx);
-  if (!guided_filter_supported(d.w))
-    return fail(GFD_ERR_UNIMPLEMENTED, "image %d: w=%d: windows wider than 17 are not built", idx, d.w);
   return GFD_OK;
 }
 
@@ -397,8 +395,17 @@ static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, I
   ALLOC(u0, P);
   ALLOC(twMd, M);
   ALLOC(twNd, N);
+  float *wV = nullptr, *wa = nullptr, *wb = nullptr;
+  if (gf_wide(src.w)) {  // the separable filter passes' window sums and coefficients
+    ALLOC(wV, 4 * P);
+    ALLOC(wa, P);
+    ALLOC(wb, P);
+  }
 #undef ALLOC
   if (e != hipSuccess) return e;
+  d.wV = wV;
+  d.wa = wa;
+  d.wb = wb;
   d.twM = twM;
   d.twN = twN;
   d.H = H;
@@ -1112,7 +1119,6 @@ static gfd_status guided_filter_any(const float *uI, const float *up, float *u, 
     return pa < pb + bytes && pb < pa + bytes;
   };
   if (overlap(u, uI) || overlap(u, up)) return fail(GFD_ERR_ARG, "u must not overlap uI or up");
-  if (!guided_filter_supported(w)) return fail(GFD_ERR_UNIMPLEMENTED, "w=%d: windows wider than 17 are not built", w);
   HIPCHK(launch_guided_filter_plain(uI, up, u, M, N, w, eps, clip, (hipStream_t)stream));
   return GFD_OK;
 }
@@ -1137,7 +1143,6 @@ gfd_status guided_filter_color(const float *I3, const float *up, float *u, int M
   const char *pu = (const char *)u, *pi = (const char *)I3, *pp = (const char *)up;
   if ((pu < pi + 3 * bytes && pi < pu + bytes) || (pu < pp + bytes && pp < pu + bytes))
     return fail(GFD_ERR_ARG, "u must not overlap I3 or up");
-  if (!guided_filter_supported(w)) return fail(GFD_ERR_UNIMPLEMENTED, "w=%d: windows wider than 17 are not built", w);
   HIPCHK(launch_guided_filter_color(I3, up, u, M, N, w, eps, (hipStream_t)stream));
   return GFD_OK;
 }

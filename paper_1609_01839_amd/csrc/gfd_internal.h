@@ -101,6 +101,9 @@ struct Img {
   struct AdjState *ad;
   float *geps_hist, *gs_hist;   // per-iteration eps gradient and scale gradient
   int bxTX, bxTY, bxNBY;        // strip geometry of the adjoint's box passes
+  // windows wider than the strip kernels hold (r > kGfRmax): the separable passes' window sums
+  // (4 planes) and the coefficients a, b between the filter's two stages; null otherwise
+  float *wV, *wa, *wb;
 };
 
 // Per-image scalars of one reverse-mode iteration.
@@ -222,6 +225,7 @@ void sort_by_size(const ImgSet &set, std::vector<int> &imgs);
 void gf_geometry(Img &d, int ty = 0);
 int gf_fill_height(const Img &d);
 bool guided_filter_supported(int w);
+bool gf_wide(int w);  // the window runs as separable passes (wider than the strip kernels hold)
 
 // Reverse mode (kernels_adj.hip).
 void adj_geometry(Img &d);

@@ -30,6 +30,7 @@
 
 #include "box_sum.h"
 #include "gfd_internal.h"
+#include "wide_box.h"
 
 namespace gfd {
 
@@ -278,6 +279,42 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
   }
 }
 
+// The same three stages for windows wider than the strip kernel holds (r > kGfRmax), as
+// separable box stages on the image's descriptor; the eps-gradient partials are per image row.
+template <class S>
+struct WideAdj {
+  static constexpr int NF = S::NF, NR = S::NR, NE = S::NE;
+  static constexpr unsigned kT = S::kT;
+  static constexpr bool kEps = S::kEps;
+  __device__ static void load(const WideArgs &a, size_t g, float (&r)[NR]) { S::load(*a.d, g, r); }
+  __device__ static void eload(const WideArgs &a, size_t g, float (&e)[NE]) { S::eload(*a.d, g, e); }
+  __device__ static void fields(const float (&r)[NR], const float (&c)[4], float (&v)[NF]) {
+    S::fields(r, c[0], c[1], v);
+  }
+  __device__ static void emit(const WideArgs &a, size_t g, const float (&B)[NF], const float (&r)[NR],
+                              const float (&e)[NE], const float (&c)[4], float &eacc) {
+    S::emit(*a.d, g, B, r, e, c[0], c[1], eacc);
+  }
+};
+
+static hipError_t launch_box_wide(const ImgSet &set, int i, int stage, hipStream_t s) {
+  const Img &d = set.imgs[i];
+  WideArgs a = {};
+  a.d = set.dev + i;
+  a.V = d.wV;
+  a.eps_part = d.geps_part;
+  a.cen[0] = state_field(d.st, offsetof(LamState, meanI));
+  a.cen[1] = state_field(d.st, offsetof(LamState, meanP));
+  a.M = d.L.M;
+  a.N = d.L.N;
+  a.r = (d.w - 1) / 2;
+  a.clip = d.clip;
+  a.eps = d.eps;
+  if (stage == 1) return wide_stage<WideAdj<BoxStage1>>(a, s);
+  if (stage == 2) return wide_stage<WideAdj<BoxStage2>>(a, s);
+  return wide_stage<WideAdj<BoxStage3>>(a, s);
+}
+
 // ============================================================================ lambda of the replayed iteration
 // The forward's lambda history drives the recomputation: lambda, lambda* and the flags of
 // iteration k.
@@ -494,6 +531,12 @@ __global__ void k_adj_out(const Img *__restrict__ D, const Item *__restrict__ W,
 // ============================================================================ host side
 void adj_geometry(Img &d) {
   const int R = (d.w - 1) / 2;
+  if (R > kGfRmax) {  // separable passes: one eps-gradient partial per image row
+    d.bxTX = d.L.N;
+    d.bxTY = 1;
+    d.bxNBY = d.L.M;
+    return;
+  }
   d.bxTX = std::min(kGfThreads - 2 * R, d.L.N);
   d.bxTY = std::min(64, d.L.M);
   d.bxNBY = (d.L.M + d.bxTY - 1) / d.bxTY;
@@ -508,6 +551,12 @@ void plan_box_stage(Plan &p, ImgSet &set, const std::vector<int> &sel, int stage
   std::map<int, std::vector<int>> byR;  // key 2 r + clip
   for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
+    if (kv.first / 2 > kGfRmax) {
+      ImgSet *setp = &set;
+      for (int i : kv.second)
+        p.steps.push_back([setp, i, stage](hipStream_t s) { return launch_box_wide(*setp, i, stage, s); });
+      continue;
+    }
     ItemRange r = add_items(set, kv.second, [](const Img &d) { return adj_strips(d); });
     const int R = kv.first / 2;
     const bool clip = (kv.first & 1) != 0;

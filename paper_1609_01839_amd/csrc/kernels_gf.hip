@@ -20,10 +20,14 @@
 // With CLIP, windows are clipped to the image instead of wrapping: pixels outside the image
 // enter the sums as zeros, every mean divides by the number of the window's pixels inside the
 // image, and windows centred outside the image contribute no coefficients.
+//
+// Windows wider than the register rings hold (r > kGfRmax) run as two separable box stages
+// (wide_box.h): window means of I, p, I^2, I p -> a, b; window means of a, b -> u.
 #include <map>
 
 #include "box_sum.h"
 #include "gfd_internal.h"
+#include "wide_box.h"
 
 namespace gfd {
 
@@ -260,7 +264,82 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
   else gf_strip<R, CLIP, false>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
 }
 
-bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1 && (w - 1) / 2 <= kGfRmax; }
+bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1; }
+bool gf_wide(int w) { return (w - 1) / 2 > kGfRmax; }
+
+// ---------------------------------------------------------------- windows of any width
+// The two stages of the filter as separable box stages, in the same mean-centred variables as
+// the strip kernel (src = {u_I, u_p}, dst = {a, b}, cen = {centre of u_I, centre of u_p}).
+struct WideGf1 {  // window means of I, p, I^2, I p  ->  a, b (Eqs. 3-4)
+  static constexpr int NF = 4, NR = 2, NE = 1;
+  static constexpr unsigned kT = 0u;
+  static constexpr bool kEps = false;
+  __device__ static void load(const WideArgs &a, size_t g, float (&r)[NR]) {
+    r[0] = a.src[0][g];
+    r[1] = a.src[1][g];
+  }
+  __device__ static void eload(const WideArgs &, size_t, float (&e)[NE]) { e[0] = 0.0f; }
+  __device__ static void fields(const float (&r)[NR], const float (&c)[4], float (&v)[NF]) {
+    const float I = __fsub_rn(r[0], c[0]), p = __fsub_rn(r[1], c[1]);
+    v[0] = I;
+    v[1] = p;
+    v[2] = I * I;
+    v[3] = I * p;
+  }
+  __device__ static void emit(const WideArgs &a, size_t g, const float (&B)[NF], const float (&)[NR],
+                              const float (&)[NE], const float (&)[4], float &) {
+    const float mu = B[0], pb = B[1];
+    const float var = fmaxf(__fmaf_rn(-mu, mu, B[2]), 0.0f);
+    const float cov = __fmaf_rn(-mu, pb, B[3]);
+    const float A = cov * __builtin_amdgcn_rcpf(var + a.eps);
+    a.dst[0][g] = A;
+    a.dst[1][g] = __fmaf_rn(-A, mu, pb);
+  }
+};
+
+struct WideGf2 {  // window means of a, b  ->  u = abar I + bbar (Eq. 5)
+  static constexpr int NF = 2, NR = 2, NE = 1;
+  static constexpr unsigned kT = 0u;
+  static constexpr bool kEps = false;
+  __device__ static void load(const WideArgs &a, size_t g, float (&r)[NR]) {
+    r[0] = a.dst[0][g];
+    r[1] = a.dst[1][g];
+  }
+  __device__ static void eload(const WideArgs &a, size_t g, float (&e)[NE]) { e[0] = a.src[0][g]; }
+  __device__ static void fields(const float (&r)[NR], const float (&)[4], float (&v)[NF]) {
+    v[0] = r[0];
+    v[1] = r[1];
+  }
+  __device__ static void emit(const WideArgs &a, size_t g, const float (&B)[NF], const float (&)[NR],
+                              const float (&e)[NE], const float (&c)[4], float &) {
+    a.out[g] = __fadd_rn(__fmaf_rn(B[0], __fsub_rn(e[0], c[0]), B[1]), c[1]);
+  }
+};
+
+static hipError_t launch_gf_wide(const WideArgs &a, hipStream_t s) {
+  hipError_t e = wide_stage<WideGf1>(a, s);
+  return e == hipSuccess ? wide_stage<WideGf2>(a, s) : e;
+}
+
+// The filter of image d of a descriptor set as separable passes, centred like the strip kernel
+// (the image means kept in its lambda state).
+static WideArgs gf_wide_args(const Img &d) {
+  WideArgs a = {};
+  a.src[0] = d.uI;
+  a.src[1] = d.uP;
+  a.dst[0] = d.wa;
+  a.dst[1] = d.wb;
+  a.out = d.uE;
+  a.V = d.wV;
+  a.cen[0] = state_field(d.st, offsetof(LamState, meanI));
+  a.cen[1] = state_field(d.st, offsetof(LamState, meanP));
+  a.M = d.L.M;
+  a.N = d.L.N;
+  a.r = (d.w - 1) / 2;
+  a.clip = d.clip;
+  a.eps = d.eps;
+  return a;
+}
 
 static void gf_tiles(int M, int N, int R, int ty, int &TX, int &TY, int &nbx, int &nby) {
   TX = kGfThreads - 4 * R;
@@ -272,6 +351,12 @@ static void gf_tiles(int M, int N, int R, int ty, int &TX, int &TY, int &nbx, in
 }
 
 void gf_geometry(Img &d, int ty) {
+  if (gf_wide(d.w)) {  // separable passes: no strips
+    d.gfTX = d.L.N;
+    d.gfTY = d.L.M;
+    d.gfNBY = 1;
+    return;
+  }
   int nbx;
   gf_tiles(d.L.M, d.L.N, (d.w - 1) / 2, ty, d.gfTX, d.gfTY, nbx, d.gfNBY);
 }
@@ -296,6 +381,7 @@ void gf_geometry(Img &d, int ty) {
 // fewer halo rows; more strips than resident blocks leave a second, mostly idle wave.
 int gf_fill_height(const Img &d) {
   const int r = (d.w - 1) / 2;
+  if (gf_wide(d.w)) return 0;
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
@@ -320,6 +406,12 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
     sort_by_size(set, kv.second);
+    if (kv.first / 2 > kGfRmax) {  // one stream-ordered sequence of separable passes per image
+      ImgSet *setp = &set;
+      for (int i : kv.second)
+        p.steps.push_back([setp, i](hipStream_t s) { return launch_gf_wide(gf_wide_args(setp->imgs[i]), s); });
+      continue;
+    }
     const size_t off = set.items_host.size();
     for (int i : kv.second) {
       const Img &d = set.imgs[i];
@@ -340,6 +432,33 @@ hipError_t launch_guided_filter_plain(const float *uI, const float *uP, float *u
                                       bool clip, hipStream_t s) {
   const int r = (w - 1) / 2;
   if (!guided_filter_supported(w)) return hipErrorInvalidValue;
+  if (gf_wide(w)) {
+    // separable passes: 4 planes of window sums and a, b (and the row prefixes of rows wider
+    // than kWideMaxN), stream-ordered temporaries
+    const size_t P = (size_t)M * N;
+    const size_t npre = N > kWideMaxN ? (size_t)M * (N + 1) : 0;
+    float *tmp = nullptr;
+    hipError_t e = hipMallocAsync((void **)&tmp, 6 * P * sizeof(float) + npre * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    WideArgs a = {};
+    a.pre = npre ? reinterpret_cast<double *>(tmp + 6 * P) : nullptr;
+    a.src[0] = uI;
+    a.src[1] = uP;
+    a.V = tmp;
+    a.dst[0] = tmp + 4 * P;
+    a.dst[1] = tmp + 5 * P;
+    a.out = u;
+    a.cen[0] = uI;  // the first pixels, like the strip kernel
+    a.cen[1] = uP;
+    a.M = M;
+    a.N = N;
+    a.r = r;
+    a.clip = clip ? 1 : 0;
+    a.eps = eps;
+    e = launch_gf_wide(a, s);
+    const hipError_t ef = hipFreeAsync(tmp, s);
+    return e != hipSuccess ? e : ef;
+  }
   int TX, TY, nbx, nby;
   gf_tiles(M, N, r, 0, TX, TY, nbx, nby);
 #define GFD_LAUNCH_GFP(RR)                                                                          \

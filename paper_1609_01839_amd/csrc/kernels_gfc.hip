@@ -13,9 +13,12 @@
 // once per strip.  The 3 x 3 systems are solved by cofactors in FP64: the covariance of strongly
 // correlated channels is nearly singular at the scale of eps, and FP32 cofactors would lose
 // most of their digits to cancellation.  Windows wrap periodically and every mean divides
-// by w^2.  Inputs are shifted by their first pixels before products are formed.
+// by w^2.  Inputs are shifted by their first pixels before products are formed.  Windows
+// wider than the register rings hold (r > kGfRmax) run as two separable box stages
+// (wide_box.h) with the same fields and the same FP64 solve.
 #include "box_sum.h"
 #include "gfd_internal.h"
+#include "wide_box.h"
 
 namespace gfd {
 
@@ -67,6 +70,57 @@ __device__ __forceinline__ void gfc_coeffs(const float (&m)[kC1], float eps, flo
   ab[2] = (float)a2;
   ab[3] = (float)(pb - a0 * mr - a1 * mg - a2 * mb);
 }
+
+// The two stages as separable box stages: src = {I_r, I_g, I_b, p}, dst = {a_r, a_g, a_b, b},
+// cen = the first pixels of the four inputs.
+struct WideGfc1 {  // the 13 window means  ->  a, b
+  static constexpr int NF = kC1, NR = 4, NE = 1;
+  static constexpr unsigned kT = 0u;
+  static constexpr bool kEps = false;
+  __device__ static void load(const WideArgs &a, size_t g, float (&r)[NR]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) r[c] = a.src[c][g];
+  }
+  __device__ static void eload(const WideArgs &, size_t, float (&e)[NE]) { e[0] = 0.0f; }
+  __device__ static void fields(const float (&r)[NR], const float (&c)[4], float (&v)[NF]) {
+    float x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = __fsub_rn(r[k], c[k]);
+    gfc_fields(x, v);
+  }
+  __device__ static void emit(const WideArgs &a, size_t g, const float (&B)[NF], const float (&)[NR],
+                              const float (&)[NE], const float (&)[4], float &) {
+    float ab[kC2];
+    gfc_coeffs(B, a.eps, ab);
+#pragma unroll
+    for (int k = 0; k < kC2; ++k) a.dst[k][g] = ab[k];
+  }
+};
+
+struct WideGfc2 {  // window means of a, b  ->  u = abar . I + bbar
+  static constexpr int NF = kC2, NR = kC2, NE = 3;
+  static constexpr unsigned kT = 0u;
+  static constexpr bool kEps = false;
+  __device__ static void load(const WideArgs &a, size_t g, float (&r)[NR]) {
+#pragma unroll
+    for (int k = 0; k < kC2; ++k) r[k] = a.dst[k][g];
+  }
+  __device__ static void eload(const WideArgs &a, size_t g, float (&e)[NE]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) e[c] = a.src[c][g];
+  }
+  __device__ static void fields(const float (&r)[NR], const float (&)[4], float (&v)[NF]) {
+#pragma unroll
+    for (int k = 0; k < kC2; ++k) v[k] = r[k];
+  }
+  __device__ static void emit(const WideArgs &a, size_t g, const float (&B)[NF], const float (&)[NR],
+                              const float (&e)[NE], const float (&c)[4], float &) {
+    float acc = B[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc = __fmaf_rn(B[k], __fsub_rn(e[k], c[k]), acc);
+    a.out[g] = __fadd_rn(acc, c[3]);
+  }
+};
 
 }  // namespace
 
@@ -215,6 +269,35 @@ hipError_t launch_guided_filter_color(const float *I3, const float *up, float *u
                                       hipStream_t s) {
   const int r = (w - 1) / 2;
   if (!guided_filter_supported(w)) return hipErrorInvalidValue;
+  if (gf_wide(w)) {
+    // separable passes: 13 planes of window sums and the 4 coefficient planes (and the row
+    // prefixes of rows wider than kWideMaxN), stream-ordered temporaries
+    const size_t P = (size_t)M * N;
+    const size_t npre = N > kWideMaxN ? (size_t)M * (N + 1) : 0;
+    float *tmp = nullptr;
+    hipError_t e = hipMallocAsync((void **)&tmp, (kC1 + kC2) * P * sizeof(float) + npre * sizeof(double), s);
+    if (e != hipSuccess) return e;
+    WideArgs a = {};
+    a.pre = npre ? reinterpret_cast<double *>(tmp + (kC1 + kC2) * P) : nullptr;
+    a.V = tmp;
+    for (int c = 0; c < 3; ++c) {
+      a.src[c] = I3 + c * P;
+      a.cen[c] = I3 + c * P;  // the first pixels, like the strip kernel
+    }
+    a.src[3] = up;
+    a.cen[3] = up;
+    for (int k = 0; k < kC2; ++k) a.dst[k] = tmp + (kC1 + k) * P;
+    a.out = u;
+    a.M = M;
+    a.N = N;
+    a.r = r;
+    a.clip = 0;
+    a.eps = eps;
+    e = wide_stage<WideGfc1>(a, s);
+    if (e == hipSuccess) e = wide_stage<WideGfc2>(a, s);
+    const hipError_t ef = hipFreeAsync(tmp, s);
+    return e != hipSuccess ? e : ef;
+  }
   int TX = kGfThreads - 4 * r, TY = 64;
   if (TX > N) TX = N;
   if (TY > M) TY = M;

@@ -46,7 +46,7 @@ def test_invalid_arguments_are_rejected_without_gpu():
         (64, 64, 3, 3, 1.0, 3, 0.0, 1.0, -1),         # eps must be > 0
         (64, 64, 3, 3, 1.0, 3, float("nan"), 1.0, -1),
         (64, 64, 3, 3, 1.0, 3, 1.0, 1.5, -1),         # rho > 1
-        (64, 64, 3, 3, 1.0, 19, 1.0, 1.0, -6),        # wider windows are not built
+        (64, 32, 3, 3, 1.0, 33, 1.0, 1.0, -1),        # window wider than the image (N = 32)
     ]
     for M, N, kh, kw, s2, w, eps, rho, want in cases:
         rc = lib.deconv_init(ctypes.byref(ctx), fake, M, N, fake, kh, kw, s2, w, eps, rho, None)
@@ -74,7 +74,7 @@ def test_guided_filter_clipped_argument_checks():
     assert lib.guided_filter_clipped(None, b, c, 16, 16, 3, 1.0, None) == -1
     assert lib.guided_filter_clipped(a, b, c, 16, 16, 2, 1.0, None) == -1
     assert lib.guided_filter_clipped(a, b, c, 16, 16, 3, 0.0, None) == -1
-    assert lib.guided_filter_clipped(a, b, c, 64, 64, 19, 1.0, None) == -6
+    assert lib.guided_filter_clipped(a, b, c, 64, 32, 33, 1.0, None) == -1  # w > N
     assert lib.guided_filter_clipped(a, ctypes.c_void_p(0x30000 - 8), c, 16, 16, 3, 1.0, None) == -1
 
 
@@ -86,7 +86,7 @@ def test_guided_filter_color_argument_checks():
     assert lib.guided_filter_color(a, b, c, 16, 16, 17, 1.0, None) == -1
     assert lib.guided_filter_color(a, b, c, 16, 0, 1, 1.0, None) == -2
     assert lib.guided_filter_color(a, b, c, 16, 16, 3, 0.0, None) == -1
-    assert lib.guided_filter_color(a, b, c, 64, 64, 19, 1.0, None) == -6
+    assert lib.guided_filter_color(a, b, c, 16, 64, 19, 1.0, None) == -1   # w > M
     # u inside the third channel plane of I3 (planes of 16 * 16 floats)
     assert lib.guided_filter_color(a, b, ctypes.c_void_p(0x100000 + 2 * 1024 + 8), 16, 16, 3, 1.0, None) == -1
     assert lib.guided_filter_color(a, b, ctypes.c_void_p(0x200000 - 4), 16, 16, 3, 1.0, None) == -1  # overlaps up
@@ -153,4 +153,4 @@ def test_static_entry_point_rejects_before_touching_the_device():
     assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 4, 1.0, -1.0, 3, fake, None, None) == -1
     assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 5, 1.0, -1.0, -1, fake, None, None) == -1
     assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 5, 1.0, -1.0, 3, None, None, None) == -1
-    assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 19, 1.0, -1.0, 3, fake, None, None) == -6
+    assert lib.deconvolve_static(fake, 64, 64, fake, 9, 9, 1.0, 65, 1.0, -1.0, 3, fake, None, None) == -1

@@ -1,0 +1,196 @@
+"""GPU parity of windows wider than the single-pass strip kernels hold (w > 17, the separable box
+passes) against the FP64 oracle: the stand-alone grey filters (periodic and clipped, windows up
+to min(M, N), rows longer than the horizontal pass's LDS row), the colour filter, the iteration
+(periodic, clipped, padded), a batch mixing narrow and wide windows, the reverse mode and the
+allocation-free entry point.  Bars as for the narrow windows."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import adjoint as adj
+from oracle import boundary as bd
+import paper_1609_01839_amd as gfd
+import synth
+from _parity import assert_parity, report, run_trajectory
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def to_gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(DEV)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def filter_inputs(M, N, seed):
+    rng = np.random.default_rng(seed)
+    I = synth.piecewise_image(M, N, rng, n_shapes=8) + 5.0 * rng.standard_normal((M, N))
+    p = I + 20.0 * rng.standard_normal((M, N))
+    return I.astype(np.float32), p.astype(np.float32)
+
+
+# (M, N, w): just past the strip kernels, a few widths, w = min(M, N) (a periodic window that
+# holds a whole row or column), ragged sizes, and rows longer than 4096 pixels
+WIDE_GF = [(96, 128, 19), (64, 200, 33), (128, 96, 65), (45, 75, 45), (75, 45, 45), (33, 1000, 21),
+           (20, 4500, 19)]
+
+
+@pytest.mark.parametrize("M,N,w", WIDE_GF)
+def test_wide_guided_filter_parity(M, N, w):
+    I, p = filter_inputs(M, N, M * 7 + N + w)
+    eps = float(np.float32(650.25))
+    out = gfd.guided_filter(to_gpu(I), to_gpu(p), w, eps).cpu().numpy()
+    ref = oracle.guided_filter(I.astype(np.float64), p.astype(np.float64), w, eps)
+    e = rel_l2(out, ref)
+    emax = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+    print(f"wide GF {M}x{N} w={w}: rel L2 {e:.2e}, max {emax:.2e}")
+    assert e < 2e-6 and emax < 2e-5
+
+
+@pytest.mark.parametrize("M,N,w", [(96, 128, 19), (64, 90, 33), (45, 75, 45), (20, 4500, 19)])
+def test_wide_clipped_guided_filter_parity(M, N, w):
+    I, p = filter_inputs(M, N, M * 13 + N + w)
+    eps = float(np.float32(650.25))
+    out = gfd.guided_filter(to_gpu(I), to_gpu(p), w, eps, clip=True).cpu().numpy()
+    ref = bd.guided_filter_clipped(I.astype(np.float64), p.astype(np.float64), w, eps)
+    e = rel_l2(out, ref)
+    emax = float(np.max(np.abs(out - ref)) / np.max(np.abs(ref)))
+    print(f"wide clipped GF {M}x{N} w={w}: rel L2 {e:.2e}, max {emax:.2e}")
+    assert e < 2e-6 and emax < 2e-5
+
+
+def test_wide_guided_filter_special_cases():
+    c = np.full((40, 50), 93.5, np.float32)
+    for clip in (False, True):
+        out = gfd.guided_filter(to_gpu(c), to_gpu(c), 25, 650.25, clip=clip).cpu().numpy()
+        assert np.max(np.abs(out - c)) < 1e-4  # flat image: the constant
+    I, p = filter_inputs(64, 64, 3)
+    out = gfd.guided_filter(to_gpu(p), to_gpu(p), 21, 1e-6).cpu().numpy()
+    assert rel_l2(out, p) < 1e-5  # identical guide, eps -> 0 returns the input
+    # w = 17 (strip kernel) and w = 19 (separable passes) on either side of the switch, against
+    # the same oracle: both within the bar, and different from each other
+    a = gfd.guided_filter(to_gpu(I), to_gpu(p), 17, 650.25).cpu().numpy()
+    b = gfd.guided_filter(to_gpu(I), to_gpu(p), 19, 650.25).cpu().numpy()
+    assert rel_l2(a, oracle.guided_filter(I.astype(np.float64), p.astype(np.float64), 17, 650.25)) < 2e-6
+    assert rel_l2(b, oracle.guided_filter(I.astype(np.float64), p.astype(np.float64), 19, 650.25)) < 2e-6
+
+
+@pytest.mark.parametrize("M,N,w", [(70, 96, 19), (64, 64, 33), (33, 1000, 25)])
+def test_wide_guided_filter_color_parity(M, N, w):
+    rng = np.random.default_rng(M + N + w)
+    base = synth.piecewise_image(M, N, rng, n_shapes=8)
+    I3 = np.stack([0.9 * base + 12.0 * rng.standard_normal((M, N)) + 10.0 * c for c in range(3)]).astype(np.float32)
+    p = (base + 15.0 * rng.standard_normal((M, N))).astype(np.float32)
+    eps = float(np.float32(7.5e-4 * 255.0 ** 2))
+    out = gfd.guided_filter_color(to_gpu(I3), to_gpu(p), w, eps).cpu().numpy()
+    ref = oracle.guided_filter_color(I3.astype(np.float64), p.astype(np.float64), w, eps)
+    e = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
+    emax = float(np.max(np.abs(out - ref)) / (np.max(ref) - np.min(ref)))
+    print(f"wide colour GF {M}x{N} w={w}: rel L2 {e:.2e}, max {emax:.2e}")
+    assert e < 1e-5 and emax < 1e-4
+
+
+class Case:
+    def __init__(self, M, N, w, seed, psf):
+        rng = np.random.default_rng(seed)
+        self.u_orig = synth.piecewise_image(M, N, rng)
+        self.h = psf
+        b = synth.blur_periodic(self.u_orig, psf)
+        self.sigma2 = float(synth.sigma2_for_bsnr(b, 30.0))
+        self.y = (b + math.sqrt(self.sigma2) * rng.standard_normal((M, N))).astype(np.float32)
+        self.w = w
+        self.eps = 650.25
+
+
+@pytest.mark.parametrize("M,N,w", [(192, 256, 33), (128, 96, 19), (100, 75, 75)])
+def test_wide_iteration_parity(M, N, w):
+    c = Case(M, N, w, M + N + w, synth.psf_gaussian(1.6, 9))
+    r = run_trajectory(c, 6, one_step_at=(0, 2, 4))
+    report(f"wide {M}x{N} w={w}", r)
+    assert_parity(r)
+
+
+@pytest.mark.parametrize("clip,pad", [(True, False), (False, True), (True, True)])
+def test_wide_boundary_iteration_matches_oracle(clip, pad):
+    M, N = (96, 120)
+    h = synth.psf_gaussian(1.6, 7)
+    u, y, s2 = synth.nonperiodic_case(M, N, h, 35.0, seed=M + N + 21)
+    eps = float(np.float32(48.77))
+    w, iters = 21, 5
+    us, lams = [], []
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h), s2, w, eps, clip=clip, pad=pad) as g:
+        for _ in range(iters):
+            uk, lam = g.iterate(1)
+            us.append(uk.cpu().numpy())
+            lams.append(float(lam.cpu()[0]))
+    ref, rinfo = bd.deconvolve_boundary(y.astype(np.float64), h.astype(np.float32).astype(np.float64), s2, w, eps,
+                                        iters, clip=clip, pad=pad, keep_iterates=True)
+    errs = [rel_l2(us[k], rinfo["iterates"][k][:M, :N]) for k in range(iters)]
+    lam_err = float(np.max(np.abs(np.array(lams) / rinfo["lam"] - 1.0)))
+    print(f"wide clip={clip} pad={pad}: max iterate rel L2 {max(errs):.1e}, lambda {lam_err:.1e}")
+    assert max(errs) < 1e-5 and lam_err < 1e-4
+
+
+def test_wide_batch_equals_single_contexts():
+    cases = []
+    for b, (M, N, w, clip) in enumerate([(64, 64, 5, False), (96, 80, 21, False), (64, 64, 19, True),
+                                         (120, 90, 33, False), (72, 72, 3, True)]):
+        h = synth.psf_gaussian(1.4, 7)
+        _, y, s2 = synth.nonperiodic_case(M, N, h, 30.0, seed=60 + b)
+        cases.append(dict(y=to_gpu(y), h=to_gpu(h), sigma2=s2, w=w, eps=650.25, clip=clip, pad=False))
+    with gfd.GFDeconvBatch(cases) as gb:
+        outs, lams = gb.iterate(4)
+        outs = [o.cpu().numpy() for o in outs]
+        lams = lams.cpu().numpy()
+    for b, c in enumerate(cases):
+        with gfd.GFDeconv(c["y"], c["h"], c["sigma2"], c["w"], c["eps"], clip=c["clip"]) as g:
+            u, lam = g.iterate(4)
+        assert np.array_equal(outs[b], u.cpu().numpy()), b
+        assert np.array_equal(lams[b], lam.cpu().numpy()), b
+
+
+@pytest.mark.parametrize("clip", [False, True])
+def test_wide_adjoint_matches_oracle(clip):
+    M, N, w, iters = 80, 96, 21, 5
+    h = synth.psf_gaussian(1.6, 9)
+    if clip:
+        u, y, s2 = synth.nonperiodic_case(M, N, h, 30.0, seed=23)
+    else:
+        c = Case(M, N, w, 23, h)
+        u, y, s2 = c.u_orig, c.y, c.sigma2
+    eps = float(np.float32(650.25))
+    scales = np.linspace(0.9, 1.1, iters).astype(np.float32)
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h), s2, w, eps, clip=clip) as g:
+        g.set_scales(scales)
+        uk, _ = g.iterate(iters)
+        gu = 2.0 * (uk - to_gpu(u)) / uk.numel()
+        ge, gs = g.backward(gu, 2)
+    ge, gs = float(ge.cpu()[0]), gs.cpu().numpy()[0].astype(np.float64)
+    y64, h64, s64 = y.astype(np.float64), h.astype(np.float32).astype(np.float64), scales.astype(np.float64)
+    if clip:
+        ref, _ = bd.deconvolve_boundary(y64, h64, s2, w, eps, iters, clip=True, scales=s64)
+        re, rs = bd.deconvolve_boundary_adjoint(y64, h64, s2, w, eps, iters, adj.mse_loss_grad(ref, u)[1], clip=True,
+                                                scales=s64)
+    else:
+        ref, _ = oracle.deconvolve(y64, h64, s2, w, eps, iters, scales=s64)
+        re, rs, _ = adj.deconvolve_adjoint(y64, h64, s2, w, eps, iters, adj.mse_loss_grad(ref, u)[1], scales=s64)
+    e_eps = abs(ge - re) / abs(re)
+    e_s = float(np.max(np.abs(gs - rs)) / np.max(np.abs(rs)))
+    print(f"wide adjoint clip={clip}: g_eps {ge:.6e} vs {re:.6e} ({e_eps:.1e}), g_s max rel {e_s:.1e}")
+    assert e_eps < 1e-4 and e_s < 1e-4
+
+
+def test_wide_static_entry_point_equals_context():
+    c = Case(96, 128, 25, 5, synth.psf_gaussian(1.6, 9))
+    iters = 3
+    with gfd.GFDeconv(to_gpu(c.y), to_gpu(c.h), c.sigma2, c.w, c.eps) as g:
+        u_ctx, lam_ctx = g.iterate(iters)
+    u_st, lam_st = gfd.deconvolve_static(to_gpu(c.y), to_gpu(c.h), c.sigma2, c.w, c.eps, iters)
+    assert np.array_equal(u_st.cpu().numpy(), u_ctx.cpu().numpy())
+    assert np.array_equal(lam_st.cpu().numpy(), lam_ctx.cpu().numpy())
