@@ -94,10 +94,20 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   // the register allocator shuffle the rings).  Loads run one round ahead: a round first
   // consumes the rows loaded during the previous round, then issues the next loads, and only
   // then does its LDS work.
-  auto fetch = [&](int it, float &I, float &p) {
-    const uint32_t g = (uint32_t)wrap(yrow(min(it, nrows - 1)), M) * (uint32_t)N + (uint32_t)gx;
+  // Rows are fetched in stream order; the wrapped image row of the next fetch is carried from
+  // one fetch to the next (a step of one row and a compare, no division per row), and stream
+  // rows past the end repeat the last row.
+  int f_it = 0, f_row = wrap(ybase, M);
+  auto fetch_next = [&](float &I, float &p) {
+    const uint32_t g = (uint32_t)f_row * (uint32_t)N + (uint32_t)gx;
     I = E(uI, g);
     p = E(uP, g);
+    if (f_it < nrows - 1) {
+      ++f_it;
+      f_row += dir;
+      if (f_row == M) f_row = 0;
+      if (f_row < 0) f_row = M - 1;
+    }
   };
   constexpr int RS = (W + RB - 1) / RB * RB;
   float sI = 0.0f, sP = 0.0f, sII = 0.0f, sIP = 0.0f, sA = 0.0f, sB = 0.0f;
@@ -106,7 +116,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
   for (int k = 0; k < RS; ++k) rI[k] = rP[k] = rA[k] = rB[k] = 0.0f;
   float nI[RB], nP[RB];
 #pragma unroll
-  for (int q = 0; q < RB; ++q) fetch(q, nI[q], nP[q]);
+  for (int q = 0; q < RB; ++q) fetch_next(nI[q], nP[q]);  // stream rows 0 .. RB - 1
   for (int base0 = 0; base0 < nrows; base0 += RS) {
 #pragma unroll
     for (int r = 0; r < RS / RB; ++r) {
@@ -142,10 +152,13 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
               sIP = __fmaf_rn(rI[k], rP[k], sIP);
             }
           } else {
-            slide(sI, I, Io);
-            slide(sP, p, po);
-            slide(sII, I * I, Io * Io);
-            slide(sIP, I * p, Io * po);
+            // I^2 - Io^2 = (I - Io)(I + Io) and I p - Io po = (I - Io) p + Io (p - po): the
+            // differences of the first two sums feed the other two (eight operations, not twelve)
+            const float dI = __fsub_rn(I, Io), dP = __fsub_rn(p, po);
+            sI = __fadd_rn(sI, dI);
+            sP = __fadd_rn(sP, dP);
+            sII = __fmaf_rn(dI, __fadd_rn(I, Io), sII);
+            sIP = __fmaf_rn(dI, p, __fmaf_rn(Io, dP, sIP));
           }
           vb[0] = active ? sI : 0.0f;
           vb[VP] = active ? sP : 0.0f;
@@ -156,7 +169,7 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
         }
       }
 #pragma unroll
-      for (int q = 0; q < RB; ++q) fetch(base + RB + q, nI[q], nP[q]);
+      for (int q = 0; q < RB; ++q) fetch_next(nI[q], nP[q]);  // stream rows base + RB + q
       __syncthreads();
       if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
       // ---- stage 1, horizontal: RB rows x 4 quantities

@@ -897,10 +897,12 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
   if (single) {
     const Item w0 = W1[0];
     const Img &d = D[w0.img];
+    // thread 0 loads the state before the reduction, so that the load's latency overlaps it
+    LamState st;
+    if (threadIdx.x == 0) st = stv[w0.img];
     float hi[2 + 2 * NC1], lo[2 + 2 * NC1];
     reduce_partials<2 + 2 * NC1, 16>(G(d.part), d.npart, d.L.col_blocks(), hi, lo, scratch);
     if (threadIdx.x == 0) {
-      LamState st = stv[w0.img];
       st.done = 0;
       st.flags = 0;
       float cand[NC1];
@@ -1372,8 +1374,11 @@ FftPlan make_plan(int L, int radix) {
   return p;
 }
 
+// Chunks of an evaluation round: about 16384 bins each (a 512-thread block streams 128 KiB of q
+// and |H|^2), at most 512.  Every chunk is one work-queue entry with its own atomics, waits and
+// fences, so smaller chunks would spend a batch's rounds on entry overheads.
 int lam_sweep_chunks(size_t nbins) {
-  size_t want = (nbins / 4 + 255) / 256;
+  size_t want = (nbins + 16383) / 16384;
   if (want < 1) want = 1;
   if (want > 512) want = 512;
   return (int)want;
