@@ -52,6 +52,12 @@ struct Tuning {
 };
 constexpr int kTuningKnobs = 5;
 
+// LDS pitch (complex slots) of one sequence of the register-resident row passes: the
+// transform's padded exchange area plus 8 slots, so that the same position of two sequences
+// falls in opposite halves of the LDS banks (the forward pass's split reads both rows of a
+// pair, one from each of two sequences, in one access).
+__host__ __device__ inline int reg_row_pitch(int N) { return N + N / 16 + 8; }
+
 Layout make_layout(int M, int N, const Tuning &tune = Tuning{});
 size_t reg_seq_lds(int N);
 bool reg_seqs_ok(int N, int seqs);

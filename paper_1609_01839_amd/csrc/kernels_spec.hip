@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int M = lay.M, N = lay.N, R = lay.Rf, T = d.rn.T;
-  const int LP = N + (N >> 4);
+  const int LP = reg_row_pitch(N);
   const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
   const bool active = seq < (R >> 1);
   const int r0 = wi.blk * R;
@@ -771,7 +771,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int M = lay.M, N = lay.N, Wh = lay.Wh, T = d.rn.T;
-  const int LP = N + (N >> 4);
+  const int LP = reg_row_pitch(N);
   const int seq = threadIdx.x / T, t = threadIdx.x - seq * T;
   const bool active = seq < lay.Ri;
   const int row = wi.blk * lay.Ri + seq;
@@ -784,7 +784,10 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
     // The staging memory is the transform's exchange area, free until the transform.
     const int Ri = lay.Ri, C = lay.C, logC = lay.logC;
     const int per = Ri << logC, lper = __ffs(per) - 1;  // words per tile (a power of two)
-    const int total = lay.NT * per, SP = lay.RP + 4;    // SP: staged row pitch in words
+    // SP: staged row pitch in words, with SP = 8 / Ri (mod 8) so that the eight words one LDS
+    // cycle writes (8 / Ri consecutive words of each of the Ri rows) cover the banks once
+    const int want = Ri <= 8 ? (8 / Ri) & 7 : 0;
+    const int total = lay.NT * per, SP = lay.RP + ((want - lay.RP) & 7);
     float4 *stage = reinterpret_cast<float4 *>(smem_raw);
     const GFD_AS1 float4 *sip = reinterpret_cast<const GFD_AS1 float4 *>(G(d.SIP));
     const int r0 = wi.blk * Ri;
@@ -1329,7 +1332,7 @@ Layout make_layout(int M, int N, const Tuning &tune) {
   return L;
 }
 
-size_t reg_seq_lds(int N) { return (size_t)(N + N / 16) * sizeof(cf); }
+size_t reg_seq_lds(int N) { return (size_t)reg_row_pitch(N) * sizeof(cf); }
 
 // A block of `seqs` register-resident sequences of length N fits: at most 1024 threads and
 // 160 KiB of LDS, power-of-two count.
@@ -1435,7 +1438,7 @@ void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
       for (int i : imgs) {
         const Img &d = set.imgs[i];
         threads = std::max(threads, (d.L.Rf / 2) * d.rn.T);
-        lds = std::max(lds, (size_t)(d.L.Rf / 2) * (d.L.N + d.L.N / 16) * sizeof(cf));
+        lds = std::max(lds, (size_t)(d.L.Rf / 2) * reg_seq_lds(d.L.N));
       }
       // the compile-time transform's twiddle tables follow
       const int tw_off = (int)(lds / sizeof(cf));
@@ -1544,8 +1547,8 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         const Img &d = set.imgs[i];
         threads = std::max(threads, d.L.Ri * d.rn.T);
         // the transform's exchange area, which first holds the staged 16-byte words of the rows
-        lds = std::max(lds, (size_t)d.L.Ri * (d.L.N + d.L.N / 16) * sizeof(cf));
-        lds = std::max(lds, (size_t)d.L.Ri * (d.L.RP + 4) * 16);
+        lds = std::max(lds, (size_t)d.L.Ri * reg_seq_lds(d.L.N));
+        lds = std::max(lds, (size_t)d.L.Ri * (d.L.RP + 8) * 16);
       }
       // the compile-time transform's twiddle tables follow
       const int tw_off = (int)(lds / sizeof(cf));
