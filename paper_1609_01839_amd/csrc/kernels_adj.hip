@@ -192,16 +192,22 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
 #pragma unroll
       for (int x = 0; x < NR; ++x) ring[k][x] = 0.0f;
     float nr[RB][NR], ne[RB][NE];
-    auto fetch = [&](int it, float (&rn)[NR], float (&en)[NE]) {
-      const int itc = min(it, nrows - 1);
-      Op::load(d, (size_t)wrap(ybase + itc, M) * N + gx, rn);
+    // Rows are fetched in stream order: the wrapped image row of the next fetch is carried from
+    // one fetch to the next (no division per row); stream rows past the end repeat the last.
+    int f_it = 0, f_row = wrap(ybase, M);
+    auto fetch_next = [&](float (&rn)[NR], float (&en)[NE]) {
+      Op::load(d, (size_t)f_row * N + gx, rn);
       // epilogue row: image row ybase + it - R, clamped into the strip's output rows
-      const int ye = min(max(ybase + itc - R, y0), min(y0 + TY, M) - 1);
+      const int ye = min(max(ybase + f_it - R, y0), min(y0 + TY, M) - 1);
       const int xe = min(x0 - R + j, N - 1);
       Op::eload(d, (size_t)ye * N + max(xe, 0), en);
+      if (f_it < nrows - 1) {
+        ++f_it;
+        if (++f_row == M) f_row = 0;
+      }
     };
 #pragma unroll
-    for (int q = 0; q < RB; ++q) fetch(q, nr[q], ne[q]);
+    for (int q = 0; q < RB; ++q) fetch_next(nr[q], ne[q]);
     for (int base0 = 0; base0 < nrows; base0 += RB * Wn) {
 #pragma unroll
       for (int rr = 0; rr < Wn; ++rr) {
@@ -241,7 +247,7 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
           }
         }
 #pragma unroll
-        for (int q = 0; q < RB; ++q) fetch(base + RB + q, nr[q], ne[q]);
+        for (int q = 0; q < RB; ++q) fetch_next(nr[q], ne[q]);  // stream rows base + RB + q
         __syncthreads();
         if (base + RB - 1 < Wn - 1) continue;  // no complete window in this round (uniform)
         for (int t = j; t < RB * NF * (kGfThreads / kGfRun); t += kGfThreads) hsum_task<R>(vbuf, hbuf, t);

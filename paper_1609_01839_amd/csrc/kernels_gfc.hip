@@ -141,12 +141,19 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
   const bool active = j < used;
   const int gx = wrap(x0 - 2 * R + j, N);
   const int nrows = TY + 4 * R, ybase = y0 - 2 * R;  // stream row it is image row ybase + it
-  auto fetch = [&](int it, float (&x)[4]) {
-    const size_t g = (size_t)wrap(ybase + min(it, nrows - 1), M) * N + gx;
+  // Rows are fetched in stream order: the wrapped image row of the next fetch is carried from
+  // one fetch to the next (no division per row); stream rows past the end repeat the last.
+  int f_it = 0, f_row = wrap(ybase, M);
+  auto fetch_next = [&](float (&x)[4]) {
+    const size_t g = (size_t)f_row * N + gx;
     x[0] = I3[g];
     x[1] = I3[plane + g];
     x[2] = I3[2 * plane + g];
     x[3] = up[g];
+    if (f_it < nrows - 1) {
+      ++f_it;
+      if (++f_row == M) f_row = 0;
+    }
   };
   Kahan s1[kC1], s2[kC2];
 #pragma unroll
@@ -166,7 +173,7 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
   }
   float nx[RB][4];
 #pragma unroll
-  for (int q = 0; q < RB; ++q) fetch(q, nx[q]);
+  for (int q = 0; q < RB; ++q) fetch_next(nx[q]);  // stream rows 0 .. RB - 1
   for (int base0 = 0; base0 < nrows; base0 += RB * W) {
 #pragma unroll
     for (int r = 0; r < W; ++r) {
@@ -200,7 +207,7 @@ __device__ __forceinline__ void gfc_strip(const GFD_AS1 float *__restrict__ I3, 
         }
       }
 #pragma unroll
-      for (int q = 0; q < RB; ++q) fetch(base + RB + q, nx[q]);
+      for (int q = 0; q < RB; ++q) fetch_next(nx[q]);  // stream rows base + RB + q
       __syncthreads();
       if (base + RB - 1 < W - 1) continue;  // no complete window in this round (uniform)
       // ---- stage 1, horizontal
