@@ -82,12 +82,11 @@ struct Bwd {
   std::vector<float *> uR, gu;
   std::vector<std::vector<float *>> ck;  // per image, checkpoint slots
   // per image and segment position: what the adjoint of that iteration reads from its forward
-  // pass (u_I, u_p, U_E and the filter's centring constants), kept while the segment is replayed
-  struct Slot {
-    float *uI = nullptr, *uP = nullptr, *means = nullptr;
-    cf *S1 = nullptr;
-  };
-  std::vector<std::vector<Slot>> seg;
+  // pass (u_I, u_p, U_E and the filter's centring constants); the replay descriptors are pointed
+  // at a position before the replay writes it and before the adjoint reads it
+  std::vector<std::vector<BwdSlot>> seg;
+  BwdSlot *seg_dev = nullptr;  // seg laid out image-major, nseg positions per image
+  int nseg = 0;
   std::vector<void *> allocs;
   int hist_cap = 0;
 };
@@ -853,7 +852,7 @@ static hipError_t bwd_slots(gfd_ctx *c, int nck, int seg) {
       b->ck[i].push_back(p);
     }
     while ((int)b->seg[i].size() < seg && e == hipSuccess) {
-      Bwd::Slot sl;
+      BwdSlot sl = {};
       e = balloc(b, &sl.uI, P);
       if (e == hipSuccess) e = balloc(b, &sl.uP, P);
       if (e == hipSuccess) e = balloc(b, &sl.S1, nb);
@@ -861,31 +860,21 @@ static hipError_t bwd_slots(gfd_ctx *c, int nck, int seg) {
       b->seg[i].push_back(sl);
     }
   }
-  return e;
-}
-
-// Save (dir = +1) or restore (dir = -1) what the adjoint of one iteration needs from its forward
-// pass: u_I, u_p, U_E and the centring constants of every image.
-static hipError_t seg_copy(gfd_ctx *c, int pos, int dir, hipStream_t s) {
-  Bwd *b = c->bwd;
-  for (int i = 0; i < c->count; ++i) {
-    const Img &d = b->bwd.imgs[i];
-    const Bwd::Slot &sl = b->seg[i][pos];
-    const size_t P = (size_t)c->meta[i].M * c->meta[i].N, nb = d.L.bins();
-    float *means = (float *)((char *)(b->st + i) + offsetof(LamState, meanI));
-    static_assert(offsetof(LamState, meanP) == offsetof(LamState, meanI) + sizeof(float), "adjacent means");
-    struct {
-      void *dev, *slot;
-      size_t bytes;
-    } parts[] = {{d.uI, sl.uI, P * sizeof(float)}, {d.uP, sl.uP, P * sizeof(float)},
-                 {d.S1, sl.S1, nb * sizeof(cf)}, {means, sl.means, 2 * sizeof(float)}};
-    for (auto &x : parts) {
-      hipError_t e = dir > 0 ? hipMemcpyAsync(x.slot, x.dev, x.bytes, hipMemcpyDeviceToDevice, s)
-                             : hipMemcpyAsync(x.dev, x.slot, x.bytes, hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return e;
-    }
+  if (e != hipSuccess || c->count == 0 || (int)b->seg[0].size() == b->nseg) return e;
+  // the positions grew: a new device copy of the table (the previous one may still be read by
+  // the last call's kernels, so it is kept until the buffers are freed)
+  const int n = (int)b->seg[0].size();
+  std::vector<BwdSlot> flat;
+  for (int i = 0; i < c->count; ++i)
+    for (int j = 0; j < n; ++j) flat.push_back(b->seg[i][j]);
+  BwdSlot *dev = nullptr;
+  e = balloc(b, &dev, flat.size());
+  if (e == hipSuccess) e = hipMemcpy(dev, flat.data(), flat.size() * sizeof(BwdSlot), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    b->seg_dev = dev;
+    b->nseg = n;
   }
-  return hipSuccess;
+  return e;
 }
 
 static hipError_t copy_images(gfd_ctx *c, const std::vector<float *> &dst, const std::vector<float *> &src,
@@ -1489,13 +1478,14 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
   for (int j = nck - 1; j >= 0; --j) {
     const int a = j * c, z = std::min(a + c, K);
     if (j != nck - 1) HIPCHK(copy_images(ctx, b->uR, slot(b->ck, j), s));
-    for (int k = a; k < z; ++k) {  // forward over the segment, keeping what the adjoint reads
+    for (int k = a; k < z; ++k) {  // forward over the segment, into the positions the adjoint reads
+      HIPCHK(launch_bwd_bind(b->bwd, b->seg_dev, b->nseg, k - a, 0, s));
       HIPCHK(replay(b, k0 + k, false, s));
-      HIPCHK(seg_copy(ctx, k - a, +1, s));
+      HIPCHK(launch_bwd_bind(b->bwd, b->seg_dev, b->nseg, k - a, +1, s));
       if (k + 1 < z) HIPCHK(b->gf.enqueue(s));
     }
     for (int k = z - 1; k >= a; --k) {
-      HIPCHK(seg_copy(ctx, k - a, -1, s));
+      HIPCHK(launch_bwd_bind(b->bwd, b->seg_dev, b->nseg, k - a, -1, s));
       HIPCHK(adjoint_step(b, k0 + k, s));
     }
   }

@@ -242,6 +242,13 @@ void plan_adj_col(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_adj_inf(Plan &p, ImgSet &set, const std::vector<int> &sel);
 ItemRange plan_one_per_image(ImgSet &set, const std::vector<int> &sel);
 hipError_t launch_lam_replay(ImgSet &set, ItemRange one, int k, hipStream_t s);
+// Buffers of one segment position of the reverse mode, per image: what the adjoint of an
+// iteration reads from its replayed forward pass (u_I, u_p, U_E and the two centring constants).
+struct BwdSlot {
+  float *uI, *uP, *means;
+  cf *S1;
+};
+hipError_t launch_bwd_bind(ImgSet &set, const BwdSlot *slots, int nslot, int j, int dir, hipStream_t s);
 hipError_t launch_adj_fin(ImgSet &set, ItemRange one, int k, hipStream_t s);
 hipError_t launch_adj_out(ImgSet &set, ItemRange one, int K, int k0, float *geps, float *gs, hipStream_t s);
 

@@ -337,6 +337,27 @@ __global__ void k_lam_replay(const Img *__restrict__ D, const Item *__restrict__
   }
 }
 
+// Points the replay descriptors of every image at segment position j, so that the replay of an
+// iteration writes u_I, u_p and U_E there and its adjoint reads them there (no copies).  dir > 0
+// also saves the centring constants the replay has just computed, dir < 0 restores them.
+__global__ void k_bwd_bind(Img *__restrict__ D, int count, const BwdSlot *__restrict__ slots, int nslot, int j,
+                           int dir) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const BwdSlot sl = slots[(size_t)i * nslot + j];
+  Img &d = D[i];
+  d.uI = sl.uI;
+  d.uP = sl.uP;
+  d.S1 = sl.S1;
+  if (dir > 0) {
+    sl.means[0] = d.st->meanI;
+    sl.means[1] = d.st->meanP;
+  } else if (dir < 0) {
+    d.st->meanI = sl.means[0];
+    d.st->meanP = sl.means[1];
+  }
+}
+
 // ============================================================================ spectral adjoint
 // Per bin of one tile: G = (lambda / dp) G_p + (lambda D2 / dI) G_I and the partial sums of
 // g_lambda and of P f'(lambda*).
@@ -635,6 +656,12 @@ ItemRange plan_one_per_image(ImgSet &set, const std::vector<int> &sel) {
 
 hipError_t launch_lam_replay(ImgSet &set, ItemRange one, int k, hipStream_t s) {
   return make_launch(&set, k_lam_replay, one, 64, 0, k)(s);
+}
+
+hipError_t launch_bwd_bind(ImgSet &set, const BwdSlot *slots, int nslot, int j, int dir, hipStream_t s) {
+  const int n = (int)set.imgs.size();
+  hipLaunchKernelGGL(k_bwd_bind, dim3((n + 63) / 64), dim3(64), 0, s, set.dev, n, slots, nslot, j, dir);
+  return hipGetLastError();
 }
 
 hipError_t launch_adj_fin(ImgSet &set, ItemRange one, int k, hipStream_t s) {

@@ -334,15 +334,16 @@ static hipError_t launch_gf_wide(const WideArgs &a, hipStream_t s) {
   return e == hipSuccess ? wide_stage<WideGf2>(a, s) : e;
 }
 
-// The filter of image d of a descriptor set as separable passes, centred like the strip kernel
-// (the image means kept in its lambda state).
-static WideArgs gf_wide_args(const Img &d) {
+// The filter of image i of a descriptor set as separable passes, centred like the strip kernel
+// (the image means kept in its lambda state); guide, input and output come from the set's
+// device table when the kernels run.
+static WideArgs gf_wide_args(const ImgSet &set, int i) {
+  const Img &d = set.imgs[i];
   WideArgs a = {};
-  a.src[0] = d.uI;
-  a.src[1] = d.uP;
+  a.d = set.dev + i;
+  a.table = 1;
   a.dst[0] = d.wa;
   a.dst[1] = d.wb;
-  a.out = d.uE;
   a.V = d.wV;
   a.cen[0] = state_field(d.st, offsetof(LamState, meanI));
   a.cen[1] = state_field(d.st, offsetof(LamState, meanP));
@@ -422,7 +423,7 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
     if (kv.first / 2 > kGfRmax) {  // one stream-ordered sequence of separable passes per image
       ImgSet *setp = &set;
       for (int i : kv.second)
-        p.steps.push_back([setp, i](hipStream_t s) { return launch_gf_wide(gf_wide_args(setp->imgs[i]), s); });
+        p.steps.push_back([setp, i](hipStream_t s) { return launch_gf_wide(gf_wide_args(*setp, i), s); });
       continue;
     }
     const size_t off = set.items_host.size();

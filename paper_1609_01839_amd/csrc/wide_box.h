@@ -42,7 +42,19 @@ struct WideArgs {
   double *pre;           // rows wider than kWideMaxN: M rows of N + 1 prefix sums (else unused)
   int M, N, r, clip;
   float eps;
+  int table;             // 1: the forward filter's guide, input and output are d's u_I, u_p, u_E,
+                         // read from the descriptor when the kernel runs
 };
+
+// The pointers a descriptor supplies, taken when the kernel runs (the reverse mode points its
+// replay descriptors at other buffers between launches).
+__device__ __forceinline__ void wide_resolve(WideArgs &a) {
+  if (a.table) {
+    a.src[0] = a.d->uI;
+    a.src[1] = a.d->uP;
+    a.out = a.d->uE;
+  }
+}
 
 // Pixels of the window of half-width r centred at c inside [0, n).
 __device__ __forceinline__ int wide_count(int c, int r, int n) { return min(c + r, n - 1) - max(c - r, 0) + 1; }
@@ -57,6 +69,7 @@ __device__ __forceinline__ void wide_centres(const WideArgs &a, float (&cen)[4])
 template <class Op, bool CLIP>
 __global__ void __launch_bounds__(kWideVThreads) k_wide_v(WideArgs a, int TY) {
   constexpr int NF = Op::NF, NR = Op::NR;
+  wide_resolve(a);
   const int M = a.M, N = a.N, r = a.r;
   const int x = blockIdx.x * kWideVThreads + threadIdx.x;
   if (x >= N) return;  // no barriers in this kernel
@@ -108,6 +121,7 @@ __global__ void __launch_bounds__(kWideVThreads) k_wide_v(WideArgs a, int TY) {
 template <class Op, bool CLIP, bool BIG>
 __global__ void __launch_bounds__(kWideThreads) k_wide_h(WideArgs a) {
   constexpr int NF = Op::NF, NR = Op::NR, NE = Op::NE;
+  wide_resolve(a);
   constexpr int NW = kWideThreads / 64;
   __shared__ float row_lds[BIG ? 1 : kWideMaxN];
   __shared__ double pre_lds[BIG ? 1 : kWideMaxN + 1];
