@@ -41,6 +41,7 @@ namespace gfd {
 // kT marks the fields whose sums are transposed means (gradients flowing back through B).
 struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
   static constexpr int NF = 4, NR = 2, NE = 1;
+  static constexpr int kWideRows = 2;  // rows per round of barriers at r >= 7
   static constexpr unsigned kT = 0u;
   static constexpr bool kEps = false;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
@@ -70,6 +71,7 @@ struct BoxStage1 {  // window means of I, p, I^2, I p  ->  a, mu, pbar, v + eps
 
 struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c, g_u B(a)
   static constexpr int NF = 3, NR = 3, NE = 3;
+  static constexpr int kWideRows = 4;
   static constexpr unsigned kT = 6u;  // B^T(g_u I), B^T(g_u)
   static constexpr bool kEps = true;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
@@ -111,6 +113,7 @@ struct BoxStage2 {  // window means of a, g_u I, g_u  ->  g_mu, g_pbar, g_v, g_c
 
 struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
   static constexpr int NF = 4, NR = 4, NE = 3;
+  static constexpr int kWideRows = 2;
   static constexpr unsigned kT = 15u;  // all four are transposed means
   static constexpr bool kEps = false;
   __device__ static void load(const Img &d, size_t g, float (&r)[NR]) {
@@ -145,7 +148,10 @@ struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
 template <int R, class Op, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict__ D, const Item *__restrict__ W,
                                                           int nitems) {
-  constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = kGfRB;
+  // rows per round of barriers: Op::kWideRows for the widest radii (measured at w = 17, 4096^2:
+  // four rows for the three-field stage, two for the four-field stages, which then lose more
+  // occupancy to registers than they save in barriers), two otherwise
+  constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = R >= 7 ? Op::kWideRows : kGfRB;
   constexpr int VP = hs_pitch<R>();
   __shared__ __align__(16) float vbuf[RB * NF * VP];
   __shared__ __align__(16) float hbuf[RB * NF * kHsOut];
@@ -185,7 +191,6 @@ __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict_
     // loaded during the previous round before it issues the next loads.  The epilogue operands
     // of the output row (stream row it - r) come from the ring and from NE loads, also issued a
     // round ahead.
-    static_assert(RB == 2, "rounds of two rows");
     float ring[Wn][NR];
 #pragma unroll
     for (int k = 0; k < Wn; ++k)
