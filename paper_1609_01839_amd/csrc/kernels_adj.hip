@@ -148,10 +148,11 @@ struct BoxStage3 {  // window means of g_mu, g_c, g_v, g_pbar  ->  g_I, g_p
 template <int R, class Op, bool CLIP>
 __global__ void __launch_bounds__(kGfThreads) k_box_stage(const Img *__restrict__ D, const Item *__restrict__ W,
                                                           int nitems) {
-  // rows per round of barriers: Op::kWideRows for the widest radii (measured at w = 17, 4096^2:
-  // four rows for the three-field stage, two for the four-field stages, which then lose more
-  // occupancy to registers than they save in barriers), two otherwise
-  constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = R >= 7 ? Op::kWideRows : kGfRB;
+  // rows per round of barriers: Op::kWideRows for the widest periodic radii (measured at w = 17,
+  // 4096^2: four rows for the three-field stage, two for the four-field stages, which then lose
+  // more occupancy to registers than they save in barriers; the clipped variant's longer body is
+  // not unrolled over four rows), two otherwise
+  constexpr int NF = Op::NF, Wn = 2 * R + 1, RB = R >= 7 && !CLIP ? Op::kWideRows : kGfRB;
   constexpr int VP = hs_pitch<R>();
   __shared__ __align__(16) float vbuf[RB * NF * VP];
   __shared__ __align__(16) float hbuf[RB * NF * kHsOut];
@@ -473,6 +474,8 @@ __device__ __forceinline__ cf adj_total(const Img &d, size_t i, int k, float kap
   return cf{__fmaf_rn(c, HR.re, g0.re), __fmaf_rn(c, HR.im, g0.im)};
 }
 
+// LF = 4096: the compile-time transform (every thread holds a sequence: M = 4096, C = 2).
+template <int LF>
 __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                     int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -493,7 +496,8 @@ __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, c
     cf v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = valid ? adj_total(d, off + (t + T * m) * C + c, k, kappa, ls) : cf{0.0f, 0.0f};
-    reg_fft<+1>(v, t, active, d.rm, lds + c, C, G(d.twM));
+    if constexpr (LF != 0) reg_fft_c<LF, +1, 2, false>(v, t, active, lds + c, TwGlobal{G(d.twM)});
+    else reg_fft<+1>(v, t, active, d.rm, lds + c, C, G(d.twM));
     if (active) {
 #pragma unroll
       for (int m = 0; m < 16; ++m)
@@ -619,11 +623,12 @@ static int adj_pick_E(size_t elems, int &threads) {
 }
 
 void plan_adj_col(Plan &p, ImgSet &set, const std::vector<int> &sel) {
-  std::map<std::pair<int, int>, std::vector<int>> groups;  // (threads, E); E = 0: register-resident
+  std::map<std::pair<int, int>, std::vector<int>> groups;  // (threads, E); threads = 0: register-resident
+                                                           // (E = 4096: the compile-time transform)
   for (int i : sel) {
     const Img &d = set.imgs[i];
     if (reg_plan_ok(d.L.M)) {
-      groups[{0, 0}].push_back(i);
+      groups[{0, d.L.M == 4096 && d.L.C == 2 ? 4096 : 0}].push_back(i);
     } else {
       int th;
       const int E = adj_pick_E((size_t)d.L.M * d.L.C, th);
@@ -635,13 +640,13 @@ void plan_adj_col(Plan &p, ImgSet &set, const std::vector<int> &sel) {
     int threads = kv.first.first;
     const int E = kv.first.second;
     size_t lds = 0;
-    if (E == 0) {
+    if (kv.first.first == 0) {
       for (int i : kv.second) {
         const Img &d = set.imgs[i];
         threads = std::max(threads, d.L.C * d.rm.T);
         lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
       }
-      p.steps.push_back(make_launch(&set, k_adjcol_r16, r, threads, lds));
+      p.steps.push_back(make_launch(&set, E == 4096 ? k_adjcol_r16<4096> : k_adjcol_r16<0>, r, threads, lds));
     } else {
       for (int i : kv.second) lds = std::max(lds, (size_t)set.imgs[i].L.M * set.imgs[i].L.C * sizeof(cf));
       p.steps.push_back(make_launch(&set, E == 4 ? k_adjcol_g<4> : E == 8 ? k_adjcol_g<8> : k_adjcol_g<16>, r,
