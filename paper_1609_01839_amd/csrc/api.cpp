@@ -1262,11 +1262,14 @@ gfd_status deconv_get_status(gfd_ctx *ctx, unsigned *flags_host) {
   if (!flags_host) return fail(GFD_ERR_ARG, "flags_host is NULL");
   // read on the context's own stream, after the context's last enqueued work
   std::vector<unsigned> f(ctx->count, 0u);
-  HIPCHK(hipStreamWaitEvent(ctx->cap_stream, ctx->done_ev, 0));
-  for (int i = 0; i < ctx->count; ++i)
-    HIPCHK(hipMemcpyAsync(&f[i], (char *)(ctx->st + i) + offsetof(LamState, flags_all), sizeof(unsigned),
-                          hipMemcpyDeviceToHost, ctx->cap_stream));
-  HIPCHK(hipStreamSynchronize(ctx->cap_stream));
+  hipError_t e = hipStreamWaitEvent(ctx->cap_stream, ctx->done_ev, 0);
+  for (int i = 0; i < ctx->count && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(&f[i], (char *)(ctx->st + i) + offsetof(LamState, flags_all), sizeof(unsigned),
+                       hipMemcpyDeviceToHost, ctx->cap_stream);
+  // the copies land in f: wait for them whatever happened above, before f goes out of scope
+  const hipError_t es = hipStreamSynchronize(ctx->cap_stream);
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return fail(GFD_ERR_HIP, "deconv_get_status failed: %s", hipGetErrorString(e));
   unsigned all = 0;
   for (unsigned v : f) all |= v;
   *flags_host = all;
@@ -1290,13 +1293,22 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
   gfd_ctx *c = ctx;
   // the trial iterations advance the estimate and the search state: keep copies
   HIPCHK(hipStreamSynchronize(s));
-  std::vector<LamState> st_save(c->count);
-  HIPCHK(hipMemcpy(st_save.data(), c->st, c->count * sizeof(LamState), hipMemcpyDeviceToHost));
+  // the search states are kept on the device, so every trial restores them with a device copy
+  LamState *st_save = nullptr;
+  HIPCHK(hipMalloc((void **)&st_save, c->count * sizeof(LamState)));
   std::vector<float *> ue_save(c->count, nullptr);
   auto release = [&]() {
     for (float *p : ue_save)
       if (p) (void)hipFree(p);
+    (void)hipFree(st_save);
   };
+  {
+    const hipError_t e = hipMemcpy(st_save, c->st, c->count * sizeof(LamState), hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) {
+      release();
+      return fail(GFD_ERR_HIP, "autotune set-up failed: %s", hipGetErrorString(e));
+    }
+  }
   for (int i = 0; i < c->count; ++i) {
     const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
     hipError_t e = hipMalloc((void **)&ue_save[i], P * sizeof(float));
@@ -1324,7 +1336,7 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
       e = hipMemcpyAsync(c->main.imgs[i].uE, ue_save[i], P * sizeof(float), hipMemcpyDeviceToDevice, s);
     }
     if (e == hipSuccess)
-      e = hipMemcpyAsync(c->st, st_save.data(), c->count * sizeof(LamState), hipMemcpyHostToDevice, s);
+      e = hipMemcpyAsync(c->st, st_save, c->count * sizeof(LamState), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipGraphLaunch(c->gexec, s);  // warm-up replay
     if (e == hipSuccess) e = hipEventRecord(e0, s);
     for (int k = 0; k < n && e == hipSuccess; ++k) e = hipGraphLaunch(c->gexec, s);
@@ -1386,7 +1398,7 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
     const size_t P = (size_t)c->meta[i].M * c->meta[i].N;
     e = hipMemcpy(c->main.imgs[i].uE, ue_save[i], P * sizeof(float), hipMemcpyDeviceToDevice);
   }
-  if (e == hipSuccess) e = hipMemcpy(c->st, st_save.data(), c->count * sizeof(LamState), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->st, st_save, c->count * sizeof(LamState), hipMemcpyDeviceToDevice);
   release();
   if (!ok) return rc;
   if (e != hipSuccess) return fail(GFD_ERR_HIP, "autotune restore failed: %s", hipGetErrorString(e));
