@@ -98,10 +98,12 @@ __device__ __forceinline__ void df_add(float &hi, float &lo, float bh, float bl)
 // by NV threads in parallel (thread v sums value v over the waves in wave order), then thread 0
 // collects them: every thread below NV ends with its value in hi[v], lo[v] and thread 0 with all.
 // `scratch` must hold 2 * NV * max(blockDim.x / 64, 1) floats.  Fixed order: deterministic.
+// A block of fewer than 64 threads (a power of two) keeps its butterfly within its lanes.
 template <int NV>
 __device__ __forceinline__ void block_reduce_df(float (&hi)[NV], float (&lo)[NV], float *scratch) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
+    if (off >= (int)blockDim.x) continue;  // uniform
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       float oh = __shfl_down(hi[v], off, 64);
@@ -109,7 +111,7 @@ __device__ __forceinline__ void block_reduce_df(float (&hi)[NV], float (&lo)[NV]
       df_add(hi[v], lo[v], oh, ol);
     }
   }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   if (lane == 0) {
 #pragma unroll

@@ -23,15 +23,18 @@ namespace gfd {
 // ============================================================================ reductions
 
 // Plain FP32 butterfly over the wave, then compensated across the waves in wave order by NV
-// threads in parallel: thread v (< NV) ends with value v in (h, l).
+// threads in parallel: thread v (< NV) ends with value v in (h, l).  A block of fewer than 64
+// threads (a power of two: the register-resident column pass at 256 rows and two columns has
+// 32) is one partial wave, and its butterfly stays within its lanes.
 template <int NV>
 __device__ __forceinline__ void block_sum_plain_then_df(float (&acc)[NV], float &h, float &l, float *scratch) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
+    if (off >= (int)blockDim.x) continue;  // uniform
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
   }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
   if (lane == 0) {
 #pragma unroll
@@ -64,7 +67,7 @@ __device__ __forceinline__ void store_partial(GFD_AS1 float *part, int npart, in
 template <int NV, int U = 32>
 __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict__ part, int npart, int nparts, float (&hi)[NV],
                                 float (&lo)[NV], float *scratch) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = max((int)(blockDim.x >> 6), 1);
   for (int v = wid; v < NV; v += nw) {
     const GFD_AS1 float *ph = part + (size_t)(2 * v) * npart, *pl = part + (size_t)(2 * v + 1) * npart;
     float h = 0.0f, l = 0.0f;
