@@ -26,7 +26,7 @@ import math
 
 import numpy as np
 
-from .gfd import discrepancy_lambda, dft2, guided_filter, rho_eq12, setup, spectral_solve
+from .gfd import discrepancy_lambda, dft2, guided_filter, residual_energy, rho_eq12, setup, spectral_solve
 from .adjoint import guided_filter_adjoint, solve_adjoint
 
 
@@ -189,16 +189,17 @@ def deconvolve_boundary(y, h, sigma2, w, eps, iters, rho=None, clip=False, pad=F
     iterates, uncropped)."""
     S, (M, N) = boundary_setup(y, h, sigma2, rho, pad)
     uE = start_estimate(S, (M, N), u0, pad)
-    lams, flags_all, iterates = [], [], []
+    lams, flags_all, iterates, Es = [], [], [], []
     for k in range(iters):
         s = 1.0 if scales is None else float(scales[k])
+        Es.append(residual_energy(math.inf, S, dft2(uE)))  # the E_inf of the branch test (reported only)
         uE, _, _, lam, _, flags = boundary_step(S, uE, w, eps, clip, s)
         lams.append(lam)
         flags_all.append(flags)
         if keep_iterates:
             iterates.append(uE)
     info = dict(lam=np.array(lams), flags=np.array(flags_all), rho=S.rho, T=S.T, shape=(S.M, S.N),
-                iterates=iterates)
+                iterates=iterates, E_inf=np.array(Es))
     return uE[:M, :N].copy(), info
 
 
