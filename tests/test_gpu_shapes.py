@@ -86,3 +86,57 @@ def test_shapes_match_oracle(M, N, kh, kw, w, mode):
                 assert tie  # either branch is right at an FP32 tie; the iterates agree (above)
             elif not math.isinf(lo) and lo <= 1e10:
                 assert abs(lg - lo) / lo < 1e-4
+
+
+def make_problem(M, N, kh, kw, seed):
+    rng = np.random.default_rng(seed)
+    h = rng.uniform(0.2, 1.0, (kh, kw))
+    h /= h.sum()
+    u = synth.piecewise_image(M, N, rng, n_shapes=4)
+    b = synth.blur_periodic(u, h)
+    s2 = float(synth.sigma2_for_bsnr(b, 30.0)) + 1e-3
+    y = (b + math.sqrt(s2) * rng.standard_normal((M, N))).astype(np.float32)
+    return u, y, h.astype(np.float32), s2
+
+
+def test_shapes_batch_equals_single_contexts():
+    """A batch of the spread's shapes (every transform kind and both filter kinds in one set of
+    launches) gives every image bit for bit what its own context gives."""
+    cases = []
+    for k, (M, N, kh, kw, w, mode) in enumerate(CASES[:12]):
+        _, y, h, s2 = make_problem(M, N, kh, kw, 50 + k)
+        cases.append(dict(y=to_gpu(y), h=to_gpu(h), sigma2=s2, w=w, eps=650.25, clip=mode in (1, 3),
+                          pad=mode in (2, 3)))
+    with gfd.GFDeconvBatch(cases) as gb:
+        outs, lams = gb.iterate(3)
+        outs = [o.cpu().numpy() for o in outs]
+        lams = lams.cpu().numpy()
+    for b, c in enumerate(cases):
+        with gfd.GFDeconv(c["y"], c["h"], c["sigma2"], c["w"], c["eps"], clip=c["clip"], pad=c["pad"]) as g:
+            u, lam = g.iterate(3)
+        assert np.array_equal(outs[b], u.cpu().numpy()), b
+        assert np.array_equal(lams[b], lam.cpu().numpy()), b
+
+
+@pytest.mark.parametrize("M,N,kh,kw,w", [(256, 3, 5, 1, 3), (5, 6, 5, 5, 3), (96, 45, 3, 9, 29), (45, 24, 1, 7, 11),
+                                         (270, 120, 13, 5, 15)])
+def test_shapes_adjoint_matches_oracle(M, N, kh, kw, w):
+    """The reverse mode at odd shapes (32-thread column blocks, sides of 5 and 6, a separable
+    filter window) against the oracle's adjoint, within 1e-4."""
+    from oracle import adjoint as adj
+    u, y, h, s2 = make_problem(M, N, kh, kw, M + N)
+    eps, iters = float(np.float32(650.25)), 3
+    scales = np.linspace(0.9, 1.1, iters).astype(np.float32)
+    with gfd.GFDeconv(to_gpu(y), to_gpu(h), s2, w, eps) as g:
+        g.set_scales(scales)
+        uk, _ = g.iterate(iters)
+        gu = 2.0 * (uk - to_gpu(u)) / uk.numel()
+        ge, gs = g.backward(gu, 2)
+    ge, gs = float(ge.cpu()[0]), gs.cpu().numpy()[0].astype(np.float64)
+    y64, h64, s64 = y.astype(np.float64), h.astype(np.float64), scales.astype(np.float64)
+    ref, _ = oracle.deconvolve(y64, h64, s2, w, eps, iters, scales=s64)
+    re, rs, _ = adj.deconvolve_adjoint(y64, h64, s2, w, eps, iters, adj.mse_loss_grad(ref, u)[1], scales=s64)
+    e_eps = abs(ge - re) / abs(re)
+    e_s = float(np.max(np.abs(gs - rs)) / np.max(np.abs(rs))) if np.max(np.abs(rs)) > 0 else 0.0
+    print(f"{M}x{N} w={w}: g_eps {ge:.6e} vs {re:.6e} ({e_eps:.1e}), g_s max rel {e_s:.1e}")
+    assert e_eps < 1e-4 and e_s < 1e-4
