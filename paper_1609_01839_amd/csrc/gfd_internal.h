@@ -13,18 +13,19 @@
 namespace gfd {
 
 // Geometry of one image and of its half spectrum.
-// The half spectrum (columns k = 0 .. N/2 of the row transforms) is stored tile-major between
-// the forward row and column passes: tile t holds columns [t*C, t*C + C) for all M rows as a
-// contiguous M x C block, element (m, c) of tile t at ((t * M) + m) * C + c.  Columns at or
-// beyond Wh are zero padding.  The column pass of the inverse writes row-major instead
-// (element (m, k) at m * RP + k, RP = NT * C), so that every pass reads contiguous data and
-// the transposition happens on the write side.
+// The half spectrum (columns k = 0 .. N/2 of the row transforms) is stored tile-major: tile t
+// holds columns [t*C, t*C + C) for all M rows as a contiguous M x C block, element (m, c) of
+// tile t at t * TS + m * C + c.  Columns at or beyond Wh are zero padding.  Tiles start TS >=
+// M * C bins apart: where M * C has a large power-of-two factor, a few bins of padding after
+// every tile keep the row passes' accesses (a few rows of every tile) from falling on the same
+// HBM channels.  Padding bins are never written by the passes and hold zeros.
 struct Layout {
   int M, N;
   int Wh;         // N / 2 + 1
   int C, logC;    // tile width (power of two)
   int NT;         // number of tiles = ceil(Wh / C)
-  int RP;         // pitch of the row-major half spectra, NT * C
+  int RP;         // columns of all tiles, NT * C
+  int TS;         // bins between the starts of consecutive tiles (>= M * C)
   int R;          // image rows per block in the LDS-resident row passes (even)
   int Rf, Ri;     // rows per block of the register-resident row passes (forward even, inverse)
   FastDiv Ndiv;   // division by N
@@ -35,10 +36,10 @@ struct Layout {
   // NT - 1 blocks (the forward pass without the residual launches NT)
   int fold;
   __host__ __device__ int col_blocks() const { return NT - fold; }
-  __host__ __device__ size_t bins() const { return (size_t)NT * M * C; }
+  __host__ __device__ size_t bins() const { return (size_t)NT * TS; }
   // tile-major position of bin (m, k): tile k / C, row m, column k % C
   __host__ __device__ size_t tpos(int m, int k) const {
-    return ((size_t)(k >> logC) * M + m) * C + (k & (C - 1));
+    return (size_t)(k >> logC) * TS + (size_t)m * C + (k & (C - 1));
   }
 };
 

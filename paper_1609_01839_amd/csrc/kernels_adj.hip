@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(256) k_adj_spec(const Img *__restrict__ D, con
     if (d.ad->skip) continue;
     const Layout &lay = d.L;
     const int C = lay.C, n = lay.M * C;
-    const size_t off = (size_t)wi.blk * n;
+    const size_t off = (size_t)wi.blk * lay.TS;
     const float lam = d.st->lam, ls = d.st->lam_star, invP = d.st->invP;
     float gl = 0.0f, fp = 0.0f;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, c
     const int C = lay.C, T = d.rm.T;
     const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
     const bool active = t < T;
-    const size_t off = (size_t)wi.blk * lay.M * C;
+    const size_t off = (size_t)wi.blk * lay.TS;
     const int k = wi.blk * C + c;
     const bool valid = active && k < lay.Wh;
     const float kappa = d.ad->kappa, ls = d.st->lam_star;
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(1024) k_adjcol_g(const Img *__restrict__ D, co
     if (d.ad->skip) continue;
     const Layout &lay = d.L;
     const int C = lay.C, n = lay.M * C;
-    const size_t off = (size_t)wi.blk * n;
+    const size_t off = (size_t)wi.blk * lay.TS;
     const float kappa = d.ad->kappa, ls = d.st->lam_star;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
       const int k = wi.blk * C + (e & (C - 1));

@@ -199,7 +199,7 @@ __device__ __forceinline__ void row_fwd_body(XP x, const Layout &lay, const FftP
       if ((rho & 1) == 0) X = cpx<T>{(Zk.re + Zn.re) * (T)0.5, (Zk.im - Zn.im) * (T)0.5};
       else X = cpx<T>{(Zk.im + Zn.im) * (T)0.5, (Zn.re - Zk.re) * (T)0.5};
     }
-    S[((size_t)t * M + m) * C + c] = X;
+    S[(size_t)t * lay.TS + (size_t)m * C + c] = X;
   }
 }
 
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd_g(const Img *__restrict__ D, c
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int n = lay.M * lay.C, C = lay.C;
-  const size_t off = (size_t)wi.blk * n;
+  const size_t off = (size_t)wi.blk * lay.TS;
   GFD_AS1 cf *tile = G(d.S1) + off;
   // F(h) and F(y) of this thread's bins do not depend on the transform: their loads are issued
   // first so that they travel while the column transform runs
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(1024) k_col_inv_g(const Img *__restrict__ D, c
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
   const int n = lay.M * lay.C, C = lay.C;
-  const size_t off = (size_t)wi.blk * n;
+  const size_t off = (size_t)wi.blk * lay.TS;
   const SolveParams sp = solve_params(d.st);
   const int kbase = wi.blk * C;
   // straight-line elements (case split outside the loop, clamped indices, padding columns
@@ -499,8 +499,8 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
       const int tstep = blockDim.x >> lp, tt0 = threadIdx.x >> lp;
       const cf *z = lds + (rho >> 1) * LP;
       const bool odd = (rho & 1) != 0;
-      const uint32_t ostep = (uint32_t)tstep * (uint32_t)M * (uint32_t)C;
-      uint32_t o = ((uint32_t)tt0 * (uint32_t)M + (uint32_t)m) * (uint32_t)C + (uint32_t)c;
+      const uint32_t ostep = (uint32_t)tstep * (uint32_t)lay.TS;
+      uint32_t o = (uint32_t)tt0 * (uint32_t)lay.TS + (uint32_t)m * (uint32_t)C + (uint32_t)c;
       for (int tt = tt0; tt < lay.NT; tt += tstep, o += ostep) {
         const int k = tt * C + c;
         cf X = {0.0f, 0.0f};
@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
         if ((rho & 1) == 0) X = cf{(Zk.re + Zn.re) * 0.5f, (Zk.im - Zn.im) * 0.5f};
         else X = cf{(Zk.im + Zn.im) * 0.5f, (Zn.re - Zk.re) * 0.5f};
       }
-      G(d.S1)[((size_t)tt * M + m) * C + c] = X;
+      G(d.S1)[(size_t)tt * lay.TS + (size_t)m * C + c] = X;
     }
   }
   GFD_ITEM_END
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   // element m of this thread's column sits at byte to + sm * m of the tile: sm * m is the same
   // for the whole block, to a 32-bit per-thread offset (inactive threads read a valid element
   // and never use it)
-  const size_t tb = (size_t)wi.blk * lay.M * C, tbN = (size_t)(lay.NT - 1) * lay.M * C;
+  const size_t tb = (size_t)wi.blk * lay.TS, tbN = (size_t)(lay.NT - 1) * lay.TS;
   const uint32_t sm = (uint32_t)(T * C * sizeof(cf));
   const uint32_t to = (uint32_t)(((active ? t : 0) * C + c) * sizeof(cf));
   const auto rS = gbytes(d.S1 + tb);
@@ -658,7 +658,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   const int C = lay.C, T = d.rm.T;
   const int c = threadIdx.x & (C - 1), t = threadIdx.x >> lay.logC;
   const bool active = t < T;
-  const size_t off = (size_t)wi.blk * lay.M * C;
+  const size_t off = (size_t)wi.blk * lay.TS;
   const SolveParams sp = solve_params(d.st);
   const int k = wi.blk * C + c;
   const bool valid = active && k < lay.Wh;
@@ -666,7 +666,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   const bool fold = lay.fold && wi.blk == 0;  // uniform over the block
   const bool fc = fold && c == 0 && active;
   if (fc) {  // column N/2, parked in LDS (free until the transforms)
-    const size_t offN = (size_t)(lay.NT - 1) * lay.M * C;
+    const size_t offN = (size_t)(lay.NT - 1) * lay.TS;
     const float dN2 = G(d.dN)[lay.N / 2];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
@@ -748,7 +748,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     // same elements to + sm * m of the tile, and a wave's 16-byte stores are contiguous
     const auto rO = gbytes(reinterpret_cast<float4 *>(d.SIP) + off);
     if (fc) {  // real parts: column 0 (this tile); imaginary parts: column N/2 (column 0 of the last tile)
-      const auto rN = gbytes(reinterpret_cast<float4 *>(d.SIP) + (size_t)(lay.NT - 1) * lay.M * C);
+      const auto rN = gbytes(reinterpret_cast<float4 *>(d.SIP) + (size_t)(lay.NT - 1) * lay.TS);
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         st_f4(vi[m].re, 0.0f, vp[m].re, 0.0f, rO, 16 * to, 16 * sm * m);
@@ -804,7 +804,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
         const int e = min(e0 + u * (int)blockDim.x, total - 1);
         const int tile = e >> lper, rem = e & (per - 1);
         const uint32_t m = (uint32_t)min(r0 + (rem >> logC), M - 1);
-        w[u] = E(sip, ((uint32_t)tile * (uint32_t)M + m) * (uint32_t)C + (uint32_t)(rem & (C - 1)));
+        w[u] = E(sip, (uint32_t)tile * (uint32_t)lay.TS + m * (uint32_t)C + (uint32_t)(rem & (C - 1)));
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
@@ -1110,7 +1110,7 @@ __global__ void __launch_bounds__(1024) k_col_fwd_plain(cpx<T> *__restrict__ S, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T> *buf = reinterpret_cast<cpx<T> *>(smem_raw);
   const int n = lay.M * lay.C;
-  GFD_AS1 cpx<T> *tile = G(S) + (size_t)blockIdx.x * n;
+  GFD_AS1 cpx<T> *tile = G(S) + (size_t)blockIdx.x * lay.TS;
   col_fwd_load_fft<T, E>(tile, lay, pm, G(tw), buf);
   for (int e = threadIdx.x; e < n; e += blockDim.x) tile[e] = buf[e];
 }
@@ -1132,11 +1132,13 @@ __global__ void k_embed_psf(const float *__restrict__ h, int kh, int kw, int M, 
 // Constants of the solves in FP32, derived in FP64: H, Y (residual), conj(H) Y and |H|^2
 // (solves and search).  |H|^2 uses the same FP32 expression as the residual pass.
 __global__ void k_init_consts(const cd *__restrict__ Hd, const cd *__restrict__ Yd, size_t n, int Wh, int M, int C,
-                              cf *__restrict__ H, cf *__restrict__ Y, cf *__restrict__ HY, float *__restrict__ H2) {
+                              int TS, cf *__restrict__ H, cf *__restrict__ Y, cf *__restrict__ HY,
+                              float *__restrict__ H2) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const size_t t = i / ((size_t)M * C);
-    const int c = (int)(i & (size_t)(C - 1));
-    const bool valid = (int)(t * C) + c < Wh;
+    const size_t t = i / (size_t)TS, rem = i - t * TS;
+    const int c = (int)(rem & (size_t)(C - 1));
+    // bins past a tile's M x C block (padding) and columns at or beyond Wh hold zeros
+    const bool valid = rem < (size_t)M * C && (int)(t * C) + c < Wh;
     const cd h = valid ? Hd[i] : cd{0.0, 0.0}, y = valid ? Yd[i] : cd{0.0, 0.0};
     const cf hf = {(float)h.re, (float)h.im};
     H[i] = hf;
@@ -1291,6 +1293,10 @@ static FastDiv mkdiv(int d) {
   return f;
 }
 
+// Padding bins after every tile of a power-of-two-rich size (a multiple of 16, so that float4
+// runs over the bins stay aligned in every tile).
+constexpr int kTilePad = 64;
+
 Layout make_layout(int M, int N, const Tuning &tune) {
   Layout L;
   L.M = M;
@@ -1304,6 +1310,9 @@ Layout make_layout(int M, int N, const Tuning &tune) {
   L.logC = ilog2(C);
   L.NT = (L.Wh + C - 1) / C;
   L.RP = L.NT * C;
+  // tile stride: M * C bins, plus kTilePad where M * C is a multiple of 1024 (a tile of 16 KiB
+  // or more of FP32 bins at a power-of-two-rich stride)
+  L.TS = M * C + ((M * C) % 1024 == 0 ? kTilePad : 0);
   // (the folded passes also use 2 M complex values of the block's LDS, which C >= 2 provides)
   L.fold = (reg_plan_ok(M) && C >= 2 && N % 2 == 0 && (N / 2) % C == 0 && L.NT >= 2) ? 1 : 0;
   // rows per block in the LDS-resident row passes: aim at >= 128-byte segments, LDS <= 64 KiB
@@ -1639,7 +1648,7 @@ hipError_t launch_init_consts(const cd *Hd, const cd *Yd, const Layout &L, cf *H
   size_t n = L.bins();
   int blocks = (int)((n + 255) / 256);
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_init_consts, dim3(blocks), dim3(256), 0, st, Hd, Yd, n, L.Wh, L.M, L.C, H, Y, HY, H2);
+  hipLaunchKernelGGL(k_init_consts, dim3(blocks), dim3(256), 0, st, Hd, Yd, n, L.Wh, L.M, L.C, L.TS, H, Y, HY, H2);
   return hipGetLastError();
 }
 
