@@ -369,7 +369,7 @@ static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, I
   const size_t P = (size_t)M * N, nb = L.bins();
   d.nchunk = lam_sweep_chunks(nb);
   d.npart = std::max(L.NT, d.nchunk);
-  cf *twM, *twN, *H, *Y, *HY, *S1, *SIP;
+  cf *twM, *twN, *twB = nullptr, *H, *Y, *HY, *S1, *SIP;
   float *H2, *dM, *dN, *uE, *uI, *uP, *q, *part;
   cd *twMd, *twNd;
   hipError_t e = hipSuccess;
@@ -377,6 +377,7 @@ static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, I
   if (e == hipSuccess) e = dalloc(c, &(ptr), (n))
   ALLOC(twM, M);
   ALLOC(twN, N);
+  if (M == 4096) ALLOC(twB, (size_t)kRegTwRows * 16);
   ALLOC(H, nb);
   ALLOC(Y, nb);
   ALLOC(HY, nb);
@@ -406,6 +407,7 @@ static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, I
   d.wa = wa;
   d.wb = wb;
   d.twM = twM;
+  d.twB = twB;
   d.twN = twN;
   d.H = H;
   d.Y = Y;
@@ -449,6 +451,18 @@ static hipError_t init_image(gfd_ctx *c, int i, const gfd_image &src, const Img 
   if (e == hipSuccess) e = hipMemcpy(twNd, tn.data(), tn.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy((void *)d.twM, tmf.data(), tmf.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy((void *)d.twN, tnf.data(), tnf.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (d.twB) {  // the same FP32 values by butterfly (TwTable): row r, entry i = w_M^(i k TS)
+    std::vector<float> tb((size_t)kRegTwRows * 16 * 2);
+    for (int r = 0; r < kRegTwRows; ++r) {
+      const int k = r < 16 ? r : r - 16, ts = r < 16 ? M / 256 : 1;
+      for (int i = 0; i < 16; ++i) {
+        const size_t e = (size_t)i * k * ts % (size_t)M;
+        tb[2 * ((size_t)r * 16 + i)] = tmf[2 * e];
+        tb[2 * ((size_t)r * 16 + i) + 1] = tmf[2 * e + 1];
+      }
+    }
+    if (e == hipSuccess) e = hipMemcpy((void *)d.twB, tb.data(), tb.size() * sizeof(float), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = launch_embed_psf(src.h, src.kh, src.kw, M, N, hp, s);
   if (e == hipSuccess) e = launch_row_fwd_d(hp, L, d.pn, twNd, Hd, s);
   if (e == hipSuccess) e = launch_col_fwd_d(Hd, L, d.pm, twMd, s);

@@ -65,6 +65,9 @@ __device__ __forceinline__ void dftR(cf *x) {
 struct TwGlobal {
   const GFD_AS1 cf *__restrict__ tw;
   __device__ __forceinline__ cf operator()(int e) const { return E(tw, (uint32_t)e); }
+  // twiddle i of butterfly k of the compile-time pass with span S and stride TS: w_L^(i k TS)
+  template <int S, int TS>
+  __device__ __forceinline__ cf at(int k, int i) const { return (*this)(i * (k * TS)); }
 };
 
 // Twiddle source from two 64-entry tables in LDS: w_L^e = w_L^(64 (e / 64)) w_L^(e % 64) for
@@ -73,6 +76,24 @@ struct TwGlobal {
 struct TwSplit {
   const cf *lo, *hi;
   __device__ __forceinline__ cf operator()(int e) const { return cmul(hi[e >> 6], lo[e & 63]); }
+  template <int S, int TS>
+  __device__ __forceinline__ cf at(int k, int i) const { return (*this)(i * (k * TS)); }
+};
+
+// Twiddle source from a butterfly-major table in global memory for the compile-time transforms:
+// row r holds the 16 twiddles w_L^(i k TS), i = 0..15, of butterfly k of one pass (rows 0..15:
+// the pass of span 16, k < 16, TS = L / 256; rows 16..271: the pass of span 256, k < 256,
+// TS = 1).  A butterfly's twiddles are then one 128-byte row reached from one address with
+// immediate offsets, where w_L^(i k TS) taken from the plain table needs an index per i.
+constexpr int kRegTwRows = 16 + 256;
+struct TwTable {
+  const GFD_AS1 cf *__restrict__ tab;
+  template <int S, int TS>
+  __device__ __forceinline__ cf at(int k, int i) const {
+    static_assert(S == 16 || S == 256, "passes after the first");
+    constexpr int row0 = S == 16 ? 0 : 16;
+    return E(tab, (uint32_t)((row0 + k) * 16 + i));
+  }
 };
 
 // One pass.  `lds` addresses the sequence's region: slot(p) = lds[lds_pad(p) * ls].
@@ -155,13 +176,14 @@ __device__ __forceinline__ void reg_pass_c(cf (&v)[16], int t, bool active_, cf 
     cf x[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) x[i] = v[b + i * NBF];
-    if (S > 1 && active) {
-      const int e1 = k * TSTRIDE;
+    if constexpr (S > 1) {
+      if (active) {
 #pragma unroll
-      for (int i = 1; i < R; ++i) {
-        cf w = tw(i * e1);
-        if (DIR > 0) w.im = -w.im;
-        x[i] = cmul(x[i], w);
+        for (int i = 1; i < R; ++i) {
+          cf w = tw.template at<S, TSTRIDE>(k, i);
+          if (DIR > 0) w.im = -w.im;
+          x[i] = cmul(x[i], w);
+        }
       }
     }
     dftR<R, DIR>(x);

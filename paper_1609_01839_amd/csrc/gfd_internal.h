@@ -75,6 +75,8 @@ struct Img {
   FftPlan pm, pn;        // LDS-resident plans (any 2^a 3^b 5^c length)
   RegPlan rm, rn;        // register-resident plans (power-of-two lengths)
   const cf *twM, *twN;   // twiddles exp(-2 pi i n / L)
+  const cf *twB;         // M = 4096: the column transforms' twiddles by butterfly (kRegTwRows
+                         // rows of 16, TwTable), null otherwise
   const cf *H, *Y, *HY;  // F(h), F(y), conj(F(h)) F(y), tile-major
   const float *H2;       // |F(h)|^2, tile-major
   const float *dM, *dN;  // |F(grad)|^2 = dM[m] + dN[k]
@@ -83,7 +85,7 @@ struct Img {
   cf *S1;                // spectra: row transforms, then U_E
   cf *SIP;               // the two solves after the column inverse, tile-major like S1 and
                          // interleaved: bin (m, k) of tile t = k / C, column c = k % C holds
-                         // U_I at SIP[2 e] and U_p at SIP[2 e + 1], e = (t M + m) C + c
+                         // U_I at SIP[2 e] and U_p at SIP[2 e + 1], e = t TS + m C + c
   float *part;           // partial sums, [2 * kLamAcc][npart]
   int npart;             // stride of `part` (>= NT and >= nchunk)
   int nchunk;            // blocks of a lambda evaluation round

@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, c
     cf v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = valid ? adj_total(d, off + (t + T * m) * C + c, k, kappa, ls) : cf{0.0f, 0.0f};
-    if constexpr (LF != 0) reg_fft_c<LF, +1, 2, false>(v, t, active, lds + c, TwGlobal{G(d.twM)});
+    if constexpr (LF != 0) reg_fft_c<LF, +1, 2, false>(v, t, active, lds + c, TwTable{G(d.twB)});
     else reg_fft<+1>(v, t, active, d.rm, lds + c, C, G(d.twM));
     if (active) {
 #pragma unroll

@@ -731,14 +731,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   // both transforms, then one 16-byte store per bin (U_I, U_p): the two columns of the tile give
   // 32 contiguous bytes per row
   if constexpr (LF != 0) {
-    // (twiddles from the global table: the two products per twiddle of the LDS tables cost
-    // this kernel's register budget more spills than the loads' latency)
-    reg_fft_c<LF, +1, 2, false>(vp, t, active, lds + c, TwGlobal{G(d.twM)});
+    // (twiddles from the butterfly-major global table: the two products per twiddle of the LDS
+    // tables, or an index per twiddle into the plain table, cost this kernel's register budget
+    // more than the loads' latency)
+    reg_fft_c<LF, +1, 2, false>(vp, t, active, lds + c, TwTable{G(d.twB)});
     // the second transform loads its twiddles again: an opaque copy of the table pointer keeps
     // the compiler from holding the first transform's twiddles in registers across both
-    const cf *tw2 = d.twM;
+    const cf *tw2 = d.twB;
     asm volatile("" : "+s"(tw2));
-    reg_fft_c<LF, +1, 2, false>(vi, t, active, lds + c, TwGlobal{G(tw2)});
+    reg_fft_c<LF, +1, 2, false>(vi, t, active, lds + c, TwTable{G(tw2)});
   } else {
     reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
     reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
