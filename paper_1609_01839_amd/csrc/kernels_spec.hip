@@ -863,8 +863,8 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
 // block waits on was taken earlier by a block that is running, and those finish without waiting
 // on later entries.  Per chunk: sums of q g_j and q g_j (1 - r_j) over its bins; the image's last
 // block to store a round's sums (the count in the image's state, fenced on both sides) folds the
-// round into the bracket.  A search's state is stored first and published after a fence (round
-// r + 1, or phase = 1 with lambda fixed).  Blocks leave when their entry is past the last round
+// round into the bracket.  An open search's state is stored first and published after a fence
+// (round r + 1); a fixed lambda is published as phase = 1 without one (lam_publish).  Blocks leave when their entry is past the last round
 // or every image's lambda is fixed; the last to leave clears the queue for the next launch.
 // A single image skips the start entry: every block reduces the partials and runs the start
 // itself (the same sums in the same order give the same decision in every block), so no block
@@ -874,15 +874,23 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
 constexpr int kLamSpinLimit = 1 << 20;  // bounded wait (about 50 ms); never reached in practice
 constexpr int kLamOpenLds = 4096;       // open images a block can map (every image of a batch)
 
+// A fixed lambda is read only by later launches (the launch boundary orders those reads); the
+// blocks of this launch only learn that the image is closed (its phase, the closed count) and
+// read nothing else of its state, so that path has no fence.  A fence is a write-back of the
+// L2's dirty lines, which after the residual pass costs microseconds.  An open search's state
+// (the next candidates) is read by the blocks of the next round: it is fenced before the round
+// is published.
 __device__ __forceinline__ void lam_publish(LamState *sp, LamState &st, int fixed, int next_round, LamQueue *lq) {
-  st.phase = 0;
   st.round = next_round - 1;
-  *sp = st;
-  __threadfence();
   if (fixed) {
+    st.phase = 1;  // the plain copy and the flag agree, whichever reaches memory first
+    *sp = st;
     __hip_atomic_store(&sp->phase, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     atomicAdd(&lq->closed, 1);
   } else {
+    st.phase = 0;
+    *sp = st;
+    __threadfence();
     __hip_atomic_store(&sp->round, next_round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -956,8 +964,10 @@ __global__ void __launch_bounds__(512) k_lam_rounds(const Img *__restrict__ D, c
         const int fixed = lam_begin(st, hi[0], lo[0], hi[1], lo[1], NC1, cand, hi + 2, lo + 2, hi + 2 + NC1);
         if (fixed) lam_commit(d, st, advance);
         lam_publish(stv + wi.img, st, fixed, 0, lq);
-        if (!fixed) __hip_atomic_store(&lq->open[atomicAdd(&lq->nopen, 1)], wi.img, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        if (!fixed) {  // the open list entry is read once the starts are counted
+          __hip_atomic_store(&lq->open[atomicAdd(&lq->nopen, 1)], wi.img, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __threadfence();
+        }
         atomicAdd(&lq->begun, 1);
       }
       __syncthreads();
