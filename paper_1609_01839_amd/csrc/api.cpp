@@ -377,7 +377,7 @@ static hipError_t alloc_image(gfd_ctx *c, int i, const gfd_image &src, Img &d, I
   if (e == hipSuccess) e = dalloc(c, &(ptr), (n))
   ALLOC(twM, M);
   ALLOC(twN, N);
-  if (M == 4096) ALLOC(twB, (size_t)kRegTwRows * 16);
+  if (reg_plan_ok(M)) ALLOC(twB, (size_t)kRegTwRows * 16);
   ALLOC(H, nb);
   ALLOC(Y, nb);
   ALLOC(HY, nb);

@@ -225,6 +225,12 @@ __device__ __forceinline__ void reg_fft_c(cf (&v)[16], int t, bool active, cf *l
 
 inline bool reg_plan_ok(int L) { return L >= 256 && L <= 4096 && (L & (L - 1)) == 0; }
 
+// Tile width of the column passes for M = L (a power of two in [256, 4096]): the widest C with
+// M x 2C complex values in 64 KiB, at most 16 (make_layout), which is also the LDS interleave of
+// the compile-time column transforms.  Narrow images can have narrower tiles; they take the
+// run-time transform.
+__host__ __device__ constexpr int col_ls(int L) { return L >= 4096 ? 2 : L == 2048 ? 4 : L == 1024 ? 8 : 16; }
+
 inline RegPlan make_reg_plan(int L) {
   RegPlan p;
   p.L = L;

@@ -75,8 +75,8 @@ struct Img {
   FftPlan pm, pn;        // LDS-resident plans (any 2^a 3^b 5^c length)
   RegPlan rm, rn;        // register-resident plans (power-of-two lengths)
   const cf *twM, *twN;   // twiddles exp(-2 pi i n / L)
-  const cf *twB;         // M = 4096: the column transforms' twiddles by butterfly (kRegTwRows
-                         // rows of 16, TwTable), null otherwise
+  const cf *twB;         // power-of-two M in [256, 4096]: the column transforms' twiddles by
+                         // butterfly (kRegTwRows rows of 16, TwTable), null otherwise
   const cf *H, *Y, *HY;  // F(h), F(y), conj(F(h)) F(y), tile-major
   const float *H2;       // |F(h)|^2, tile-major
   const float *dM, *dN;  // |F(grad)|^2 = dM[m] + dN[k]

@@ -474,7 +474,8 @@ __device__ __forceinline__ cf adj_total(const Img &d, size_t i, int k, float kap
   return cf{__fmaf_rn(c, HR.re, g0.re), __fmaf_rn(c, HR.im, g0.im)};
 }
 
-// LF = 4096: the compile-time transform (every thread holds a sequence: M = 4096, C = 2).
+// LF != 0: the compile-time transform of length M = LF (tiles of col_ls(LF) columns: every
+// thread of the block holds a sequence).
 template <int LF>
 __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, const Item *__restrict__ W,
                                                     int nitems) {
@@ -496,7 +497,7 @@ __global__ void __launch_bounds__(512) k_adjcol_r16(const Img *__restrict__ D, c
     cf v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = valid ? adj_total(d, off + (t + T * m) * C + c, k, kappa, ls) : cf{0.0f, 0.0f};
-    if constexpr (LF != 0) reg_fft_c<LF, +1, 2, false>(v, t, active, lds + c, TwTable{G(d.twB)});
+    if constexpr (LF != 0) reg_fft_c<LF, +1, col_ls(LF), false>(v, t, active, lds + c, TwTable{G(d.twB)});
     else reg_fft<+1>(v, t, active, d.rm, lds + c, C, G(d.twM));
     if (active) {
 #pragma unroll
@@ -624,11 +625,11 @@ static int adj_pick_E(size_t elems, int &threads) {
 
 void plan_adj_col(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   std::map<std::pair<int, int>, std::vector<int>> groups;  // (threads, E); threads = 0: register-resident
-                                                           // (E = 4096: the compile-time transform)
+                                                           // (E = M: the compile-time transform)
   for (int i : sel) {
     const Img &d = set.imgs[i];
     if (reg_plan_ok(d.L.M)) {
-      groups[{0, d.L.M == 4096 && d.L.C == 2 ? 4096 : 0}].push_back(i);
+      groups[{0, d.L.C == col_ls(d.L.M) ? d.L.M : 0}].push_back(i);
     } else {
       int th;
       const int E = adj_pick_E((size_t)d.L.M * d.L.C, th);
@@ -646,7 +647,16 @@ void plan_adj_col(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         threads = std::max(threads, d.L.C * d.rm.T);
         lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
       }
-      p.steps.push_back(make_launch(&set, E == 4096 ? k_adjcol_r16<4096> : k_adjcol_r16<0>, r, threads, lds));
+      auto kern = k_adjcol_r16<0>;
+      switch (E) {
+        case 4096: kern = k_adjcol_r16<4096>; break;
+        case 2048: kern = k_adjcol_r16<2048>; break;
+        case 1024: kern = k_adjcol_r16<1024>; break;
+        case 512: kern = k_adjcol_r16<512>; break;
+        case 256: kern = k_adjcol_r16<256>; break;
+        default: break;
+      }
+      p.steps.push_back(make_launch(&set, kern, r, threads, lds));
     } else {
       for (int i : kv.second) lds = std::max(lds, (size_t)set.imgs[i].L.M * set.imgs[i].L.C * sizeof(cf));
       p.steps.push_back(make_launch(&set, E == 4 ? k_adjcol_g<4> : E == 8 ? k_adjcol_g<8> : k_adjcol_g<16>, r,

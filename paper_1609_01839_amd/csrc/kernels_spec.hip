@@ -439,14 +439,17 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 // and last passes straight from / to global memory.  Threads beyond an image's need (blocks
 // sized for a larger image of the batch) only join the barriers.
 
-// The compile-time row transforms and the forward column pass (length 4096) take their
-// twiddles from two 64-entry tables in LDS (TwSplit), written here from the image's FP32 table at the block's start into tab[0 .. 128),
+// The compile-time row transforms and the forward column pass take their twiddles from two
+// 64-entry tables in LDS (TwSplit), written here from the image's FP32 table at the block's start into tab[0 .. 128),
 // a region no exchange touches; the first pass of a transform needs no twiddles and ends with
 // a barrier, which makes the tables visible before they are read.
+template <int L>
 __device__ __forceinline__ void load_tw_split(cf *tab, const cf *tw) {
-  if (threadIdx.x < 128) {
-    const int j = threadIdx.x & 63;
-    tab[threadIdx.x] = E(G(tw), (uint32_t)(threadIdx.x < 64 ? j : 64 * j));
+  // (blocks of short rows can have fewer than 128 threads; entries 64 j with j >= L / 64 are
+  // never used: they are read at 64 j mod L, inside the table)
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    const int j = i & 63;
+    tab[i] = E(G(tw), (uint32_t)(i < 64 ? j : (64 * j) & (L - 1)));
   }
 }
 
@@ -456,7 +459,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd_r16(const Img *__restrict__ D,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
   if constexpr (LF != 0) {
-    if ((int)blockIdx.x < nitems) load_tw_split(lds + tw_off, D[W[blockIdx.x].img].twN);
+    if ((int)blockIdx.x < nitems) load_tw_split<LF>(lds + tw_off, D[W[blockIdx.x].img].twN);
   }
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
@@ -545,7 +548,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
   cf *lds = reinterpret_cast<cf *>(smem_raw);
   __shared__ float scratch[kLamAcc * 16];
   if constexpr (LF != 0) {
-    if ((int)blockIdx.x < nitems) load_tw_split(lds + tw_off, D[W[blockIdx.x].img].twM);
+    if ((int)blockIdx.x < nitems) load_tw_split<LF>(lds + tw_off, D[W[blockIdx.x].img].twM);
   }
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
@@ -569,7 +572,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m].im = ld_f(rN, to, sm * m);
   }
-  if constexpr (LF != 0) reg_fft_c<LF, -1, 2, false>(v, t, active, lds + c, TwSplit{lds + tw_off, lds + tw_off + 64});
+  if constexpr (LF != 0) reg_fft_c<LF, -1, col_ls(LF), false>(v, t, active, lds + c, TwSplit{lds + tw_off, lds + tw_off + 64});
   else reg_fft<-1>(v, t, active, d.rm, lds + c, C, G(d.twM));
   if (!RESID) {
     if (active) {
@@ -734,12 +737,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 8))
     // (twiddles from the butterfly-major global table: the two products per twiddle of the LDS
     // tables, or an index per twiddle into the plain table, cost this kernel's register budget
     // more than the loads' latency)
-    reg_fft_c<LF, +1, 2, false>(vp, t, active, lds + c, TwTable{G(d.twB)});
+    reg_fft_c<LF, +1, col_ls(LF), false>(vp, t, active, lds + c, TwTable{G(d.twB)});
     // the second transform loads its twiddles again: an opaque copy of the table pointer keeps
     // the compiler from holding the first transform's twiddles in registers across both
     const cf *tw2 = d.twB;
     asm volatile("" : "+s"(tw2));
-    reg_fft_c<LF, +1, 2, false>(vi, t, active, lds + c, TwTable{G(tw2)});
+    reg_fft_c<LF, +1, col_ls(LF), false>(vi, t, active, lds + c, TwTable{G(tw2)});
   } else {
     reg_fft<+1>(vp, t, active, d.rm, lds + c, C, G(d.twM));
     reg_fft<+1>(vi, t, active, d.rm, lds + c, C, G(d.twM));
@@ -770,7 +773,7 @@ __global__ void __launch_bounds__(1024) k_row_inv_r16(const Img *__restrict__ D,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cf *lds = reinterpret_cast<cf *>(smem_raw);
   if constexpr (LF != 0) {
-    if ((int)blockIdx.x < nitems) load_tw_split(lds + tw_off, D[W[blockIdx.x].img].twN);
+    if ((int)blockIdx.x < nitems) load_tw_split<LF>(lds + tw_off, D[W[blockIdx.x].img].twN);
   }
   GFD_ITEM_LOOP
   const Layout &lay = d.L;
@@ -1426,7 +1429,21 @@ using GKey = std::tuple<int, int, int>;  // (register-resident?, threads or comp
 // Length of the compile-time register-resident transform for a pass of length L whose
 // sequences are interleaved LS apart in LDS (1 in the row passes, the tile width C in the
 // column passes), given the interleave the kernel is compiled for; 0: the run-time transform.
-static int fixed_len(int L, int LS, int compiled_LS) { return L == 4096 && LS == compiled_LS ? 4096 : 0; }
+static int fixed_len(int L, int LS, bool col) { return reg_plan_ok(L) && LS == (col ? col_ls(L) : 1) ? L : 0; }
+
+// f(std::integral_constant<int, L>) for a compile-time length L (0: the run-time transform):
+// picks the instantiation of a register-resident pass kernel.
+template <class F>
+static auto by_len(int L, F f) {
+  switch (L) {
+    case 4096: return f(std::integral_constant<int, 4096>{});
+    case 2048: return f(std::integral_constant<int, 2048>{});
+    case 1024: return f(std::integral_constant<int, 1024>{});
+    case 512: return f(std::integral_constant<int, 512>{});
+    case 256: return f(std::integral_constant<int, 256>{});
+    default: return f(std::integral_constant<int, 0>{});
+  }
+}
 // Largest images first within a launch: blocks are dealt in item order, so the longest work
 // starts first and the small images fill the tail.
 void sort_by_size(const ImgSet &set, std::vector<int> &imgs) {
@@ -1452,7 +1469,7 @@ static auto pickE(int E, K4 a, K8 b, K16 c) {
 
 void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.N)) return GKey{1, fixed_len(d.L.N, 1, 1), 0};
+    if (reg_plan_ok(d.L.N)) return GKey{1, fixed_len(d.L.N, 1, false), 0};
     int th; int E = pick_E((size_t)(d.L.R / 2) * d.L.N, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1467,7 +1484,8 @@ void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
       const int tw_off = (int)(lds / sizeof(cf));
       if (std::get<1>(k)) lds += 128 * sizeof(cf);
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Rf - 1) / d.L.Rf; });
-      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_fwd_r16<4096> : k_row_fwd_r16<0>, r, threads, lds, tw_off));
+      const auto kern = by_len(std::get<1>(k), [](auto L) { return k_row_fwd_r16<decltype(L)::value>; });
+      p.steps.push_back(make_launch(&set, kern, r, threads, lds, tw_off));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1480,7 +1498,7 @@ void plan_row_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel) {
 
 void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.M)) return GKey{1, fixed_len(d.L.M, d.L.C, 2), 0};
+    if (reg_plan_ok(d.L.M)) return GKey{1, fixed_len(d.L.M, d.L.C, true), 0};
     int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1498,9 +1516,9 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
       // the compile-time transform's twiddle tables follow
       const int tw_off = (int)(lds / sizeof(cf));
       if (fx) lds += 128 * sizeof(cf);
-      p.steps.push_back(resid ? make_launch(&set, fx ? k_col_fwd_r16<true, 4096> : k_col_fwd_r16<true, 0>, r, threads, lds, tw_off)
-                              : make_launch(&set, fx ? k_col_fwd_r16<false, 4096> : k_col_fwd_r16<false, 0>, r, threads,
-                                            lds, tw_off));
+      const auto kern = resid ? by_len(std::get<1>(k), [](auto L) { return k_col_fwd_r16<true, decltype(L)::value>; })
+                              : by_len(std::get<1>(k), [](auto L) { return k_col_fwd_r16<false, decltype(L)::value>; });
+      p.steps.push_back(make_launch(&set, kern, r, threads, lds, tw_off));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1535,7 +1553,7 @@ void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, 
 
 void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.M)) return GKey{1, fixed_len(d.L.M, d.L.C, 2), 0};
+    if (reg_plan_ok(d.L.M)) return GKey{1, fixed_len(d.L.M, d.L.C, true), 0};
     int th; int E = pick_E((size_t)d.L.M * d.L.C, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1548,7 +1566,8 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
         threads = std::max(threads, d.L.C * d.rm.T);
         lds = std::max(lds, (size_t)d.L.C * (d.L.M + d.L.M / 16) * sizeof(cf));
       }
-      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_col_inv_r16<4096> : k_col_inv_r16<0>, r, threads, lds));
+      const auto kern = by_len(std::get<1>(k), [](auto L) { return k_col_inv_r16<decltype(L)::value>; });
+      p.steps.push_back(make_launch(&set, kern, r, threads, lds));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
@@ -1560,7 +1579,7 @@ void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
 
 void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
   group_by(set, sel, [](const Img &d) {
-    if (reg_plan_ok(d.L.N)) return GKey{1, fixed_len(d.L.N, 1, 1), 0};
+    if (reg_plan_ok(d.L.N)) return GKey{1, fixed_len(d.L.N, 1, false), 0};
     int th; int E = pick_E((size_t)d.L.R * d.L.N, th);
     return GKey{0, th, E};
   }, [&](const GKey &k, const std::vector<int> &imgs) {
@@ -1577,7 +1596,8 @@ void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel) {
       const int tw_off = (int)(lds / sizeof(cf));
       if (std::get<1>(k)) lds += 128 * sizeof(cf);
       ItemRange r = add_items(set, imgs, [](const Img &d) { return (d.L.M + d.L.Ri - 1) / d.L.Ri; });
-      p.steps.push_back(make_launch(&set, std::get<1>(k) ? k_row_inv_r16<4096> : k_row_inv_r16<0>, r, threads, lds, tw_off));
+      const auto kern = by_len(std::get<1>(k), [](auto L) { return k_row_inv_r16<decltype(L)::value>; });
+      p.steps.push_back(make_launch(&set, kern, r, threads, lds, tw_off));
     } else {
       const int threads = std::get<1>(k), E = std::get<2>(k);
       size_t lds = 0;
