@@ -162,6 +162,11 @@ def lam_err(g: float, o: float) -> float:
 
 # ----------------------------------------------------------------------------- GPU legs
 
+# launch shapes of the batch leg: strip rows, forward row pairs, inverse rows, mixed-radix rows,
+# mixed-radix schedule
+BATCH_TUNING = (32, 1, 2, 2, 8)
+
+
 def batch_leg(steps: int, warmup: int, n_images: int = 64, ref=None) -> dict:
     """Mixed-size batch: one context (one launch per pass for all images, graph replay) against
     the one-image-per-launch path (a context per image, kernels launched one by one, images in
@@ -191,8 +196,11 @@ def batch_leg(steps: int, warmup: int, n_images: int = 64, ref=None) -> dict:
 
     parity = None
     with gfd.GFDeconvBatch(probs) as gb:
-        tuning = gb.autotune(4)
-        gb.reset()
+        # fixed launch shapes (the autotuner's usual choice for this batch; the library does not
+        # autotune multi-image contexts)
+        gb.set_tuning(*BATCH_TUNING)
+        tuning = dict(zip(("gf_strip_rows", "row_pairs_fwd", "rows_inv", "rows_lds", "radix"), BATCH_TUNING))
+        tuning["fixed"] = True
         if ref is not None:  # the first iteration of every image against the oracle's
             us, lam = gb.iterate(1)
             lam = lam.cpu().numpy()

@@ -256,7 +256,9 @@ gfd_status deconv_profile(gfd_ctx *ctx, int n_iter, float *stage_ms_host, int n_
  * strip height (its running sums restart at strip edges).  Needs a context with no iterations
  * run (after deconv_init or deconv_reset); the estimate and the search state are restored
  * afterwards.  choice_host (5 ints, host, or NULL) receives the five choices for image 0.
- * Synchronises `stream`.
+ * Synchronises `stream`.  Single-image contexts only: a multi-image context returns
+ * GFD_ERR_UNIMPLEMENTED (its trials, graphs of parallel branches re-instantiated in a row, have
+ * ended in a host fault inside the HIP runtime); give it launch shapes with deconv_set_tuning.
  */
 gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stream);
 

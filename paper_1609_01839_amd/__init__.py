@@ -198,7 +198,8 @@ class GFDeconv:
     TUNING_KEYS = ("gf_strip_rows", "row_pairs_fwd", "rows_inv", "rows_lds", "radix")
 
     def autotune(self, iters: int = 4) -> dict:
-        """Time candidate launch shapes and keep the fastest (needs no iterations run yet)."""
+        """Time candidate launch shapes and keep the fastest (needs no iterations run yet;
+        single-image contexts only: a batch raises GFDError, give it shapes with set_tuning)."""
         ch = (_i * 5)()
         _check(load_library().deconv_autotune(self.handle, int(iters), ch, _stream(self.device)))
         return dict(zip(self.TUNING_KEYS, list(ch)))

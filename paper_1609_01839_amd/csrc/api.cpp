@@ -1302,6 +1302,12 @@ gfd_status deconv_autotune(gfd_ctx *ctx, int iters, int *choice_host, void *stre
   if (!live(ctx)) return fail(GFD_ERR_STATE, "invalid or destroyed context");
   if (ctx->iters != 0) return fail(GFD_ERR_STATE, "deconv_autotune needs a context with no iterations run");
   if (iters < 0 || iters > 64) return fail(GFD_ERR_ARG, "iters must be in [0, 64] (0: default 4)");
+  // Multi-image contexts are not tuned: their trials (a graph of parallel branches captured,
+  // instantiated, replayed and destroyed a dozen times in a row) twice ended in a host
+  // segmentation fault inside the HIP runtime whose cause has not been found; set their launch
+  // shapes with deconv_set_tuning.
+  if (ctx->count > 1)
+    return fail(GFD_ERR_UNIMPLEMENTED, "deconv_autotune tunes single-image contexts only (use deconv_set_tuning)");
   const int n = iters == 0 ? 4 : std::max(iters, 2);
   hipStream_t s = (hipStream_t)stream;
   gfd_ctx *c = ctx;
