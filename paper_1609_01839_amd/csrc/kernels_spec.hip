@@ -445,11 +445,21 @@ __global__ void __launch_bounds__(1024) k_row_inv_g(const Img *__restrict__ D, c
 // a barrier, which makes the tables visible before they are read.
 template <int L>
 __device__ __forceinline__ void load_tw_split(cf *tab, const cf *tw) {
-  // (blocks of short rows can have fewer than 128 threads; entries 64 j with j >= L / 64 are
-  // never used: they are read at 64 j mod L, inside the table)
-  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
-    const int j = i & 63;
-    tab[i] = E(G(tw), (uint32_t)(i < 64 ? j : (64 * j) & (L - 1)));
+  // (entries 64 j with j >= L / 64 are never used: they are read at 64 j mod L, inside the table)
+  // One load per thread, written at once, wherever the block has 128 threads (always at
+  // L >= 2048, T = L / 16 threads per sequence): a loop here let the compiler defer the write
+  // behind the pass's own loads (7-10 us more per pass at 4096, 3 % of the batch).
+  if (L >= 2048 || blockDim.x >= 128) {
+    if (threadIdx.x < 128) {
+      const int j = threadIdx.x & 63;
+      tab[threadIdx.x] = E(G(tw), (uint32_t)(threadIdx.x < 64 ? j : (64 * j) & (L - 1)));
+    }
+  } else {
+    // blocks of short rows can have fewer than 128 threads
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+      const int j = i & 63;
+      tab[i] = E(G(tw), (uint32_t)(i < 64 ? j : (64 * j) & (L - 1)));
+    }
   }
 }
 
