@@ -71,10 +71,12 @@ def backward_bytes(P: int, Q: int, K: int, c: int) -> int:
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources and the build script (its compiler flags)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1609_01839_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_1609_01839_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 

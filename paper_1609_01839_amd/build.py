@@ -22,9 +22,16 @@ FLAGS = [
 ]
 
 
+# Per-source flags: the guided filter's streaming kernels are scheduled for instruction-level
+# parallelism (the filter issues VALU in about half of its cycles; measured 83.6 -> 82.2 us at
+# 4096^2, w = 17, and 0.882 -> 0.875 ms per step for the mixed-size batch; the reverse mode's box
+# passes showed no change and keep the default).
+SOURCE_FLAGS = {"kernels_gf.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     err = "\n".join(l for l in r.stderr.splitlines() if noise not in l)
