@@ -165,8 +165,10 @@ def lam_err(g: float, o: float) -> float:
 # ----------------------------------------------------------------------------- GPU legs
 
 # launch shapes of the batch leg: strip rows, forward row pairs, inverse rows, mixed-radix rows,
-# mixed-radix schedule
-BATCH_TUNING = (32, 1, 2, 2, 8)
+# mixed-radix schedule (from a sweep of fixed shapes, one process each: 64-row strips and row
+# pairs took 0.867 ms per step against 0.878 for 32 rows and single pairs, 0.870 for 64 rows with
+# single pairs, 0.88-0.90 for 40, 48, 80, 96 and 128 rows)
+BATCH_TUNING = (64, 2, 2, 2, 8)
 
 
 def batch_leg(steps: int, warmup: int, n_images: int = 64, ref=None) -> dict:
