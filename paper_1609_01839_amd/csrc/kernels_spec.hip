@@ -59,38 +59,54 @@ __device__ __forceinline__ void store_partial(GFD_AS1 float *part, int npart, in
 }
 
 // Compensated sums of the NV values of the partials of `nparts` blocks.  Wave w takes values
-// w, w + nwaves, ...: each lane accumulates the partials lane, lane + 64, ... in order (loaded
-// U at a time, so that up to 64 U partials cost one memory round trip), then the
-// wave combines its lanes by shuffles, so no lane carries more than one value through the
-// shuffle tree (the tree is the expensive part).  Deterministic order; thread 0 receives all NV
-// sums.  `scratch` must hold 2 NV floats.  U: partials per lane loaded together (2 U registers).
+// w, w + nwaves, ... in pairs (w and w + nwaves, then w + 2 nwaves and w + 3 nwaves, ...): each
+// lane accumulates the partials lane, lane + 64, ... of both values in order (loaded U at a time
+// for both values before either is added, so that a pair of values with up to 64 U partials
+// costs one memory round trip), then the wave combines its lanes by shuffles.  A wave whose pair
+// has no second value loads the first one twice and keeps one result.  Deterministic order (each
+// value's additions are the same as with one value per pass); thread 0 receives all NV sums.
+// `scratch` must hold 2 NV floats.  U: partials per lane and value loaded together (4 U
+// registers).
 template <int NV, int U = 32>
 __device__ __forceinline__ void reduce_partials(const GFD_AS1 float *__restrict__ part, int npart, int nparts, float (&hi)[NV],
                                 float (&lo)[NV], float *scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = max((int)(blockDim.x >> 6), 1);
-  for (int v = wid; v < NV; v += nw) {
+  for (int v = wid; v < NV; v += 2 * nw) {
+    const bool two = v + nw < NV;  // uniform in the wave
+    const int v2 = two ? v + nw : v;
     const GFD_AS1 float *ph = part + (size_t)(2 * v) * npart, *pl = part + (size_t)(2 * v + 1) * npart;
-    float h = 0.0f, l = 0.0f;
-    // U partials per lane per pass, loaded together before they are added in order
+    const GFD_AS1 float *qh = part + (size_t)(2 * v2) * npart, *ql = part + (size_t)(2 * v2 + 1) * npart;
+    float h = 0.0f, l = 0.0f, h2 = 0.0f, l2 = 0.0f;
     for (int p0 = lane; p0 < nparts; p0 += 64 * U) {
-      float xh[U], xl[U];
+      float xh[U], xl[U], yh[U], yl[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int p = p0 + 64 * u;
         xh[u] = p < nparts ? ph[p] : 0.0f;
         xl[u] = p < nparts ? pl[p] : 0.0f;
+        yh[u] = p < nparts ? qh[p] : 0.0f;
+        yl[u] = p < nparts ? ql[p] : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) df_add(h, l, xh[u], xl[u]);
+      for (int u = 0; u < U; ++u) {
+        df_add(h, l, xh[u], xl[u]);
+        df_add(h2, l2, yh[u], yl[u]);
+      }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       const float oh = __shfl_down(h, off, 64), ol = __shfl_down(l, off, 64);
+      const float oh2 = __shfl_down(h2, off, 64), ol2 = __shfl_down(l2, off, 64);
       df_add(h, l, oh, ol);
+      df_add(h2, l2, oh2, ol2);
     }
     if (lane == 0) {
       scratch[2 * v] = h;
       scratch[2 * v + 1] = l;
+      if (two) {
+        scratch[2 * v2] = h2;
+        scratch[2 * v2 + 1] = l2;
+      }
     }
   }
   __syncthreads();
