@@ -40,7 +40,7 @@ ALG_BYTES = {
 }
 KERNEL_SYMBOL = {
     "row_fwd": "k_row_fwd_r16<4096>", "col_fwd_resid": "k_col_fwd_r16<true, 4096>", "lambda_sweeps": "k_lam_rounds",
-    "col_inv_solve": "k_col_inv_r16<4096>", "row_inv": "k_row_inv_r16<4096>", "guided_filter": "k_gf_g<8, false>",
+    "col_inv_solve": "k_col_inv_r16<4096>", "row_inv": "k_row_inv_r16<4096>", "guided_filter": "k_gf_g<8, false, false>",
 }
 PARITY_ITERS = 3   # iterations of the single frame compared with the oracle (the CPU sample)
 

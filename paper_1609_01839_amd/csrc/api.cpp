@@ -76,6 +76,9 @@ struct gfd_ctx {
 struct Bwd {
   ImgSet bwd, grad, gout;
   Plan fwd_a, fwd_b, gf, box[3], grad_fft, spec, col, gout_inv, inf;
+  // a segment's replays filter with gf_save, which also leaves the first box pass's results of
+  // the strip-kernel images; that pass (box[0]) then covers the other images only
+  Plan gf_save;
   ItemRange one{0, 0};
   LamState *st = nullptr;
   AdjState *ad = nullptr;
@@ -837,7 +840,14 @@ static hipError_t build_bwd(gfd_ctx *c) {
   plan_col_inv(b->fwd_b, b->bwd, all);
   plan_row_inv(b->fwd_b, b->bwd, all);
   plan_guided_filter(b->gf, b->bwd, all);
-  for (int st = 0; st < 3; ++st) plan_box_stage(b->box[st], b->bwd, all, st + 1);
+  plan_guided_filter(b->gf_save, b->bwd, all, true);
+  {
+    std::vector<int> rest;  // images whose filter runs as separable passes
+    for (int i = 0; i < n; ++i)
+      if (gf_wide(b->bwd.imgs[i].w)) rest.push_back(i);
+    if (!rest.empty()) plan_box_stage(b->box[0], b->bwd, rest, 1);
+  }
+  for (int st = 1; st < 3; ++st) plan_box_stage(b->box[st], b->bwd, all, st + 1);
   plan_adj_spec(b->spec, b->bwd, all);
   plan_adj_col(b->col, b->bwd, all);
   plan_adj_inf(b->inf, b->bwd, all);
@@ -871,6 +881,8 @@ static hipError_t bwd_slots(gfd_ctx *c, int nck, int seg) {
       if (e == hipSuccess) e = balloc(b, &sl.uP, P);
       if (e == hipSuccess) e = balloc(b, &sl.S1, nb);
       if (e == hipSuccess) e = balloc(b, &sl.means, 2);
+      for (float **q : {&sl.ga, &sl.gmu, &sl.gpb, &sl.gve})
+        if (e == hipSuccess) e = balloc(b, q, P);
       b->seg[i].push_back(sl);
     }
   }
@@ -919,7 +931,8 @@ static hipError_t replay(Bwd *b, int k, bool filter, hipStream_t s) {
 
 // Adjoint of iteration k, whose forward quantities (u_I, u_p, U_E, centring constants) are in
 // place; gu holds the gradient with respect to its output on entry and with respect to its
-// pre-estimate on exit.
+// pre-estimate on exit.  The replay of iteration k ran the saving filter, which left the first
+// box pass's results of the strip-kernel images; that pass runs for the other images only.
 static hipError_t adjoint_step(Bwd *b, int k, hipStream_t s) {
   hipError_t e = launch_lam_replay(b->bwd, b->one, k, s);
   for (int st = 0; st < 3 && e == hipSuccess; ++st) e = b->box[st].enqueue(s);
@@ -1514,7 +1527,10 @@ gfd_status deconv_backward(gfd_ctx *ctx, const float *grad_u, float *grad_eps_de
       HIPCHK(launch_bwd_bind(b->bwd, b->seg_dev, b->nseg, k - a, 0, s));
       HIPCHK(replay(b, k0 + k, false, s));
       HIPCHK(launch_bwd_bind(b->bwd, b->seg_dev, b->nseg, k - a, +1, s));
-      if (k + 1 < z) HIPCHK(b->gf.enqueue(s));
+      // the filter also after the segment's last iteration, whose output (in uR) nothing reads:
+      // every iteration's first box pass results then come from the same kernel, so gradients
+      // do not depend on where the segments end
+      HIPCHK(b->gf_save.enqueue(s));
     }
     for (int k = z - 1; k >= a; --k) {
       HIPCHK(launch_bwd_bind(b->bwd, b->seg_dev, b->nseg, k - a, -1, s));

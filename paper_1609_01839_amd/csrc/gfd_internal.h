@@ -228,7 +228,10 @@ void plan_col_fwd(Plan &p, ImgSet &set, const std::vector<int> &sel, bool resid)
 void plan_lambda(Plan &p, ImgSet &set, const std::vector<int> &sel, int rounds, bool advance);
 void plan_col_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
 void plan_row_inv(Plan &p, ImgSet &set, const std::vector<int> &sel);
-void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel);
+// save: the reverse mode's replays, whose filter also writes the first stage's results (a, the
+// means of I and p, var + eps) to the images' ga, gmu, gpb and gve planes (strip kernels only;
+// windows that run as separable passes write none)
+void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool save = false);
 hipError_t finalize_items(ImgSet &set);
 void sort_by_size(const ImgSet &set, std::vector<int> &imgs);
 void gf_geometry(Img &d, int ty = 0);
@@ -250,6 +253,7 @@ hipError_t launch_lam_replay(ImgSet &set, ItemRange one, int k, hipStream_t s);
 struct BwdSlot {
   float *uI, *uP, *means;
   cf *S1;
+  float *ga, *gmu, *gpb, *gve;  // the first box pass's results for this iteration
 };
 hipError_t launch_bwd_bind(ImgSet &set, const BwdSlot *slots, int nslot, int j, int dir, hipStream_t s);
 hipError_t launch_adj_fin(ImgSet &set, ItemRange one, int k, hipStream_t s);

@@ -344,8 +344,9 @@ __global__ void k_lam_replay(const Img *__restrict__ D, const Item *__restrict__
 }
 
 // Points the replay descriptors of every image at segment position j, so that the replay of an
-// iteration writes u_I, u_p and U_E there and its adjoint reads them there (no copies).  dir > 0
-// also saves the centring constants the replay has just computed, dir < 0 restores them.
+// iteration writes u_I, u_p and U_E there (and its filter the first box pass's results, where it
+// runs) and its adjoint reads them there (no copies).  dir > 0 also saves the centring constants
+// the replay has just computed, dir < 0 restores them.
 __global__ void k_bwd_bind(Img *__restrict__ D, int count, const BwdSlot *__restrict__ slots, int nslot, int j,
                            int dir) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -355,6 +356,10 @@ __global__ void k_bwd_bind(Img *__restrict__ D, int count, const BwdSlot *__rest
   d.uI = sl.uI;
   d.uP = sl.uP;
   d.S1 = sl.S1;
+  d.ga = sl.ga;
+  d.gmu = sl.gmu;
+  d.gpb = sl.gpb;
+  d.gve = sl.gve;
   if (dir > 0) {
     sl.means[0] = d.st->meanI;
     sl.means[1] = d.st->meanP;

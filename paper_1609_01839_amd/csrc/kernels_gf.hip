@@ -50,13 +50,26 @@ struct GfLds {
   float hbuf[gf_rows<R>() * 4 * kHsOut];
 };
 
+// Planes that keep the first stage's results for the reverse mode (Eqs.(3)-(4)): a, the window
+// means of I and p, and var + eps, per pixel, in the same mean-centred variables.
+struct GfSave {
+  float *a, *mu, *pb, *ve;
+};
+
 // One strip (logical block lb of an nbx x nby grid of strips, nby strips per column).  FULL:
 // the strip uses every thread (TX = kGfThreads - 4R, images at least that wide), so no thread
-// needs the selects that zero the sums of columns past a narrow strip.
-template <int R, bool CLIP, bool FULL>
+// needs the selects that zero the sums of columns past a narrow strip.  SAVE: the first stage's
+// results of the windows centred on the strip's output pixels also go to `sv` (every pixel of
+// the image is an output pixel of exactly one strip).
+template <int R, bool CLIP, bool FULL, bool SAVE>
 __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, const GFD_AS1 float *__restrict__ uP,
                                          GFD_AS1 float *__restrict__ u, int M, int N, float eps, int TX, int TY, int nby,
-                                         int lb, float cI, float cP, GfLds<R> &sh) {
+                                         int lb, float cI, float cP, const GfSave &sv, GfLds<R> &sh) {
+  // No contraction of separate multiplies and additions into fused ones: every fused operation
+  // is written out, so the arithmetic is the same in every instantiation (with and without SAVE,
+  // whatever the compiler's choices), and the reverse mode's replays reproduce the forward
+  // filter bit for bit.
+#pragma clang fp contract(off)
   constexpr int W = 2 * R + 1;
   constexpr int RB = gf_rows<R>();
   constexpr int VP = hs_pitch<R>();  // padded row of vertical sums
@@ -196,9 +209,21 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
           const float pb = hb[kHsOut] * nrm;
           const float var = fmaxf(__fmaf_rn(-mu, mu, hb[2 * kHsOut] * nrm), 0.0f);
           const float cov = __fmaf_rn(-mu, pb, hb[3 * kHsOut] * nrm);
-          float a = cov * __builtin_amdgcn_rcpf(var + eps);  // hardware reciprocal, 1 ulp
+          const float ve = var + eps;
+          const float rv = __builtin_amdgcn_rcpf(ve);  // hardware reciprocal, 1 ulp
+          float a = cov * rv;
           float b = __fmaf_rn(-a, mu, pb);
           if (CLIP && !cin) a = b = 0.0f;  // windows centred outside the image do not exist
+          if (SAVE) {  // window centred at image row yrow(it - R), column x0 - 2R + j
+            const int yc = yrow(it - R), xc = x0 - 2 * R + j;
+            if (j >= 2 * R && j < TX + 2 * R && xc < N && yc >= y0 && yc < y0 + TY && yc < M) {
+              const uint32_t g = (uint32_t)yc * (uint32_t)N + (uint32_t)xc;
+              E(G(sv.a), g) = a;
+              E(G(sv.mu), g) = mu;
+              E(G(sv.pb), g) = pb;
+              E(G(sv.ve), g) = ve;
+            }
+          }
           // slots of it2 and of it2 - W (zero while it2 < W)
           const int slot = (RB * r + q - (W - 1) + RS) % RS, slo = (RB * r + q - (W - 1) - W + 2 * RS) % RS;
           const float ao = rA[slo], bo = rB[slo];
@@ -212,7 +237,8 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
               sB = __fadd_rn(sB, rB[k]);
             }
           } else {
-            slide(sA, a, ao);
+            // a - ao as one fused operation, cov rv - ao
+            sA = __fadd_rn(sA, (CLIP && !cin) ? -ao : __fmaf_rn(cov, rv, -ao));
             slide(sB, b, bo);
           }
           // Columns without coefficients still enter the first window of a sliding run before
@@ -249,7 +275,9 @@ __device__ __forceinline__ void gf_strip(const GFD_AS1 float *__restrict__ uI, c
 }
 
 // Inside the iteration: one launch filters every image of the group (images of one radius).
-template <int R, bool CLIP>
+// SAVE (the reverse mode's replays): the first stage's results go to the image's ga, gmu, gpb
+// and gve planes as well.
+template <int R, bool CLIP, bool SAVE = false>
 __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu(gf_waves<R>()))) k_gf_g(const Img *__restrict__ D, const Item *__restrict__ W,
                                                      int nitems) {
   __shared__ __align__(16) GfLds<R> sh;
@@ -258,10 +286,13 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
     if (wi.blk < 0) continue;
     const Img &d = D[wi.img];
     const float cI = d.st->meanI, cP = d.st->meanP;
+    const GfSave sv = {d.ga, d.gmu, d.gpb, d.gve};
     if (d.gfTX + 4 * R == kGfThreads)
-      gf_strip<R, CLIP, true>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
+      gf_strip<R, CLIP, true, SAVE>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI,
+                                    cP, sv, sh);
     else
-      gf_strip<R, CLIP, false>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI, cP, sh);
+      gf_strip<R, CLIP, false, SAVE>(G(d.uI), G(d.uP), G(d.uE), d.L.M, d.L.N, d.eps, d.gfTX, d.gfTY, d.gfNBY, wi.blk, cI,
+                                     cP, sv, sh);
     __syncthreads();
   }
 }
@@ -273,8 +304,10 @@ __global__ void __launch_bounds__(kGfThreads) __attribute__((amdgpu_waves_per_eu
                                                          int TY, int nby) {
   __shared__ __align__(16) GfLds<R> sh;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  if (TX + 4 * R == kGfThreads) gf_strip<R, CLIP, true>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
-  else gf_strip<R, CLIP, false>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], sh);
+  const GfSave none = {};
+  if (TX + 4 * R == kGfThreads)
+    gf_strip<R, CLIP, true, false>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], none, sh);
+  else gf_strip<R, CLIP, false, false>(G(uI), G(uP), G(u), M, N, eps, TX, TY, nby, lb, uI[0], uP[0], none, sh);
 }
 
 bool guided_filter_supported(int w) { return w >= 1 && (w % 2) == 1; }
@@ -415,7 +448,7 @@ int gf_fill_height(const Img &d) {
   return 0;
 }
 
-void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
+void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel, bool save) {
   std::map<int, std::vector<int>> byR;  // key 2 r + clip
   for (int i : sel) byR[(set.imgs[i].w - 1) + (set.imgs[i].clip ? 1 : 0)].push_back(i);
   for (auto &kv : byR) {
@@ -435,8 +468,11 @@ void plan_guided_filter(Plan &p, ImgSet &set, const std::vector<int> &sel) {
     const int r = kv.first / 2;
     const bool clip = (kv.first & 1) != 0;
     const ItemRange range{off, n};
-#define GFD_PLAN_GF(RR) \
-  p.steps.push_back(make_launch(&set, clip ? k_gf_g<RR, true> : k_gf_g<RR, false>, range, kGfThreads, 0))
+#define GFD_PLAN_GF(RR)                                                                              \
+  p.steps.push_back(make_launch(&set,                                                                \
+                                save ? (clip ? k_gf_g<RR, true, true> : k_gf_g<RR, false, true>)     \
+                                     : (clip ? k_gf_g<RR, true, false> : k_gf_g<RR, false, false>),  \
+                                range, kGfThreads, 0))
     GFD_R_SWITCH(r, GFD_PLAN_GF)
 #undef GFD_PLAN_GF
   }
