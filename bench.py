@@ -55,18 +55,20 @@ def backward_bytes(P: int, Q: int, K: int, c: int) -> int:
     """Algorithmic bytes of deconv_backward over K iterations with checkpoints every c, following
     its schedule: a replay of the forward from the starting estimate keeping every c-th
     pre-estimate, then per segment (last first) a replay of each iteration that writes u_I, u_p
-    and U_E straight into that iteration's slot, and the adjoint of each iteration in reverse,
-    reading them there."""
+    and U_E straight into that iteration's slot, with the filter that also writes the first box
+    pass's results there, and the adjoint of each iteration in reverse, reading them there
+    (windows that the strip filter holds, as in the benchmark's workload)."""
     replay = 12 * P + 76 * Q          # row_fwd 4P+8Q, column pass 16Q, column inverse 36Q, row inverse 8P+16Q
     gf = 12 * P                       # guided filter
+    gf_save = 28 * P                  # the same, also writing a, the means of I and p, var + eps
     copy = 8 * P                      # an estimate copied to or from a checkpoint
-    adjoint = 120 * P + 168 * Q       # box passes 24P+44P+36P, transforms of g_I, g_p 8P+48Q,
+    adjoint = 96 * P + 168 * Q        # box passes 44P+36P, transforms of g_I, g_p 8P+48Q,
     #                                   spectral adjoint 52Q, adjoint column pass 52Q, row inverse 8P+16Q
     nck = -(-K // c)
     total = copy + (nck - 1) * c * (replay + gf) + nck * copy
     for j in range(nck):
         n = min(c, K - j * c)
-        total += (copy if j != nck - 1 else 0) + n * replay + (n - 1) * gf + n * adjoint
+        total += (copy if j != nck - 1 else 0) + n * (replay + gf_save) + n * adjoint
     return total
 
 
