@@ -11,7 +11,9 @@
 //   g_I = g_u B(a) + B(g_mu) + p B(g_c) + 2 I B(g_v),  g_p = B(g_pbar) + I B(g_c).
 // Three streaming box passes compute it (k_box_stage with three epilogues), in the same
 // mean-centred variables as the forward filter (the filter commutes with constant shifts, so
-// the gradient is the same).  With windows clipped to the image, B = D^-1 S (S the clipped
+// the gradient is the same); the first one's results (a, mu, pbar, v + eps) come from the
+// replayed iteration's own filter wherever the strip kernel runs it, so that pass runs only for
+// windows that take the separable passes.  With windows clipped to the image, B = D^-1 S (S the clipped
 // window sum, symmetric; D the counts) and the box sums that carry gradients backwards are
 // B^T = S D^-1: their fields are divided by the count of the input pixel's window before they
 // are summed, and their sums are used as they are.
