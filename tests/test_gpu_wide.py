@@ -194,3 +194,30 @@ def test_wide_static_entry_point_equals_context():
     u_st, lam_st = gfd.deconvolve_static(to_gpu(c.y), to_gpu(c.h), c.sigma2, c.w, c.eps, iters)
     assert np.array_equal(u_st.cpu().numpy(), u_ctx.cpu().numpy())
     assert np.array_equal(lam_st.cpu().numpy(), lam_ctx.cpu().numpy())
+
+
+def test_wide_batch_backward_equals_single_contexts():
+    """Reverse mode of a batch that mixes strip-kernel windows (whose replays' filter also leaves
+    the first box pass's results) with separable-pass windows (for which that pass runs), each
+    periodic and clipped: every image's gradients equal its own context's bit for bit."""
+    cases = []
+    for b, (M, N, w, clip) in enumerate([(64, 64, 5, False), (96, 80, 21, False), (72, 72, 7, True),
+                                         (64, 80, 19, True)]):
+        h = synth.psf_gaussian(1.4, 7)
+        u, y, s2 = synth.nonperiodic_case(M, N, h, 30.0, seed=80 + b)
+        cases.append((dict(y=to_gpu(y), h=to_gpu(h), sigma2=s2, w=w, eps=650.25, clip=clip, pad=False), u))
+    iters = 3
+    singles = []
+    for c, u in cases:
+        with gfd.GFDeconv(c["y"], c["h"], c["sigma2"], c["w"], c["eps"], clip=c["clip"]) as g:
+            uu, _ = g.iterate(iters)
+            ge, gs = g.backward(2.0 * (uu - to_gpu(u)) / uu.numel(), 2)
+            singles.append((ge.cpu().numpy(), gs.cpu().numpy()))
+    with gfd.GFDeconvBatch([c for c, _ in cases]) as gb:
+        us, _ = gb.iterate(iters)
+        gu = torch.cat([(2.0 * (x - to_gpu(u)) / x.numel()).reshape(-1) for x, (_, u) in zip(us, cases)])
+        ge, gs = gb.backward(gu, 2)
+        ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
+    for b, (se, ss) in enumerate(singles):
+        print(f"image {b}: g_eps {ge[b]:.6e} / {se[0]:.6e}", flush=True)
+        assert ge[b] == se[0] and np.array_equal(gs[b], ss[0]), b
