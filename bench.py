@@ -310,7 +310,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the deconvolution of one frame runs on a single device "
-              "(multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding over several GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
